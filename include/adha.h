@@ -1,0 +1,356 @@
+/*
+ * adha.h -- C-ABI of libadha: layout remaps, layout-generic section kernels
+ * and two-level layout selection for record arrays on MI355X (gfx950).
+ *
+ * Problem statement followed (ADHA, Majeti, Meel, Barik, Sarkar, PACT 2014):
+ *   section 2: a program is a sequence of "sections" (data-parallel loops);
+ *   the affinity graph's nodes are the fields the sections access; a
+ *   per-section layout is obtained by greedy clustering of that graph; a
+ *   program layout is a shortest path over the sections with "combine"
+ *   (keep one layout) and "remap" (change layout) edges, weighted from a
+ *   profile of section times.
+ *   section 1 and Tables 2-3: layouts are AoS, SoA and structures of
+ *   clustered fields; here each group of fields is either interleaved
+ *   (tile 1) or stored in tiles of T records (AoSoA).
+ *
+ * Conventions for every call:
+ *   - Every call returns adha_status.  Out-parameters are written only on
+ *     success.  Nothing is thrown across this boundary and nothing aborts.
+ *     adha_last_error() returns a message for the last failing call made
+ *     on the calling thread.
+ *   - All arguments are validated on the host before any device work.
+ *   - Device buffers are owned by the caller, passed as plain device
+ *     pointers with their capacity in bytes; they must be 256-byte aligned.
+ *     The library never frees them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default
+ *     stream).  Device work is enqueued on it and is asynchronous; faults
+ *     and gather-index errors surface from adha_ctx_check().
+ *   - Handles from *_create are released by the matching *_destroy.
+ *     Layouts, sections and programs copy what they need from the struct,
+ *     so a struct may be destroyed once they exist.
+ *   - A context is not thread-safe; separate contexts are.
+ *
+ * Layout definition (byte address of field f of record r):
+ *   groups are ordered by their smallest field id; fields inside a group are
+ *   packed in ascending id (p_f = byte offset inside the group's record,
+ *   S_g = group record bytes, e_f = element bytes);
+ *   addr(r, f) = base_g + (r / T)*T*S_g + p_f*T + (r % T)*e_f;
+ *   base_0 = 0, base_{g+1} = roundup(base_g + roundup(N, T_g)*S_g, 256);
+ *   size = roundup(end of last group, 256); a one-field group has T = 1;
+ *   bytes owned by no (r, f) are padding and a remap writes them as zero.
+ */
+#ifndef ADHA_H
+#define ADHA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t adha_status;
+#define ADHA_OK 0
+#define ADHA_WARN_FALLBACK 1     /* success, but a fallback was taken */
+#define ADHA_ERR_INVALID (-1)    /* bad argument; nothing was launched */
+#define ADHA_ERR_OOM (-2)        /* device or host allocation failed */
+#define ADHA_ERR_DEVICE (-3)     /* HIP error (launch, fault, no device) */
+#define ADHA_ERR_STATE (-4)      /* object not in a usable state */
+#define ADHA_ERR_UNSUPPORTED (-5)/* valid request this library cannot do */
+#define ADHA_ERR_IO (-6)         /* file missing, unreadable or corrupt */
+
+typedef enum { ADHA_F32 = 0, ADHA_F64 = 1, ADHA_I32 = 2, ADHA_RAW = 3 } adha_dtype;
+
+/* Section bodies (the paper gives none; these are the workloads' bodies).
+ * Terms are read first: direct sections (degree 0) read the read fields of
+ * record i in ascending id; gather sections read, for j = 0..d-1, the read
+ * fields in ascending id of record idx[i*d + j].  Then each write field w_k
+ * (ascending id, k < 2) of record i is written:
+ *   GEN, fp w:  acc = 0, per term v = convert(t) to w's type (int -> fp and
+ *               f64 -> f32 round to nearest even), k = 0: acc = acc + v,
+ *               k = 1: acc = acc*0.5 + v, every operation rounded in w's type;
+ *   GEN, i32 w: acc = 0, per term u = its 32-bit pattern (f64: low ^ high),
+ *               k = 0: acc = acc + u, k = 1: acc = (acc ^ u) * 16777619 (mod 2^32);
+ *   MULADD3:    w = a*b + c (two roundings), read set {a < b < c}, direct only;
+ *   SUB2:       w = a - b, read set {a < b}, direct only;
+ *   SUM:        w = ((t0 + t1) + ...) left to right, direct only.
+ * MULADD3, SUB2 and SUM need one fp write field. */
+typedef enum { ADHA_OP_GEN = 0, ADHA_OP_MULADD3 = 1, ADHA_OP_SUB2 = 2, ADHA_OP_SUM = 3 } adha_op;
+
+#define ADHA_MAX_FIELDS 64
+#define ADHA_MAX_READ 32
+#define ADHA_MAX_WRITE 2
+#define ADHA_MAX_DEGREE 32
+#define ADHA_MAX_TILE 256
+#define ADHA_MAX_SECTIONS 64
+
+typedef struct adha_ctx adha_ctx;
+typedef struct adha_struct adha_struct;
+typedef struct adha_layout adha_layout;
+typedef struct adha_section adha_section;
+typedef struct adha_program adha_program;
+typedef struct adha_plan adha_plan;
+
+/* ------------------------------------------------------------ errors */
+/* Static text for a status code. */
+const char *adha_status_string(adha_status st);
+/* Message of the last failing call on this thread ("" if none). */
+const char *adha_last_error(void);
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t adha_version(void);
+
+/* ------------------------------------------------------------ context */
+/* Opens `device` (must be a gfx950 GPU).  Owns caches of kernel descriptors
+ * and the cost model.  ERR_DEVICE if the device is missing or not gfx950. */
+adha_status adha_ctx_create(int32_t device, adha_ctx **out);
+adha_status adha_ctx_destroy(adha_ctx *ctx);
+/* Waits for `stream`, then reports: ERR_DEVICE on a HIP error, ERR_INVALID
+ * if a gather section met an index outside [0, N) since the last check
+ * (such terms are skipped), else OK.  Clears the gather-index flag. */
+adha_status adha_ctx_check(adha_ctx *ctx, void *stream);
+/* Number of compute units (used to size persistent launches). */
+adha_status adha_ctx_cu_count(const adha_ctx *ctx, int32_t *out);
+
+/* ------------------------------------------------------------ struct */
+/* A struct of n_records records (n_records >= 0; 0 makes every operation a
+ * no-op).  Fields are added in order and get ids 0, 1, ... */
+adha_status adha_struct_create(int64_t n_records, adha_struct **out);
+/* dtype F32 and I32 need elem_bytes 4, F64 needs 8, RAW any of 1, 2, 4, 8
+ * (RAW fields can be remapped but not used by sections).  At most 64 fields
+ * and 2048 record bytes. */
+adha_status adha_struct_add_field(adha_struct *s, adha_dtype dt, uint32_t elem_bytes,
+                                  int32_t *out_id);
+adha_status adha_struct_destroy(adha_struct *s);
+adha_status adha_struct_info(const adha_struct *s, int64_t *n_records, int32_t *n_fields,
+                             uint32_t *record_bytes);
+
+/* ------------------------------------------------------------ layouts */
+/* group_of_field[f] is f's group label; labels must be exactly
+ * 0..n_groups-1; tile_of_group[g] is a power of two in [1, 256]. */
+adha_status adha_layout_create(const adha_struct *s, uint32_t n_groups,
+                               const uint32_t *group_of_field, const uint32_t *tile_of_group,
+                               adha_layout **out);
+/* AoS: one interleaved group.  SoA: one group per field. */
+adha_status adha_layout_aos(const adha_struct *s, adha_layout **out);
+adha_status adha_layout_soa(const adha_struct *s, adha_layout **out);
+adha_status adha_layout_destroy(adha_layout *l);
+/* Bytes a buffer in this layout occupies. */
+adha_status adha_layout_nbytes(const adha_layout *l, uint64_t *out);
+/* Byte address of field f of record r (0 <= r < N). */
+adha_status adha_layout_addr(const adha_layout *l, int64_t r, int32_t f, uint64_t *out);
+/* Canonical form: group index of every field (groups ordered by smallest
+ * field id) and each group's tile.  Either array may be NULL; each needs
+ * room for n_fields entries. */
+adha_status adha_layout_groups(const adha_layout *l, uint32_t *n_groups,
+                               uint32_t *group_of_field, uint32_t *tile_of_group);
+/* *out = 1 when a and b have the same struct shape and address map. */
+adha_status adha_layout_equal(const adha_layout *a, const adha_layout *b, int32_t *out);
+
+/* ------------------------------------------------------------ remap */
+/* Remap (section 2, the remap edge; section 3, the remap between the
+ * Medical program's sections): writes into dst, laid out by dst_l, every
+ * field of every record of src, laid out by src_l, and zero into every
+ * padding byte.  Bit-exact byte copy.  Both layouts must describe the same
+ * struct shape; src and dst must not overlap; caps must cover each
+ * layout's size. */
+adha_status adha_remap(adha_ctx *ctx, const adha_layout *src_l, const void *src, uint64_t src_cap,
+                       const adha_layout *dst_l, void *dst, uint64_t dst_cap, void *stream);
+
+typedef struct {
+  const adha_layout *src_layout;
+  const void *src;
+  uint64_t src_cap;
+  const adha_layout *dst_layout;
+  void *dst;
+  uint64_t dst_cap;
+} adha_remap_item;
+
+/* flags for adha_remap_batched */
+#define ADHA_BATCH_GRAPH 1u     /* capture the launches once in a hipGraph, replay after */
+#define ADHA_BATCH_SEPARATE 2u  /* one adha_remap per item instead (for comparison) */
+
+/* Remaps many arrays (each item as adha_remap) with one persistent launch
+ * over a work list of record tiles, plus one launch for all ragged tails.
+ * With ADHA_BATCH_GRAPH the context caches an instantiated graph keyed by
+ * the item list and replays it when the same list comes again.  Items must
+ * not overlap each other. */
+adha_status adha_remap_batched(adha_ctx *ctx, uint32_t n, const adha_remap_item *items,
+                               uint32_t flags, void *stream);
+
+/* Tile shape used for a remap (records per tile, 16-byte slots per thread,
+ * LDS padding shift); 0 in any field = choose automatically. */
+typedef struct {
+  uint32_t tile_records;
+  uint32_t slots;
+  uint32_t pad_shift;
+  uint32_t wg_per_cu;
+} adha_tile_shape;
+/* Force a tile shape for subsequent remaps of this layout pair (tests and
+ * the autotuner).  Invalid shapes are rejected with ERR_INVALID. */
+adha_status adha_remap_set_shape(adha_ctx *ctx, const adha_layout *src_l, const adha_layout *dst_l,
+                                 const adha_tile_shape *shape);
+/* Tile shape the next remap of this pair would use. */
+adha_status adha_remap_get_shape(adha_ctx *ctx, const adha_layout *src_l, const adha_layout *dst_l,
+                                 adha_tile_shape *out);
+
+/* Host-only description of how a remap would run with its default tile
+ * shape on a device with cu_count compute units: no device is touched. */
+typedef struct {
+  adha_tile_shape shape;
+  uint64_t full_tiles;        /* record tiles moved by the main kernel */
+  uint64_t tail_bytes;        /* destination bytes written by the tail kernel */
+  uint64_t descriptor_bytes;  /* size of the launch's descriptor blob */
+  uint64_t grid;              /* workgroups of the main kernel */
+  uint32_t lds_bytes;         /* LDS per workgroup of the main kernel */
+} adha_remap_info;
+adha_status adha_remap_describe(const adha_layout *src_l, const adha_layout *dst_l, int32_t cu_count,
+                                adha_remap_info *out);
+
+/* ------------------------------------------------------------ sections */
+/* A section (section 2: one data-parallel loop) reading n_read fields and
+ * writing n_write fields, direct (degree 0) or gathering `degree` neighbours
+ * per record through an int32 index array [N][degree].  Gather sections
+ * must not write a field they read.  Ids are sorted internally. */
+adha_status adha_section_create(const adha_struct *s, adha_op op, uint32_t n_read,
+                                const int32_t *read, uint32_t n_write, const int32_t *write,
+                                uint32_t degree, adha_section **out);
+adha_status adha_section_destroy(adha_section *sec);
+/* Runs the section in place on buf laid out by l.  idx (device, int32,
+ * idx_count >= N*degree) is needed only for gather sections. */
+adha_status adha_section_run(adha_ctx *ctx, const adha_section *sec, const adha_layout *l,
+                             void *buf, uint64_t buf_cap, const int32_t *idx, uint64_t idx_count,
+                             void *stream);
+/* Algorithmic bytes one run moves: N*(read + write bytes) for direct
+ * sections, N*(4*d + d*read + write bytes) for gathers. */
+adha_status adha_section_bytes(const adha_section *sec, uint64_t *out);
+
+/* ------------------------------------------------------------ programs */
+adha_status adha_program_create(const adha_struct *s, uint32_t k, const adha_section *const *secs,
+                                adha_program **out);
+adha_status adha_program_destroy(adha_program *p);
+
+/* Affinity weights (section 2, the ODS pass) of sections first..last:
+ * w[a*F + b] for a != b.  Per loop iteration, fields touched at the same
+ * record co-occur once: a direct section adds 1 to every pair of R u W; a
+ * gather adds d to every pair of R and 1 to every pair of W. */
+adha_status adha_affinity(const adha_program *p, uint32_t first, uint32_t last, uint64_t *w);
+/* Greedy clustering (section 2, the ODS pass) of the merged sections
+ * first..last under cap_bytes: edges by decreasing weight, ties by
+ * (smaller id, larger id), join two clusters when their bytes fit.
+ * Writes a layout (clusters interleaved with the given tile, every other
+ * field on its own). */
+adha_status adha_ods(const adha_program *p, uint32_t first, uint32_t last, uint32_t cap_bytes,
+                     uint32_t tile, adha_layout **out);
+/* Shortest path (section 2, the PDL pass) through the layered DAG of k
+ * sections by C candidates: T[s*C + c] section costs, R[a*C + b] remap
+ * costs (diagonal ignored, taken as 0), R0[c] start costs (NULL = 0).
+ * Ties go to the smaller candidate index.  path[k] receives the choice. */
+adha_status adha_pdl_solve(uint32_t k, uint32_t C, const double *T, const double *R,
+                           const double *R0, uint32_t *path, double *cost);
+
+/* ------------------------------------------------------------ planning */
+typedef enum {
+  ADHA_COST_MEASURED = 0, /* time every (section, candidate) on the device */
+  ADHA_COST_ANALYTIC = 1, /* bytes moved / bandwidth, no device work */
+  ADHA_COST_LEARNED = 2   /* the trained cost model; falls back to MEASURED */
+} adha_cost_source;
+typedef enum { ADHA_CAT_AOS_SOA = 0, ADHA_CAT_FULL = 1 } adha_catalogue;
+typedef enum { ADHA_INIT_FREE = 0, ADHA_INIT_AOS = 1 } adha_init;
+
+typedef struct {
+  adha_cost_source cost;
+  adha_catalogue catalogue;
+  uint32_t cap_bytes; /* ODS structure capacity in bytes */
+  adha_init init;     /* FREE: data starts in the first chosen layout at no cost */
+  uint32_t reps;      /* measured costs: median of this many timed runs */
+} adha_plan_opts;
+
+adha_status adha_plan_opts_default(adha_plan_opts *o);
+/* Builds the candidate catalogue (AoS, SoA, AoS tiled by 64, and the ODS
+ * layout of every run of consecutive sections, interleaved and tiled),
+ * fills the cost tables from the chosen source and solves the shortest
+ * path.  Measured and learned costs use device scratch the call allocates
+ * and frees; gather sections are timed with idx (device, N*d entries) when
+ * given, else with uniformly random neighbours.  Measured remap costs are
+ * the median time of a whole-struct remap, the same for every pair of
+ * different layouts.  Returns WARN_FALLBACK when LEARNED had no model. */
+adha_status adha_plan_create(adha_ctx *ctx, const adha_program *p, const adha_plan_opts *o,
+                             const int32_t *idx, uint64_t idx_count, void *stream,
+                             adha_plan **out);
+/* A plan that keeps one layout for every section (the all-AoS / all-SoA
+ * baselines). */
+adha_status adha_plan_uniform(const adha_program *p, const adha_layout *l, adha_plan **out);
+adha_status adha_plan_destroy(adha_plan *pl);
+adha_status adha_plan_n_candidates(const adha_plan *pl, uint32_t *out);
+/* Candidate c's layout; the plan owns it. */
+adha_status adha_plan_candidate(const adha_plan *pl, uint32_t c, const adha_layout **out);
+adha_status adha_plan_choice(const adha_plan *pl, uint32_t s, uint32_t *candidate);
+/* Predicted program cost in microseconds under the plan's cost tables. */
+adha_status adha_plan_cost(const adha_plan *pl, double *us);
+/* Copies the cost tables (T: k*C, R: C*C, microseconds); either may be NULL. */
+adha_status adha_plan_tables(const adha_plan *pl, double *T, double *R);
+/* Seconds spent building the plan (catalogue, costs, path). */
+adha_status adha_plan_time(const adha_plan *pl, double *seconds);
+
+/* Runs the program under the plan.  The data starts in buf_a laid out by
+ * in_layout (under INIT_FREE pass the plan's first layout, or any layout,
+ * in which case a remap is made first).  Between sections with different
+ * layouts the data is remapped into the other buffer.  *out_layout (owned
+ * by the plan or equal to in_layout) and *out_in_b tell where it ends. */
+adha_status adha_run(adha_ctx *ctx, const adha_plan *pl, const adha_layout *in_layout,
+                     void *buf_a, void *buf_b, uint64_t buf_cap, const int32_t *idx,
+                     uint64_t idx_count, void *stream, const adha_layout **out_layout,
+                     int32_t *out_in_b);
+
+/* ------------------------------------------------------------ cost model */
+#define ADHA_N_FEATURES 16
+/* Feature vector of (section, layout) for the learned cost model. */
+adha_status adha_features(const adha_section *sec, const adha_layout *l, float *out16);
+
+/* Network: 16 -> 64 -> 64 -> 64 -> 1 (ReLU), fp32, predicting ln(time in
+ * microseconds).  Parameters are one fp32 array: W0[64][16], b0[64],
+ * W1[64][64], b1[64], W2[64][64], b2[64], W3[1][64], b3[1]. */
+#define ADHA_MLP_PARAMS (64 * 16 + 64 + 64 * 64 + 64 + 64 * 64 + 64 + 64 + 1)
+/* Device kernels of the network, on caller-owned device buffers:
+ * forward: x [B][16] -> y [B]; backward: gradient of mean((y - t)^2) into
+ * grad [ADHA_MLP_PARAMS] (overwritten) and, if loss != NULL, the loss
+ * (device float); adam: one Adam step (lr, b1, b2, eps, step count t >= 1)
+ * on params with moments m, v. */
+adha_status adha_mlp_forward(adha_ctx *ctx, const float *params, const float *x, uint32_t batch,
+                             float *y, void *stream);
+adha_status adha_mlp_backward(adha_ctx *ctx, const float *params, const float *x,
+                              const float *target, uint32_t batch, float *grad, float *loss,
+                              void *stream);
+adha_status adha_mlp_adam(adha_ctx *ctx, float *params, const float *grad, float *m, float *v,
+                          float lr, float b1, float b2, float eps, uint32_t t, void *stream);
+
+typedef struct {
+  uint32_t n_samples;  /* sections to generate and time */
+  uint32_t epochs;
+  uint32_t batch;
+  float lr;
+  uint64_t seed;
+  int32_t min_log2_n, max_log2_n; /* record counts of generated sections */
+  uint32_t reps;       /* timing: median of reps */
+} adha_train_opts;
+typedef struct {
+  double gen_seconds, train_seconds;
+  double train_loss, val_loss;
+  double val_mape;     /* mean absolute percentage error of predicted time */
+  uint32_t n_train, n_val;
+} adha_train_report;
+adha_status adha_train_opts_default(adha_train_opts *o);
+/* Generates sections and layouts, times them on the device, trains the
+ * network with the kernels above and keeps it in the context. */
+adha_status adha_costmodel_train(adha_ctx *ctx, const adha_train_opts *o, adha_train_report *rep);
+adha_status adha_costmodel_save(const adha_ctx *ctx, const char *path);
+/* ERR_IO on a missing, short or corrupt file (checksum); the context then
+ * keeps no model. */
+adha_status adha_costmodel_load(adha_ctx *ctx, const char *path);
+/* Predicted time (microseconds) of sec under l with the loaded model. */
+adha_status adha_costmodel_predict(adha_ctx *ctx, const adha_section *sec, const adha_layout *l,
+                                   double *us);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADHA_H */

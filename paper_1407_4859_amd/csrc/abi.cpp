@@ -1,0 +1,544 @@
+// The exported C-ABI: argument validation on the host, then dispatch.
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+#include "adha_impl.h"
+
+namespace adha {
+const char *last_error();
+
+Ctx::~Ctx() {
+  for (auto &g : graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  for (auto &kv : remap_cache)
+    if (kv.second.dev) (void)hipFree(kv.second.dev);
+  if (err_flag) (void)hipFree(err_flag);
+}
+
+static bool aligned(const void *p) { return ((uintptr_t)p & 255u) == 0; }
+
+static adha_status check_dev_buf(const char *what, const void *p, uint64_t cap, uint64_t need) {
+  if (need == 0) return ADHA_OK;
+  if (!p) return fail(ADHA_ERR_INVALID, "%s is NULL", what);
+  if (!aligned(p)) return fail(ADHA_ERR_INVALID, "%s is not 256-byte aligned", what);
+  if (cap < need)
+    return fail(ADHA_ERR_INVALID, "%s holds %llu bytes, the layout needs %llu", what,
+                (unsigned long long)cap, (unsigned long long)need);
+  return ADHA_OK;
+}
+
+static bool overlap(const void *a, uint64_t na, const void *b, uint64_t nb) {
+  if (!na || !nb) return false;
+  uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
+}
+
+static const size_t kCacheLimit = 4096;
+
+// Drops every cached descriptor blob and every graph that launches them.
+static adha_status flush_cache(Ctx *ctx) {
+  ADHA_HIP(hipDeviceSynchronize());
+  for (auto &ge : ctx->graphs) {
+    if (ge.exec) (void)hipGraphExecDestroy(ge.exec);
+    if (ge.graph) (void)hipGraphDestroy(ge.graph);
+  }
+  ctx->graphs.clear();
+  for (auto &kv : ctx->remap_cache) (void)hipFree(kv.second.dev);
+  ctx->remap_cache.clear();
+  return ADHA_OK;
+}
+
+// Cached remap launch for one (src layout, dst layout, shape); pointers are
+// passed at run time.
+static adha_status prepared_for(Ctx *ctx, const adha_layout *a, const adha_layout *b,
+                                const TileShape &sh, const RemapPrepared **out) {
+  std::vector<uint64_t> key{1, a->id, b->id, sh.R, sh.K, sh.shift, sh.wg_per_cu};
+  auto it = ctx->remap_cache.find(key);
+  if (it == ctx->remap_cache.end()) {
+    if (ctx->remap_cache.size() >= kCacheLimit) ADHA_TRY(flush_cache(ctx));
+    RemapPrepared p;
+    ADHA_TRY(remap_prepare(ctx, {&a->d}, {nullptr}, {&b->d}, {nullptr}, {sh}, &p));
+    it = ctx->remap_cache.emplace(key, p).first;
+  }
+  *out = &it->second;
+  return ADHA_OK;
+}
+
+static adha_status shape_for(Ctx *ctx, const adha_layout *a, const adha_layout *b, TileShape *sh) {
+  auto it = ctx->forced_shapes.find({a->id, b->id});
+  if (it != ctx->forced_shapes.end()) {
+    *sh = it->second;
+    return ADHA_OK;
+  }
+  return choose_shape(ctx, a->d, b->d, sh);
+}
+
+static adha_status validate_remap(const adha_layout *sl, const void *src, uint64_t src_cap,
+                                  const adha_layout *dl, const void *dst, uint64_t dst_cap) {
+  if (!sl || !dl) return fail(ADHA_ERR_INVALID, "layout is NULL");
+  if (!sl->d.shape.same(dl->d.shape))
+    return fail(ADHA_ERR_INVALID, "source and destination layouts describe different structs");
+  ADHA_TRY(check_dev_buf("src", src, src_cap, sl->d.nbytes));
+  ADHA_TRY(check_dev_buf("dst", dst, dst_cap, dl->d.nbytes));
+  if (overlap(src, sl->d.nbytes, dst, dl->d.nbytes))
+    return fail(ADHA_ERR_INVALID, "src and dst overlap (remaps are out of place)");
+  return ADHA_OK;
+}
+
+adha_status remap_one(Ctx *ctx, const adha_layout *sl, const void *src, const adha_layout *dl,
+                      void *dst, hipStream_t stream) {
+  if (sl->d.shape.n == 0 || dl->d.nbytes == 0) return ADHA_OK;
+  TileShape sh;
+  ADHA_TRY(shape_for(ctx, sl, dl, &sh));
+  const RemapPrepared *p = nullptr;
+  ADHA_TRY(prepared_for(ctx, sl, dl, sh, &p));
+  return remap_run(ctx, *p, src, dst, stream);
+}
+
+}  // namespace adha
+
+using namespace adha;
+
+extern "C" {
+
+const char *adha_status_string(adha_status st) {
+  switch (st) {
+    case ADHA_OK: return "ok";
+    case ADHA_WARN_FALLBACK: return "ok (fallback taken)";
+    case ADHA_ERR_INVALID: return "invalid argument";
+    case ADHA_ERR_OOM: return "out of memory";
+    case ADHA_ERR_DEVICE: return "device error";
+    case ADHA_ERR_STATE: return "invalid state";
+    case ADHA_ERR_UNSUPPORTED: return "unsupported";
+    case ADHA_ERR_IO: return "i/o error";
+    default: return "unknown status";
+  }
+}
+
+const char *adha_last_error(void) { return adha::last_error(); }
+
+int32_t adha_version(void) { return 10000; }
+
+// ------------------------------------------------------------------ context
+adha_status adha_ctx_create(int32_t device, adha_ctx **out) {
+  if (!out) return fail(ADHA_ERR_INVALID, "out is NULL");
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n == 0) return fail(ADHA_ERR_DEVICE, "no HIP device visible");
+  if (device < 0 || device >= n) return fail(ADHA_ERR_INVALID, "device %d not in [0, %d)", device, n);
+  hipDeviceProp_t prop;
+  ADHA_HIP(hipGetDeviceProperties(&prop, device));
+  std::string arch = prop.gcnArchName;
+  if (arch.compare(0, 6, "gfx950") != 0)
+    return fail(ADHA_ERR_DEVICE, "device %d is %s; this library is built for gfx950", device, arch.c_str());
+  auto *c = new (std::nothrow) adha_ctx;
+  if (!c) return fail(ADHA_ERR_OOM, "context allocation failed");
+  c->c.device = device;
+  c->c.arch = arch;
+  c->c.cu_count = prop.multiProcessorCount;
+  DeviceGuard g(device);
+  if (hipMalloc((void **)&c->c.err_flag, 256) != hipSuccess ||
+      hipMemset(c->c.err_flag, 0, 256) != hipSuccess) {
+    delete c;
+    return fail(ADHA_ERR_OOM, "context scratch allocation failed");
+  }
+  *out = c;
+  return ADHA_OK;
+}
+
+adha_status adha_ctx_destroy(adha_ctx *ctx) {
+  if (!ctx) return ADHA_OK;
+  DeviceGuard g(ctx->c.device);
+  (void)hipDeviceSynchronize();
+  delete ctx;
+  return ADHA_OK;
+}
+
+adha_status adha_ctx_check(adha_ctx *ctx, void *stream) {
+  if (!ctx) return fail(ADHA_ERR_INVALID, "ctx is NULL");
+  DeviceGuard g(ctx->c.device);
+  ADHA_HIP(hipStreamSynchronize((hipStream_t)stream));
+  uint32_t flag = 0;
+  ADHA_HIP(hipMemcpy(&flag, ctx->c.err_flag, 4, hipMemcpyDeviceToHost));
+  if (flag) {
+    ADHA_HIP(hipMemset(ctx->c.err_flag, 0, 4));
+    return fail(ADHA_ERR_INVALID, "a gather section met an index outside [0, N); those terms were skipped");
+  }
+  return ADHA_OK;
+}
+
+adha_status adha_ctx_cu_count(const adha_ctx *ctx, int32_t *out) {
+  if (!ctx || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
+  *out = ctx->c.cu_count;
+  return ADHA_OK;
+}
+
+// ------------------------------------------------------------------ struct
+adha_status adha_struct_create(int64_t n_records, adha_struct **out) {
+  if (!out) return fail(ADHA_ERR_INVALID, "out is NULL");
+  if (n_records < 0 || n_records > (int64_t(1) << 40))
+    return fail(ADHA_ERR_INVALID, "n_records %lld not in [0, 2^40]", (long long)n_records);
+  auto *s = new (std::nothrow) adha_struct;
+  if (!s) return fail(ADHA_ERR_OOM, "struct allocation failed");
+  s->shape.n = n_records;
+  *out = s;
+  return ADHA_OK;
+}
+
+adha_status adha_struct_add_field(adha_struct *s, adha_dtype dt, uint32_t elem_bytes, int32_t *out_id) {
+  if (!s) return fail(ADHA_ERR_INVALID, "struct is NULL");
+  switch (dt) {
+    case ADHA_F32:
+    case ADHA_I32:
+      if (elem_bytes != 4) return fail(ADHA_ERR_INVALID, "F32 / I32 fields have 4-byte elements");
+      break;
+    case ADHA_F64:
+      if (elem_bytes != 8) return fail(ADHA_ERR_INVALID, "F64 fields have 8-byte elements");
+      break;
+    case ADHA_RAW:
+      if (elem_bytes != 1 && elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8)
+        return fail(ADHA_ERR_INVALID, "RAW element size %u not in {1, 2, 4, 8}", elem_bytes);
+      break;
+    default:
+      return fail(ADHA_ERR_INVALID, "unknown dtype %d", (int)dt);
+  }
+  if (s->shape.nfields() >= ADHA_MAX_FIELDS) return fail(ADHA_ERR_INVALID, "at most %d fields", ADHA_MAX_FIELDS);
+  if (s->shape.record_bytes() + elem_bytes > 2048) return fail(ADHA_ERR_INVALID, "records are limited to 2048 bytes");
+  if ((uint64_t)(s->shape.record_bytes() + elem_bytes) * (uint64_t)s->shape.n > (uint64_t(1) << 46))
+    return fail(ADHA_ERR_INVALID, "N * record bytes exceeds 2^46");
+  s->shape.dtype.push_back((int32_t)dt);
+  s->shape.ebytes.push_back(elem_bytes);
+  if (out_id) *out_id = s->shape.nfields() - 1;
+  return ADHA_OK;
+}
+
+adha_status adha_struct_destroy(adha_struct *s) {
+  delete s;
+  return ADHA_OK;
+}
+
+adha_status adha_struct_info(const adha_struct *s, int64_t *n_records, int32_t *n_fields,
+                             uint32_t *record_bytes) {
+  if (!s) return fail(ADHA_ERR_INVALID, "struct is NULL");
+  if (n_records) *n_records = s->shape.n;
+  if (n_fields) *n_fields = s->shape.nfields();
+  if (record_bytes) *record_bytes = s->shape.record_bytes();
+  return ADHA_OK;
+}
+
+// ------------------------------------------------------------------ layouts
+static adha_status emit_layout(LayoutDesc d, adha_layout **out) {
+  adha_layout *l = new_layout(std::move(d));
+  if (!l) return fail(ADHA_ERR_OOM, "layout allocation failed");
+  *out = l;
+  return ADHA_OK;
+}
+
+adha_status adha_layout_create(const adha_struct *s, uint32_t n_groups, const uint32_t *group_of_field,
+                               const uint32_t *tile_of_group, adha_layout **out) {
+  if (!s || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
+  LayoutDesc d;
+  ADHA_TRY(build_layout(s->shape, n_groups, group_of_field, tile_of_group, &d));
+  return emit_layout(std::move(d), out);
+}
+
+adha_status adha_layout_aos(const adha_struct *s, adha_layout **out) {
+  if (!s || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (s->shape.nfields() == 0) return fail(ADHA_ERR_INVALID, "struct has no fields");
+  return emit_layout(layout_aos(s->shape), out);
+}
+
+adha_status adha_layout_soa(const adha_struct *s, adha_layout **out) {
+  if (!s || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (s->shape.nfields() == 0) return fail(ADHA_ERR_INVALID, "struct has no fields");
+  return emit_layout(layout_soa(s->shape), out);
+}
+
+adha_status adha_layout_destroy(adha_layout *l) {
+  delete l;
+  return ADHA_OK;
+}
+
+adha_status adha_layout_nbytes(const adha_layout *l, uint64_t *out) {
+  if (!l || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
+  *out = l->d.nbytes;
+  return ADHA_OK;
+}
+
+adha_status adha_layout_addr(const adha_layout *l, int64_t r, int32_t f, uint64_t *out) {
+  if (!l || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (r < 0 || r >= l->d.shape.n) return fail(ADHA_ERR_INVALID, "record %lld out of range", (long long)r);
+  if (f < 0 || f >= l->d.shape.nfields()) return fail(ADHA_ERR_INVALID, "field %d out of range", f);
+  *out = l->d.addr(r, f);
+  return ADHA_OK;
+}
+
+adha_status adha_layout_groups(const adha_layout *l, uint32_t *n_groups, uint32_t *group_of_field,
+                               uint32_t *tile_of_group) {
+  if (!l) return fail(ADHA_ERR_INVALID, "layout is NULL");
+  if (n_groups) *n_groups = (uint32_t)l->d.groups.size();
+  if (group_of_field)
+    for (int f = 0; f < l->d.shape.nfields(); ++f) group_of_field[f] = l->d.group_of[f];
+  if (tile_of_group)
+    for (size_t g = 0; g < l->d.groups.size(); ++g) tile_of_group[g] = l->d.groups[g].T;
+  return ADHA_OK;
+}
+
+adha_status adha_layout_equal(const adha_layout *a, const adha_layout *b, int32_t *out) {
+  if (!a || !b || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
+  *out = a->d.same_map(b->d) ? 1 : 0;
+  return ADHA_OK;
+}
+
+// ------------------------------------------------------------------ remap
+adha_status adha_remap(adha_ctx *ctx, const adha_layout *src_l, const void *src, uint64_t src_cap,
+                       const adha_layout *dst_l, void *dst, uint64_t dst_cap, void *stream) {
+  if (!ctx) return fail(ADHA_ERR_INVALID, "ctx is NULL");
+  ADHA_TRY(validate_remap(src_l, src, src_cap, dst_l, dst, dst_cap));
+  DeviceGuard g(ctx->c.device);
+  return remap_one(&ctx->c, src_l, src, dst_l, dst, (hipStream_t)stream);
+}
+
+adha_status adha_remap_set_shape(adha_ctx *ctx, const adha_layout *src_l, const adha_layout *dst_l,
+                                 const adha_tile_shape *shape) {
+  if (!ctx || !src_l || !dst_l || !shape) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (!src_l->d.shape.same(dst_l->d.shape)) return fail(ADHA_ERR_INVALID, "layouts describe different structs");
+  TileShape d;
+  ADHA_TRY(choose_shape(&ctx->c, src_l->d, dst_l->d, &d));
+  TileShape s;
+  s.R = shape->tile_records ? shape->tile_records : d.R;
+  s.K = shape->slots ? shape->slots : d.K;
+  s.shift = shape->pad_shift ? shape->pad_shift : d.shift;
+  s.wg_per_cu = shape->wg_per_cu ? shape->wg_per_cu : d.wg_per_cu;
+  if (s.R != 0) {
+    if (!src_l->d.dword_fields()) return fail(ADHA_ERR_UNSUPPORTED, "1- and 2-byte fields use the tail path only");
+    ADHA_TRY(check_shape(src_l->d, dst_l->d, s));
+  }
+  ctx->c.forced_shapes[{src_l->id, dst_l->id}] = s;
+  return ADHA_OK;
+}
+
+adha_status adha_remap_get_shape(adha_ctx *ctx, const adha_layout *src_l, const adha_layout *dst_l,
+                                 adha_tile_shape *out) {
+  if (!ctx || !src_l || !dst_l || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
+  TileShape s;
+  ADHA_TRY(shape_for(&ctx->c, src_l, dst_l, &s));
+  out->tile_records = s.R;
+  out->slots = s.K;
+  out->pad_shift = s.shift;
+  out->wg_per_cu = s.wg_per_cu;
+  return ADHA_OK;
+}
+
+adha_status adha_remap_describe(const adha_layout *src_l, const adha_layout *dst_l, int32_t cu_count,
+                                adha_remap_info *out) {
+  if (!src_l || !dst_l || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (!src_l->d.shape.same(dst_l->d.shape)) return fail(ADHA_ERR_INVALID, "layouts describe different structs");
+  if (cu_count <= 0 || cu_count > 4096) return fail(ADHA_ERR_INVALID, "cu_count %d not in [1, 4096]", cu_count);
+  Ctx tmp;
+  tmp.cu_count = cu_count;
+  TileShape s;
+  ADHA_TRY(choose_shape(&tmp, src_l->d, dst_l->d, &s));
+  RemapPrepared p;
+  ADHA_TRY(remap_prepare(&tmp, {&src_l->d}, {nullptr}, {&dst_l->d}, {nullptr}, {s}, &p, false));
+  out->shape.tile_records = s.R;
+  out->shape.slots = s.K;
+  out->shape.pad_shift = s.shift;
+  out->shape.wg_per_cu = s.wg_per_cu;
+  out->full_tiles = p.main_tiles;
+  out->tail_bytes = p.tail_bytes;
+  out->descriptor_bytes = p.desc_bytes;
+  out->grid = p.grid;
+  out->lds_bytes = p.lds;
+  return ADHA_OK;
+}
+
+adha_status adha_remap_batched(adha_ctx *ctx, uint32_t n, const adha_remap_item *items, uint32_t flags,
+                               void *stream) {
+  if (!ctx) return fail(ADHA_ERR_INVALID, "ctx is NULL");
+  if (n == 0) return ADHA_OK;
+  if (!items) return fail(ADHA_ERR_INVALID, "items is NULL");
+  for (uint32_t i = 0; i < n; ++i) {
+    const adha_remap_item &it = items[i];
+    adha_status st = validate_remap(it.src_layout, it.src, it.src_cap, it.dst_layout, it.dst, it.dst_cap);
+    if (st < 0) return fail(st, "item %u: %s", i, adha::last_error());
+  }
+  for (uint32_t i = 0; i < n; ++i)
+    for (uint32_t j = i + 1; j < n; ++j) {
+      const adha_remap_item &a = items[i], &b = items[j];
+      uint64_t an = a.dst_layout->d.nbytes, bn = b.dst_layout->d.nbytes;
+      if (overlap(a.dst, an, b.dst, bn) || overlap(a.dst, an, b.src, b.src_layout->d.nbytes) ||
+          overlap(b.dst, bn, a.src, a.src_layout->d.nbytes))
+        return fail(ADHA_ERR_INVALID, "items %u and %u overlap", i, j);
+    }
+  DeviceGuard g(ctx->c.device);
+  Ctx *c = &ctx->c;
+  hipStream_t st = (hipStream_t)stream;
+  if (flags & ADHA_BATCH_SEPARATE) {
+    for (uint32_t i = 0; i < n; ++i)
+      ADHA_TRY(remap_one(c, items[i].src_layout, items[i].src, items[i].dst_layout, items[i].dst, st));
+    return ADHA_OK;
+  }
+  std::vector<const LayoutDesc *> sl, dl;
+  std::vector<const void *> sp;
+  std::vector<void *> dp;
+  std::vector<TileShape> shapes;
+  std::vector<uint64_t> key{2};
+  for (uint32_t i = 0; i < n; ++i) {
+    const adha_remap_item &it = items[i];
+    if (it.src_layout->d.shape.n == 0 || it.dst_layout->d.nbytes == 0) continue;
+    TileShape sh;
+    ADHA_TRY(shape_for(c, it.src_layout, it.dst_layout, &sh));
+    sl.push_back(&it.src_layout->d);
+    dl.push_back(&it.dst_layout->d);
+    sp.push_back(it.src);
+    dp.push_back(it.dst);
+    shapes.push_back(sh);
+    for (uint64_t v : {it.src_layout->id, it.dst_layout->id, (uint64_t)(uintptr_t)it.src,
+                       (uint64_t)(uintptr_t)it.dst, (uint64_t)sh.R, (uint64_t)sh.K,
+                       (uint64_t)sh.shift, (uint64_t)sh.wg_per_cu})
+      key.push_back(v);
+  }
+  if (sl.empty()) return ADHA_OK;
+  // a batch mixes arrays with different shifts only through its first entry
+  for (auto &s : shapes) s.shift = shapes[0].shift;
+  auto it = c->remap_cache.find(key);
+  if (it == c->remap_cache.end()) {
+    if (c->remap_cache.size() >= kCacheLimit) ADHA_TRY(flush_cache(c));
+    RemapPrepared p;
+    ADHA_TRY(remap_prepare(c, sl, sp, dl, dp, shapes, &p));
+    it = c->remap_cache.emplace(key, p).first;
+  }
+  const RemapPrepared &P = it->second;
+  if (!(flags & ADHA_BATCH_GRAPH)) return remap_run(c, P, nullptr, nullptr, st);
+
+  GraphEntry *ge = nullptr;
+  for (auto &e : c->graphs)
+    if (e.key == key) ge = &e;
+  if (!ge) {
+    hipStream_t cap = nullptr;
+    ADHA_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    GraphEntry e;
+    e.key = key;
+    hipError_t he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    adha_status rs = he == hipSuccess ? remap_run(c, P, nullptr, nullptr, cap) : ADHA_ERR_DEVICE;
+    hipError_t he2 = hipStreamEndCapture(cap, &e.graph);
+    (void)hipStreamDestroy(cap);
+    if (he != hipSuccess || rs < 0 || he2 != hipSuccess) {
+      if (e.graph) (void)hipGraphDestroy(e.graph);
+      return fail(ADHA_ERR_DEVICE, "graph capture of the batched remap failed");
+    }
+    he = hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0);
+    if (he != hipSuccess) {
+      (void)hipGraphDestroy(e.graph);
+      return fail(ADHA_ERR_DEVICE, "graph instantiation failed: %s", hipGetErrorString(he));
+    }
+    c->graphs.push_back(e);
+    ge = &c->graphs.back();
+  }
+  ADHA_HIP(hipGraphLaunch(ge->exec, st));
+  return ADHA_OK;
+}
+
+// ------------------------------------------------------------------ sections
+adha_status adha_section_create(const adha_struct *s, adha_op op, uint32_t n_read, const int32_t *read,
+                                uint32_t n_write, const int32_t *write, uint32_t degree,
+                                adha_section **out) {
+  if (!s || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
+  const Shape &sh = s->shape;
+  const int F = sh.nfields();
+  if (n_read == 0 || n_read > ADHA_MAX_READ)
+    return fail(ADHA_ERR_INVALID, "n_read %u not in [1, %d]", n_read, ADHA_MAX_READ);
+  if (n_write == 0 || n_write > ADHA_MAX_WRITE)
+    return fail(ADHA_ERR_INVALID, "n_write %u not in [1, %d]", n_write, ADHA_MAX_WRITE);
+  if (!read || !write) return fail(ADHA_ERR_INVALID, "read / write arrays are NULL");
+  if (degree > ADHA_MAX_DEGREE) return fail(ADHA_ERR_INVALID, "degree %u > %d", degree, ADHA_MAX_DEGREE);
+  SectionDesc d;
+  d.shape = sh;
+  d.op = (int32_t)op;
+  d.degree = degree;
+  d.rd.assign(read, read + n_read);
+  d.wr.assign(write, write + n_write);
+  std::sort(d.rd.begin(), d.rd.end());
+  std::sort(d.wr.begin(), d.wr.end());
+  for (auto *v : {&d.rd, &d.wr}) {
+    for (size_t i = 0; i < v->size(); ++i) {
+      int f = (*v)[i];
+      if (f < 0 || f >= F) return fail(ADHA_ERR_INVALID, "field id %d out of range", f);
+      if (i && (*v)[i - 1] == f) return fail(ADHA_ERR_INVALID, "field id %d listed twice", f);
+      if (sh.dtype[f] == ADHA_RAW) return fail(ADHA_ERR_UNSUPPORTED, "field %d is RAW; sections need typed fields", f);
+    }
+  }
+  if (degree > 0) {
+    for (int f : d.wr)
+      if (std::find(d.rd.begin(), d.rd.end(), f) != d.rd.end())
+        return fail(ADHA_ERR_INVALID, "gather section writes field %d that it reads (records would race)", f);
+  }
+  switch (op) {
+    case ADHA_OP_GEN:
+      break;
+    case ADHA_OP_MULADD3:
+    case ADHA_OP_SUB2:
+    case ADHA_OP_SUM: {
+      uint32_t need = op == ADHA_OP_MULADD3 ? 3 : op == ADHA_OP_SUB2 ? 2 : 0;
+      if (need && n_read != need) return fail(ADHA_ERR_INVALID, "op needs exactly %u read fields", need);
+      if (n_write != 1) return fail(ADHA_ERR_INVALID, "op writes exactly one field");
+      if (degree) return fail(ADHA_ERR_UNSUPPORTED, "op is direct only");
+      if (sh.dtype[d.wr[0]] == ADHA_I32) return fail(ADHA_ERR_UNSUPPORTED, "op needs a floating-point write field");
+      break;
+    }
+    default:
+      return fail(ADHA_ERR_INVALID, "unknown op %d", (int)op);
+  }
+  auto *sec = new (std::nothrow) adha_section;
+  if (!sec) return fail(ADHA_ERR_OOM, "section allocation failed");
+  sec->d = std::move(d);
+  *out = sec;
+  return ADHA_OK;
+}
+
+adha_status adha_section_destroy(adha_section *sec) {
+  delete sec;
+  return ADHA_OK;
+}
+
+adha_status adha_section_bytes(const adha_section *sec, uint64_t *out) {
+  if (!sec || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
+  *out = sec->d.algorithmic_bytes();
+  return ADHA_OK;
+}
+
+}  // extern "C"
+
+namespace adha {
+adha_status validate_section_run(const adha_section *sec, const adha_layout *l, const void *buf,
+                                 uint64_t buf_cap, const int32_t *idx, uint64_t idx_count) {
+  if (!sec || !l) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (!sec->d.shape.same(l->d.shape)) return fail(ADHA_ERR_INVALID, "section and layout describe different structs");
+  ADHA_TRY(check_dev_buf("buf", buf, buf_cap, l->d.nbytes));
+  if (sec->d.degree > 0 && l->d.shape.n > 0) {
+    if (!idx) return fail(ADHA_ERR_INVALID, "gather section needs an index array");
+    if (!aligned(idx)) return fail(ADHA_ERR_INVALID, "idx is not 256-byte aligned");
+    if (idx_count < (uint64_t)l->d.shape.n * sec->d.degree)
+      return fail(ADHA_ERR_INVALID, "idx holds %llu entries, N*d = %llu are needed",
+                  (unsigned long long)idx_count, (unsigned long long)l->d.shape.n * sec->d.degree);
+    if (overlap(idx, idx_count * 4, buf, l->d.nbytes)) return fail(ADHA_ERR_INVALID, "idx overlaps buf");
+  }
+  return ADHA_OK;
+}
+}  // namespace adha
+
+extern "C" {
+
+adha_status adha_section_run(adha_ctx *ctx, const adha_section *sec, const adha_layout *l, void *buf,
+                             uint64_t buf_cap, const int32_t *idx, uint64_t idx_count, void *stream) {
+  if (!ctx) return fail(ADHA_ERR_INVALID, "ctx is NULL");
+  ADHA_TRY(validate_section_run(sec, l, buf, buf_cap, idx, idx_count));
+  DeviceGuard g(ctx->c.device);
+  return section_launch(&ctx->c, sec->d, l->d, buf, idx, (hipStream_t)stream);
+}
+
+}  // extern "C"

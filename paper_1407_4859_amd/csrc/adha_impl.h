@@ -1,0 +1,195 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "adha.h"
+
+namespace adha {
+
+// ------------------------------------------------------------------ errors
+adha_status fail(adha_status st, const char *fmt, ...);
+void clear_error();
+
+#define ADHA_TRY(expr)                 \
+  do {                                 \
+    adha_status st_ = (expr);          \
+    if (st_ < 0) return st_;           \
+  } while (0)
+
+#define ADHA_HIP(expr)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return ::adha::fail(ADHA_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// ------------------------------------------------------------------ shapes
+struct Shape {
+  int64_t n = 0;
+  std::vector<int32_t> dtype;
+  std::vector<uint32_t> ebytes;
+  int nfields() const { return (int)ebytes.size(); }
+  uint32_t record_bytes() const {
+    uint32_t s = 0;
+    for (auto e : ebytes) s += e;
+    return s;
+  }
+  bool same(const Shape &o) const { return n == o.n && dtype == o.dtype && ebytes == o.ebytes; }
+};
+
+struct Group {
+  std::vector<int> fields;  // ascending
+  uint32_t T = 1, logT = 0, S = 0;
+  uint64_t base = 0, bytes = 0;  // bytes = roundup(N, T) * S
+};
+
+// Canonical layout: groups ordered by smallest field id, fields packed.
+struct LayoutDesc {
+  Shape shape;
+  std::vector<Group> groups;
+  std::vector<uint32_t> group_of, p;  // per field: group index, byte offset in group record
+  uint64_t nbytes = 0;
+
+  uint64_t addr(int64_t r, int f) const {
+    const Group &g = groups[group_of[f]];
+    return g.base + (uint64_t)(r >> g.logT) * g.T * g.S + (uint64_t)p[f] * g.T +
+           (uint64_t)(r & (g.T - 1)) * shape.ebytes[f];
+  }
+  uint64_t group_end(size_t gi) const {  // start of the next group (or the size)
+    return gi + 1 < groups.size() ? groups[gi + 1].base : nbytes;
+  }
+  bool same_map(const LayoutDesc &o) const;
+  bool dword_fields() const;   // every element is 4 or 8 bytes
+  uint32_t max_tile() const;
+  int layout_class() const;    // 0 AoS, 1 SoA, 2 tiled, 3 grouped interleaved / mixed
+};
+
+adha_status build_layout(const Shape &sh, uint32_t n_groups, const uint32_t *gof,
+                         const uint32_t *tog, LayoutDesc *out);
+LayoutDesc layout_aos(const Shape &sh, uint32_t tile = 1);
+LayoutDesc layout_soa(const Shape &sh);
+LayoutDesc layout_from_parts(const Shape &sh, const std::vector<std::vector<int>> &parts,
+                             uint32_t tile);
+
+struct SectionDesc {
+  Shape shape;
+  int32_t op = 0;
+  std::vector<int32_t> rd, wr;
+  uint32_t degree = 0;
+  uint64_t algorithmic_bytes() const;
+};
+
+}  // namespace adha
+
+// --------------------------------------------------------------- handles
+struct adha_struct {
+  adha::Shape shape;
+};
+struct adha_layout {
+  adha::LayoutDesc d;
+  uint64_t id;
+};
+struct adha_section {
+  adha::SectionDesc d;
+};
+struct adha_program {
+  adha::Shape shape;
+  std::vector<adha::SectionDesc> secs;
+};
+
+namespace adha {
+
+uint64_t next_layout_id();
+adha_layout *new_layout(LayoutDesc d);
+
+// ------------------------------------------------------------------ remap
+struct TileShape {
+  uint32_t R = 0, K = 0, shift = 0, wg_per_cu = 0;
+};
+
+struct Ctx;
+// A remap launch, prepared once: its descriptor blob lives in device memory
+// (owned by the context's cache) and only kernel launches remain.
+struct RemapPrepared {
+  uint8_t *dev = nullptr;           // blob allocation
+  const uint8_t *arrays = nullptr;  // every array (tail kernel)
+  const uint8_t *main_arrays = nullptr;  // arrays with full tiles (main kernel)
+  const uint8_t *tails = nullptr;
+  uint64_t main_tiles = 0, tiles_per_wg = 0, grid = 0, tail_blocks = 0;
+  uint32_t n_arrays = 0, n_main = 0, n_tails = 0;
+  uint32_t K = 1, shift = 6, wg_per_cu = 1, lds = 0;
+  uint64_t desc_bytes = 0, tail_bytes = 0;
+};
+// Builds the descriptor blob of a launch; with upload it is copied into a
+// new device allocation (owned by the caller through RemapPrepared::dev).
+adha_status remap_prepare(Ctx *ctx, const std::vector<const LayoutDesc *> &src_l,
+                          const std::vector<const void *> &src,
+                          const std::vector<const LayoutDesc *> &dst_l,
+                          const std::vector<void *> &dst, const std::vector<TileShape> &shapes,
+                          RemapPrepared *out, bool upload = true);
+// src_override / dst_override replace the (single) array's pointers when set.
+adha_status remap_run(Ctx *ctx, const RemapPrepared &p, const void *src_override,
+                      void *dst_override, hipStream_t stream);
+adha_status choose_shape(const Ctx *ctx, const LayoutDesc &a, const LayoutDesc &b, TileShape *out);
+adha_status check_shape(const LayoutDesc &a, const LayoutDesc &b, const TileShape &s);
+uint32_t remap_lds_bytes(const LayoutDesc &a, const TileShape &s);
+
+// ------------------------------------------------------------------ sections
+adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l, void *buf,
+                           const int32_t *idx, hipStream_t stream);
+
+// ------------------------------------------------------------------ MLP
+adha_status mlp_forward(Ctx *ctx, const float *params, const float *x, uint32_t batch, float *y,
+                        hipStream_t stream);
+adha_status mlp_backward(Ctx *ctx, const float *params, const float *x, const float *target,
+                         uint32_t batch, float *grad, float *loss, float *scratch,
+                         hipStream_t stream);
+adha_status mlp_adam(Ctx *ctx, float *params, const float *grad, float *m, float *v, float lr,
+                     float b1, float b2, float eps, uint32_t t, hipStream_t stream);
+size_t mlp_scratch_floats(uint32_t batch);
+
+// ------------------------------------------------------------------ context
+struct GraphEntry {
+  std::vector<uint64_t> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+struct Ctx {
+  int device = 0;
+  std::map<std::vector<uint64_t>, RemapPrepared> remap_cache;
+  int cu_count = 256;
+  std::string arch;
+  uint32_t *err_flag = nullptr;  // device word: gather index out of range seen
+  std::map<std::tuple<uint64_t, uint64_t>, TileShape> forced_shapes;
+  std::vector<GraphEntry> graphs;
+  std::vector<float> model;  // trained / loaded cost-model parameters (empty = none)
+  bool has_model = false;
+  ~Ctx();
+};
+
+// Switches to the context's device for the lifetime of the guard.
+struct DeviceGuard {
+  int prev = -1;
+  bool changed = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) changed = (hipSetDevice(dev) == hipSuccess);
+  }
+  ~DeviceGuard() {
+    if (changed) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace adha
+
+struct adha_ctx {
+  adha::Ctx c;
+};

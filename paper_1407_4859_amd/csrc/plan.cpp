@@ -1,0 +1,551 @@
+// Two-level layout selection and plan execution.
+//
+// Level 1, the ODS pass (section 2): an affinity graph over the fields a
+// run of sections touches, then greedy clustering of the fields into
+// structures no larger than a capacity in bytes.
+// Level 2, the PDL pass (section 2): the sections in program order form a
+// layered DAG whose nodes are (section, candidate layout); keeping a layout
+// between consecutive sections is the paper's "combine" choice (the layout
+// of a combined run is the ODS of the merged sections), changing it costs a
+// "remap"; a shortest path gives the program layout.  Edge weights come from
+// a profile of section times (measured on the device, the analytic bytes
+// model, or the learned model).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "adha_impl.h"
+
+struct adha_plan {
+  adha::Shape shape;
+  std::vector<adha::SectionDesc> secs;
+  std::vector<adha_layout *> cands;
+  std::vector<uint32_t> choice;
+  std::vector<double> T, R;  // k*C and C*C, microseconds
+  double cost = 0.0, seconds = 0.0;
+  ~adha_plan() {
+    for (auto *l : cands) delete l;
+  }
+};
+
+namespace adha {
+
+adha_status remap_one(Ctx *ctx, const adha_layout *sl, const void *src, const adha_layout *dl,
+                      void *dst, hipStream_t stream);
+adha_status validate_section_run(const adha_section *sec, const adha_layout *l, const void *buf,
+                                 uint64_t buf_cap, const int32_t *idx, uint64_t idx_count);
+adha_status fill_uniform_index(int32_t *idx, uint64_t count, int64_t n, uint64_t seed, hipStream_t stream);
+adha_status predict_costs(Ctx *ctx, const std::vector<std::vector<float>> &feats, std::vector<double> *us,
+                          hipStream_t stream);
+void section_features(const SectionDesc &s, const LayoutDesc &l, float *out);
+
+// ------------------------------------------------------------------ affinity
+std::vector<uint64_t> affinity(const std::vector<SectionDesc> &secs, size_t first, size_t last, int F) {
+  std::vector<uint64_t> w((size_t)F * F, 0);
+  auto bump = [&](const std::vector<int32_t> &ids, uint64_t amount) {
+    for (size_t x = 0; x < ids.size(); ++x)
+      for (size_t y = x + 1; y < ids.size(); ++y) {
+        w[(size_t)ids[x] * F + ids[y]] += amount;
+        w[(size_t)ids[y] * F + ids[x]] += amount;
+      }
+  };
+  for (size_t s = first; s <= last; ++s) {
+    const SectionDesc &d = secs[s];
+    if (d.degree == 0) {
+      std::vector<int32_t> all = d.rd;
+      for (int f : d.wr)
+        if (std::find(all.begin(), all.end(), f) == all.end()) all.push_back(f);
+      std::sort(all.begin(), all.end());
+      bump(all, 1);
+    } else {
+      bump(d.rd, d.degree);
+      bump(d.wr, 1);
+    }
+  }
+  return w;
+}
+
+// Greedy clustering: edges by decreasing weight (ties by smaller then larger
+// id); an edge joins its two clusters when they differ and fit the cap.
+std::vector<std::vector<int>> ods_parts(const std::vector<SectionDesc> &secs, size_t first, size_t last,
+                                        const Shape &sh, uint32_t cap) {
+  const int F = sh.nfields();
+  auto w = affinity(secs, first, last, F);
+  struct E {
+    uint64_t w;
+    int a, b;
+  };
+  std::vector<E> edges;
+  for (int a = 0; a < F; ++a)
+    for (int b = a + 1; b < F; ++b)
+      if (w[(size_t)a * F + b] > 0) edges.push_back({w[(size_t)a * F + b], a, b});
+  std::sort(edges.begin(), edges.end(), [](const E &x, const E &y) {
+    if (x.w != y.w) return x.w > y.w;
+    if (x.a != y.a) return x.a < y.a;
+    return x.b < y.b;
+  });
+  std::vector<int> cl(F);
+  std::vector<uint64_t> bytes(F);
+  for (int f = 0; f < F; ++f) {
+    cl[f] = f;
+    bytes[f] = sh.ebytes[f];
+  }
+  for (const E &e : edges) {
+    int ca = cl[e.a], cb = cl[e.b];
+    if (ca == cb || bytes[ca] + bytes[cb] > cap) continue;
+    int keep = std::min(ca, cb), drop = std::max(ca, cb);
+    for (int f = 0; f < F; ++f)
+      if (cl[f] == drop) cl[f] = keep;
+    bytes[keep] += bytes[drop];
+  }
+  std::vector<std::vector<int>> parts;
+  for (int c = 0; c < F; ++c) {
+    std::vector<int> m;
+    for (int f = 0; f < F; ++f)
+      if (cl[f] == c) m.push_back(f);
+    if (m.size() > 1) parts.push_back(m);
+  }
+  std::sort(parts.begin(), parts.end());
+  return parts;
+}
+
+// ------------------------------------------------------------------ shortest path
+adha_status pdl_solve(uint32_t k, uint32_t C, const double *T, const double *R, const double *R0,
+                      std::vector<uint32_t> *path, double *cost) {
+  std::vector<double> dist(C), nd(C);
+  std::vector<uint32_t> back((size_t)k * C, 0);
+  for (uint32_t c = 0; c < C; ++c) dist[c] = (R0 ? R0[c] : 0.0) + T[c];
+  for (uint32_t s = 1; s < k; ++s) {
+    for (uint32_t b = 0; b < C; ++b) {
+      double best = 0.0;
+      uint32_t arg = 0;
+      for (uint32_t a = 0; a < C; ++a) {
+        const double v = dist[a] + (a == b ? 0.0 : R[(size_t)a * C + b]);
+        if (a == 0 || v < best) {
+          best = v;
+          arg = a;
+        }
+      }
+      nd[b] = best + T[(size_t)s * C + b];
+      back[(size_t)s * C + b] = arg;
+    }
+    dist.swap(nd);
+  }
+  uint32_t end = 0;
+  for (uint32_t c = 1; c < C; ++c)
+    if (dist[c] < dist[end]) end = c;
+  path->assign(k, 0);
+  (*path)[k - 1] = end;
+  for (uint32_t s = k - 1; s > 0; --s) (*path)[s - 1] = back[(size_t)s * C + (*path)[s]];
+  *cost = dist[end];
+  return ADHA_OK;
+}
+
+// ------------------------------------------------------------------ catalogue
+static const uint32_t kAosoaTile = 64;
+
+static void catalogue(const Shape &sh, const std::vector<SectionDesc> &secs, bool full, uint32_t cap,
+                      std::vector<LayoutDesc> *out) {
+  std::vector<LayoutDesc> all{layout_aos(sh), layout_soa(sh)};
+  if (full) {
+    all.push_back(layout_aos(sh, kAosoaTile));
+    for (size_t i = 0; i < secs.size(); ++i)
+      for (size_t j = i; j < secs.size(); ++j) {
+        auto parts = ods_parts(secs, i, j, sh, cap);
+        all.push_back(layout_from_parts(sh, parts, 1));
+        all.push_back(layout_from_parts(sh, parts, kAosoaTile));
+      }
+  }
+  for (auto &L : all) {
+    bool dup = false;
+    for (auto &M : *out)
+      if (M.same_map(L)) dup = true;
+    if (!dup) out->push_back(L);
+  }
+}
+
+// ------------------------------------------------------------------ costs
+// Analytic model: effective HBM bytes per record over a bandwidth.
+static const double kGranule = 64.0;       // bytes per DRAM access granule
+static const double kBytesPerUs = 5.6e6;   // 70% of 8 TB/s
+static const double kLaunchUs = 4.0;
+
+static double group_stream_bytes(const LayoutDesc &l, size_t gi, const std::vector<int32_t> &touched) {
+  const Group &g = l.groups[gi];
+  double b = 0.0;
+  for (int f : touched)
+    if (l.group_of[f] == gi) b += std::max<double>(l.shape.ebytes[f], kGranule / g.T);
+  return std::min<double>(b, g.S);
+}
+
+static double group_random_bytes(const LayoutDesc &l, size_t gi, const std::vector<int32_t> &touched) {
+  const Group &g = l.groups[gi];
+  if (g.T == 1 && g.fields.size() > 1) {
+    uint32_t lo = ~0u, hi = 0;
+    for (int f : touched)
+      if (l.group_of[f] == gi) {
+        lo = std::min(lo, l.p[f]);
+        hi = std::max(hi, l.p[f] + l.shape.ebytes[f]);
+      }
+    if (hi == 0) return 0.0;
+    return (hi - lo) + kGranule - 1.0;
+  }
+  double b = 0.0;
+  for (int f : touched)
+    if (l.group_of[f] == gi) b += l.shape.ebytes[f] + kGranule - 1.0;
+  return b;
+}
+
+double analytic_bytes_per_record(const SectionDesc &s, const LayoutDesc &l) {
+  double b = 0.0;
+  for (size_t gi = 0; gi < l.groups.size(); ++gi) {
+    if (s.degree == 0) b += group_stream_bytes(l, gi, s.rd);
+    else b += s.degree * group_random_bytes(l, gi, s.rd);
+    b += group_stream_bytes(l, gi, s.wr);
+  }
+  if (s.degree) b += 4.0 * s.degree;
+  return b;
+}
+
+double analytic_section_us(const SectionDesc &s, const LayoutDesc &l) {
+  return kLaunchUs + (double)l.shape.n * analytic_bytes_per_record(s, l) / kBytesPerUs;
+}
+
+double analytic_remap_us(const LayoutDesc &a, const LayoutDesc &b) {
+  if (a.same_map(b)) return 0.0;
+  return kLaunchUs + 2.0 * (double)a.shape.n * a.shape.record_bytes() / kBytesPerUs;
+}
+
+// Median time in microseconds of `reps` runs of fn on `stream`, after one warm-up.
+template <class Fn>
+static adha_status time_us(hipStream_t stream, uint32_t reps, Fn fn, double *out) {
+  hipEvent_t a, b;
+  ADHA_HIP(hipEventCreate(&a));
+  ADHA_HIP(hipEventCreate(&b));
+  std::vector<double> ts;
+  adha_status st = fn();
+  for (uint32_t r = 0; r < reps && st >= 0; ++r) {
+    (void)hipEventRecord(a, stream);
+    st = fn();
+    (void)hipEventRecord(b, stream);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    ts.push_back(ms * 1000.0);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (st < 0) return st;
+  std::sort(ts.begin(), ts.end());
+  *out = ts.empty() ? 0.0 : ts[ts.size() / 2];
+  return ADHA_OK;
+}
+
+struct DevBuf {
+  void *p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  adha_status alloc(size_t n) {
+    if (hipMalloc(&p, std::max<size_t>(n, 256)) != hipSuccess) {
+      p = nullptr;
+      return fail(ADHA_ERR_OOM, "device scratch of %zu bytes failed", n);
+    }
+    return ADHA_OK;
+  }
+};
+
+static adha_status measured_costs(Ctx *ctx, const Shape &sh, const std::vector<SectionDesc> &secs,
+                                  const std::vector<adha_layout *> &cands, uint32_t reps,
+                                  const int32_t *idx_in, uint64_t idx_count, hipStream_t stream,
+                                  std::vector<double> *T, std::vector<double> *R) {
+  const size_t k = secs.size(), C = cands.size();
+  uint64_t maxb = 0;
+  uint32_t maxd = 0;
+  for (auto *l : cands) maxb = std::max(maxb, l->d.nbytes);
+  for (auto &s : secs) maxd = std::max(maxd, s.degree);
+  DevBuf a, b, ix;
+  ADHA_TRY(a.alloc(maxb));
+  ADHA_TRY(b.alloc(maxb));
+  ADHA_HIP(hipMemsetAsync(a.p, 0, maxb, stream));
+  const int32_t *idx = idx_in;
+  if (maxd > 0 && sh.n > 0 && (!idx_in || idx_count < (uint64_t)sh.n * maxd)) {
+    ADHA_TRY(ix.alloc((size_t)sh.n * maxd * 4));
+    ADHA_TRY(fill_uniform_index((int32_t *)ix.p, (uint64_t)sh.n * maxd, sh.n, 0x5eedULL, stream));
+    idx = (const int32_t *)ix.p;
+  }
+  T->assign(k * C, 0.0);
+  for (size_t c = 0; c < C; ++c)
+    for (size_t s = 0; s < k; ++s) {
+      // a gather section's index array is [N][d]; a wider one is read as [N][d] too
+      ADHA_TRY(time_us(stream, reps,
+                       [&] { return section_launch(ctx, secs[s], cands[c]->d, a.p, idx, stream); },
+                       &(*T)[s * C + c]));
+    }
+  // The remap always moves the whole struct: one measured figure, from a
+  // few representative pairs, serves every pair of different layouts.
+  double rsum = 0.0;
+  int rn = 0;
+  for (size_t c = 1; c < C && rn < 4; ++c) {
+    double t = 0.0;
+    ADHA_TRY(time_us(stream, reps, [&] { return remap_one(ctx, cands[0], a.p, cands[c], b.p, stream); }, &t));
+    rsum += t;
+    ++rn;
+  }
+  const double rem = rn ? rsum / rn : 0.0;
+  R->assign(C * C, 0.0);
+  for (size_t x = 0; x < C; ++x)
+    for (size_t y = 0; y < C; ++y)
+      if (x != y) (*R)[x * C + y] = rem;
+  ADHA_HIP(hipStreamSynchronize(stream));
+  return ADHA_OK;
+}
+
+}  // namespace adha
+
+using namespace adha;
+
+extern "C" {
+
+adha_status adha_program_create(const adha_struct *s, uint32_t k, const adha_section *const *secs,
+                                adha_program **out) {
+  if (!s || !out || (k && !secs)) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (k == 0 || k > ADHA_MAX_SECTIONS) return fail(ADHA_ERR_INVALID, "k = %u not in [1, %d]", k, ADHA_MAX_SECTIONS);
+  auto *p = new (std::nothrow) adha_program;
+  if (!p) return fail(ADHA_ERR_OOM, "program allocation failed");
+  p->shape = s->shape;
+  for (uint32_t i = 0; i < k; ++i) {
+    if (!secs[i] || !secs[i]->d.shape.same(s->shape)) {
+      delete p;
+      return fail(ADHA_ERR_INVALID, "section %u is NULL or belongs to another struct", i);
+    }
+    p->secs.push_back(secs[i]->d);
+  }
+  *out = p;
+  return ADHA_OK;
+}
+
+adha_status adha_program_destroy(adha_program *p) {
+  delete p;
+  return ADHA_OK;
+}
+
+adha_status adha_affinity(const adha_program *p, uint32_t first, uint32_t last, uint64_t *w) {
+  if (!p || !w) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (first > last || last >= p->secs.size()) return fail(ADHA_ERR_INVALID, "bad section range");
+  auto v = affinity(p->secs, first, last, p->shape.nfields());
+  memcpy(w, v.data(), v.size() * sizeof(uint64_t));
+  return ADHA_OK;
+}
+
+adha_status adha_ods(const adha_program *p, uint32_t first, uint32_t last, uint32_t cap_bytes, uint32_t tile,
+                     adha_layout **out) {
+  if (!p || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (first > last || last >= p->secs.size()) return fail(ADHA_ERR_INVALID, "bad section range");
+  if (tile == 0 || tile > ADHA_MAX_TILE || (tile & (tile - 1))) return fail(ADHA_ERR_INVALID, "bad tile %u", tile);
+  auto parts = ods_parts(p->secs, first, last, p->shape, cap_bytes);
+  adha_layout *l = new_layout(layout_from_parts(p->shape, parts, tile));
+  if (!l) return fail(ADHA_ERR_OOM, "layout allocation failed");
+  *out = l;
+  return ADHA_OK;
+}
+
+adha_status adha_pdl_solve(uint32_t k, uint32_t C, const double *T, const double *R, const double *R0,
+                           uint32_t *path, double *cost) {
+  if (!T || !R || !path || !cost) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (k == 0 || C == 0) return fail(ADHA_ERR_INVALID, "k and C must be positive");
+  std::vector<uint32_t> pv;
+  double c = 0;
+  ADHA_TRY(pdl_solve(k, C, T, R, R0, &pv, &c));
+  memcpy(path, pv.data(), k * sizeof(uint32_t));
+  *cost = c;
+  return ADHA_OK;
+}
+
+adha_status adha_plan_opts_default(adha_plan_opts *o) {
+  if (!o) return fail(ADHA_ERR_INVALID, "NULL argument");
+  o->cost = ADHA_COST_MEASURED;
+  o->catalogue = ADHA_CAT_FULL;
+  o->cap_bytes = 64;
+  o->init = ADHA_INIT_FREE;
+  o->reps = 5;
+  return ADHA_OK;
+}
+
+adha_status adha_plan_create(adha_ctx *ctx, const adha_program *p, const adha_plan_opts *o,
+                             const int32_t *idx, uint64_t idx_count, void *stream, adha_plan **out) {
+  if (!p || !o || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (o->cost != ADHA_COST_ANALYTIC && !ctx) return fail(ADHA_ERR_INVALID, "measured and learned costs need a context");
+  if (o->cap_bytes == 0) return fail(ADHA_ERR_INVALID, "cap_bytes must be positive");
+  if (o->cost < ADHA_COST_MEASURED || o->cost > ADHA_COST_LEARNED) return fail(ADHA_ERR_INVALID, "unknown cost source");
+  if (idx && ((uintptr_t)idx & 255u)) return fail(ADHA_ERR_INVALID, "idx is not 256-byte aligned");
+  auto t0 = std::chrono::steady_clock::now();
+  std::unique_ptr<adha_plan> pl(new (std::nothrow) adha_plan);
+  if (!pl) return fail(ADHA_ERR_OOM, "plan allocation failed");
+  pl->shape = p->shape;
+  pl->secs = p->secs;
+  std::vector<LayoutDesc> cat;
+  catalogue(p->shape, p->secs, o->catalogue == ADHA_CAT_FULL, o->cap_bytes, &cat);
+  for (auto &L : cat) {
+    adha_layout *l = new_layout(L);
+    if (!l) return fail(ADHA_ERR_OOM, "layout allocation failed");
+    pl->cands.push_back(l);
+  }
+  const size_t k = p->secs.size(), C = pl->cands.size();
+  adha_status result = ADHA_OK;
+  adha_cost_source src = o->cost;
+  hipStream_t st = (hipStream_t)stream;
+  std::unique_ptr<DeviceGuard> guard;
+  if (ctx) guard.reset(new DeviceGuard(ctx->c.device));
+  if (src == ADHA_COST_LEARNED) {
+    if (!ctx->c.has_model) {
+      src = ADHA_COST_MEASURED;
+      result = ADHA_WARN_FALLBACK;
+    } else {
+      std::vector<std::vector<float>> feats;
+      for (size_t s = 0; s < k; ++s)
+        for (size_t c = 0; c < C; ++c) {
+          std::vector<float> f(ADHA_N_FEATURES);
+          section_features(p->secs[s], pl->cands[c]->d, f.data());
+          feats.push_back(f);
+        }
+      std::vector<double> us;
+      ADHA_TRY(predict_costs(&ctx->c, feats, &us, st));
+      pl->T = us;
+      pl->R.assign(C * C, 0.0);
+      for (size_t a = 0; a < C; ++a)
+        for (size_t b = 0; b < C; ++b) pl->R[a * C + b] = analytic_remap_us(pl->cands[a]->d, pl->cands[b]->d);
+    }
+  }
+  if (src == ADHA_COST_ANALYTIC) {
+    pl->T.resize(k * C);
+    pl->R.resize(C * C);
+    for (size_t s = 0; s < k; ++s)
+      for (size_t c = 0; c < C; ++c) pl->T[s * C + c] = analytic_section_us(p->secs[s], pl->cands[c]->d);
+    for (size_t a = 0; a < C; ++a)
+      for (size_t b = 0; b < C; ++b) pl->R[a * C + b] = analytic_remap_us(pl->cands[a]->d, pl->cands[b]->d);
+  } else if (src == ADHA_COST_MEASURED) {
+    ADHA_TRY(measured_costs(&ctx->c, p->shape, p->secs, pl->cands, std::max<uint32_t>(1, o->reps), idx,
+                            idx_count, st, &pl->T, &pl->R));
+  }
+  std::vector<double> R0(C, 0.0);
+  if (o->init == ADHA_INIT_AOS)
+    for (size_t c = 0; c < C; ++c) R0[c] = pl->R[0 * C + c];
+  ADHA_TRY(pdl_solve((uint32_t)k, (uint32_t)C, pl->T.data(), pl->R.data(), R0.data(), &pl->choice, &pl->cost));
+  pl->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *out = pl.release();
+  return result;
+}
+
+adha_status adha_plan_uniform(const adha_program *p, const adha_layout *l, adha_plan **out) {
+  if (!p || !l || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (!p->shape.same(l->d.shape)) return fail(ADHA_ERR_INVALID, "layout describes another struct");
+  auto *pl = new (std::nothrow) adha_plan;
+  if (!pl) return fail(ADHA_ERR_OOM, "plan allocation failed");
+  pl->shape = p->shape;
+  pl->secs = p->secs;
+  adha_layout *c = new_layout(l->d);
+  if (!c) {
+    delete pl;
+    return fail(ADHA_ERR_OOM, "layout allocation failed");
+  }
+  pl->cands.push_back(c);
+  pl->choice.assign(p->secs.size(), 0);
+  pl->T.assign(p->secs.size(), 0.0);
+  pl->R.assign(1, 0.0);
+  *out = pl;
+  return ADHA_OK;
+}
+
+adha_status adha_plan_destroy(adha_plan *pl) {
+  delete pl;
+  return ADHA_OK;
+}
+
+adha_status adha_plan_n_candidates(const adha_plan *pl, uint32_t *out) {
+  if (!pl || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
+  *out = (uint32_t)pl->cands.size();
+  return ADHA_OK;
+}
+
+adha_status adha_plan_candidate(const adha_plan *pl, uint32_t c, const adha_layout **out) {
+  if (!pl || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (c >= pl->cands.size()) return fail(ADHA_ERR_INVALID, "candidate %u out of range", c);
+  *out = pl->cands[c];
+  return ADHA_OK;
+}
+
+adha_status adha_plan_choice(const adha_plan *pl, uint32_t s, uint32_t *candidate) {
+  if (!pl || !candidate) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (s >= pl->choice.size()) return fail(ADHA_ERR_INVALID, "section %u out of range", s);
+  *candidate = pl->choice[s];
+  return ADHA_OK;
+}
+
+adha_status adha_plan_cost(const adha_plan *pl, double *us) {
+  if (!pl || !us) return fail(ADHA_ERR_INVALID, "NULL argument");
+  *us = pl->cost;
+  return ADHA_OK;
+}
+
+adha_status adha_plan_tables(const adha_plan *pl, double *T, double *R) {
+  if (!pl) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (T && !pl->T.empty()) memcpy(T, pl->T.data(), pl->T.size() * sizeof(double));
+  if (R && !pl->R.empty()) memcpy(R, pl->R.data(), pl->R.size() * sizeof(double));
+  return ADHA_OK;
+}
+
+adha_status adha_plan_time(const adha_plan *pl, double *seconds) {
+  if (!pl || !seconds) return fail(ADHA_ERR_INVALID, "NULL argument");
+  *seconds = pl->seconds;
+  return ADHA_OK;
+}
+
+adha_status adha_run(adha_ctx *ctx, const adha_plan *pl, const adha_layout *in_layout, void *buf_a,
+                     void *buf_b, uint64_t buf_cap, const int32_t *idx, uint64_t idx_count, void *stream,
+                     const adha_layout **out_layout, int32_t *out_in_b) {
+  if (!ctx || !pl || !in_layout || !out_layout || !out_in_b) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (!in_layout->d.shape.same(pl->shape)) return fail(ADHA_ERR_INVALID, "input layout describes another struct");
+  // validate everything before the first launch
+  const adha_layout *cur = in_layout;
+  bool in_b = false, needs_b = false;
+  uint64_t need = in_layout->d.nbytes;
+  for (size_t s = 0; s < pl->secs.size(); ++s) {
+    const adha_layout *L = pl->cands[pl->choice[s]];
+    need = std::max(need, L->d.nbytes);
+    if (!cur->d.same_map(L->d)) needs_b = true;
+    cur = L;
+    adha_section tmp;
+    tmp.d = pl->secs[s];
+    ADHA_TRY(validate_section_run(&tmp, L, buf_a, buf_cap, idx, idx_count));
+  }
+  if (buf_cap < need) return fail(ADHA_ERR_INVALID, "buffers hold %llu bytes, the plan needs %llu",
+                                  (unsigned long long)buf_cap, (unsigned long long)need);
+  if (need && (!buf_a || ((uintptr_t)buf_a & 255u))) return fail(ADHA_ERR_INVALID, "buf_a is NULL or misaligned");
+  if (needs_b && need && (!buf_b || ((uintptr_t)buf_b & 255u)))
+    return fail(ADHA_ERR_INVALID, "buf_b is NULL or misaligned and the plan remaps");
+  if (needs_b && buf_b) {
+    uintptr_t x = (uintptr_t)buf_a, y = (uintptr_t)buf_b;
+    if (x < y + need && y < x + need) return fail(ADHA_ERR_INVALID, "buf_a and buf_b overlap");
+  }
+  DeviceGuard g(ctx->c.device);
+  hipStream_t st = (hipStream_t)stream;
+  cur = in_layout;
+  for (size_t s = 0; s < pl->secs.size(); ++s) {
+    const adha_layout *L = pl->cands[pl->choice[s]];
+    if (!cur->d.same_map(L->d)) {
+      void *from = in_b ? buf_b : buf_a, *to = in_b ? buf_a : buf_b;
+      ADHA_TRY(remap_one(&ctx->c, cur, from, L, to, st));
+      in_b = !in_b;
+      cur = L;
+    }
+    ADHA_TRY(section_launch(&ctx->c, pl->secs[s], L->d, in_b ? buf_b : buf_a, idx, st));
+  }
+  *out_layout = cur;
+  *out_in_b = in_b ? 1 : 0;
+  return ADHA_OK;
+}
+
+}  // extern "C"

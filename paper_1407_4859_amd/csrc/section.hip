@@ -1,0 +1,258 @@
+// Section kernels for CDNA4 (gfx950).
+//
+// A section (section 2: one data-parallel loop) reads some fields of each
+// record -- of the record itself (direct) or of d neighbour records named by
+// an index array (gather) -- and writes one or two fields of the record.
+// Whatever the layout, field f of record r sits at
+//   base_g + (r >> logT) * T*S_g + p_f*T + (r & (T-1)) * e_f,
+// so a kernel is generic over layouts through five numbers per field and the
+// layout decides the memory traffic: consecutive lanes read consecutive
+// records, which is a dense 256-byte run per field in SoA and in T >= 64
+// tiles, and a strided walk over whole records in interleaved groups.
+// One lane owns one record.  All terms are read before any write, in the
+// order the section's definition fixes, and every floating-point step uses
+// the explicitly rounded intrinsics so that no multiply-add is fused.
+#include <algorithm>
+
+#include "adha_impl.h"
+
+namespace adha {
+
+struct SField {
+  uint64_t base;
+  uint32_t TS;    // T * S_g
+  uint32_t pT;    // p_f * T
+  uint32_t logT;
+  uint32_t e;     // 4 or 8
+  uint32_t dt;
+  uint32_t pad;
+};
+
+struct SectionArgs {
+  uint8_t *buf;
+  const int32_t *idx;
+  uint32_t *err;
+  int64_t n;
+  uint32_t degree, n_read, n_write, op;
+  SField rd[ADHA_MAX_READ];
+  SField wr[ADHA_MAX_WRITE];
+};
+
+__device__ __forceinline__ uint64_t faddr(const SField &F, uint64_t r) {
+  return F.base + (r >> F.logT) * F.TS + F.pT + (r & ((1ull << F.logT) - 1)) * F.e;
+}
+
+__device__ __forceinline__ uint64_t load_term(const uint8_t *buf, const SField &F, uint64_t r) {
+  const uint32_t *p = reinterpret_cast<const uint32_t *>(buf + faddr(F, r));
+  if (F.e == 4) return p[0];
+  return (uint64_t)p[0] | ((uint64_t)p[1] << 32);
+}
+
+__device__ __forceinline__ float to_f32(uint32_t dt, uint64_t b) {
+  if (dt == ADHA_F32) return __uint_as_float((uint32_t)b);
+  if (dt == ADHA_I32) return __int2float_rn((int32_t)(uint32_t)b);
+  return __double2float_rn(__longlong_as_double((long long)b));
+}
+
+__device__ __forceinline__ double to_f64(uint32_t dt, uint64_t b) {
+  if (dt == ADHA_F32) return (double)__uint_as_float((uint32_t)b);
+  if (dt == ADHA_I32) return (double)(int32_t)(uint32_t)b;
+  return __longlong_as_double((long long)b);
+}
+
+__device__ __forceinline__ uint32_t bits32(uint32_t dt, uint64_t b) {
+  return dt == ADHA_F64 ? (uint32_t)b ^ (uint32_t)(b >> 32) : (uint32_t)b;
+}
+
+struct Acc {
+  float f;
+  double d;
+  uint32_t u;
+};
+
+// Fold one term into write k's accumulator (GEN and SUM).
+__device__ __forceinline__ void fold(Acc &a, uint32_t k, uint32_t wdt, uint32_t tdt, uint64_t t) {
+  if (wdt == ADHA_F32) {
+    const float v = to_f32(tdt, t);
+    a.f = k == 0 ? __fadd_rn(a.f, v) : __fadd_rn(__fmul_rn(a.f, 0.5f), v);
+  } else if (wdt == ADHA_F64) {
+    const double v = to_f64(tdt, t);
+    a.d = k == 0 ? __dadd_rn(a.d, v) : __dadd_rn(__dmul_rn(a.d, 0.5), v);
+  } else {
+    const uint32_t u = bits32(tdt, t);
+    a.u = k == 0 ? a.u + u : (a.u ^ u) * 16777619u;
+  }
+}
+
+__device__ __forceinline__ void store_acc(uint8_t *buf, const SField &W, uint64_t r, const Acc &a) {
+  uint32_t *p = reinterpret_cast<uint32_t *>(buf + faddr(W, r));
+  if (W.dt == ADHA_F32) {
+    p[0] = __float_as_uint(a.f);
+  } else if (W.dt == ADHA_F64) {
+    const uint64_t b = (uint64_t)__double_as_longlong(a.d);
+    p[0] = (uint32_t)b;
+    p[1] = (uint32_t)(b >> 32);
+  } else {
+    p[0] = a.u;
+  }
+}
+
+template <int OP, bool GATHER, int MAXR>
+__global__ __launch_bounds__(256) void section_kernel(const SectionArgs a) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  if (i >= (uint64_t)a.n) return;
+  const uint32_t nr = a.n_read, nw = a.n_write;
+  Acc acc[2];
+  acc[0] = acc[1] = Acc{0.0f, 0.0, 0u};
+
+  if constexpr (!GATHER) {
+    uint64_t tv[MAXR];
+#pragma unroll
+    for (int q = 0; q < MAXR; ++q)
+      if (q < (int)nr) tv[q] = load_term(a.buf, a.rd[q], i);
+    if constexpr (OP == ADHA_OP_GEN || OP == ADHA_OP_SUM) {
+#pragma unroll
+      for (int q = 0; q < MAXR; ++q)
+        if (q < (int)nr) {
+          fold(acc[0], 0, a.wr[0].dt, a.rd[q].dt, tv[q]);
+          if (nw > 1) fold(acc[1], 1, a.wr[1].dt, a.rd[q].dt, tv[q]);
+        }
+    } else {
+      const uint32_t wdt = a.wr[0].dt;
+      if (wdt == ADHA_F32) {
+        const float x = to_f32(a.rd[0].dt, tv[0]), y = to_f32(a.rd[1].dt, tv[1]);
+        if constexpr (OP == ADHA_OP_MULADD3)
+          acc[0].f = __fadd_rn(__fmul_rn(x, y), to_f32(a.rd[2].dt, tv[2]));
+        else
+          acc[0].f = __fsub_rn(x, y);
+      } else {
+        const double x = to_f64(a.rd[0].dt, tv[0]), y = to_f64(a.rd[1].dt, tv[1]);
+        if constexpr (OP == ADHA_OP_MULADD3)
+          acc[0].d = __dadd_rn(__dmul_rn(x, y), to_f64(a.rd[2].dt, tv[2]));
+        else
+          acc[0].d = __dsub_rn(x, y);
+      }
+    }
+  } else {
+    const uint32_t deg = a.degree;
+    const int32_t *row = a.idx + i * deg;
+    bool bad = false;
+    for (uint32_t j = 0; j < deg; j += 2) {
+      const bool two = j + 1 < deg;
+      const int32_t n0 = row[j];
+      const int32_t n1 = two ? row[j + 1] : 0;
+      const bool ok0 = n0 >= 0 && (int64_t)n0 < a.n;
+      const bool ok1 = two && n1 >= 0 && (int64_t)n1 < a.n;
+      bad |= !ok0 || (two && !ok1);
+      uint64_t t0[MAXR], t1[MAXR];
+#pragma unroll
+      for (int q = 0; q < MAXR; ++q)
+        if (q < (int)nr) {
+          t0[q] = ok0 ? load_term(a.buf, a.rd[q], (uint64_t)n0) : 0;
+          t1[q] = ok1 ? load_term(a.buf, a.rd[q], (uint64_t)n1) : 0;
+        }
+      if (ok0) {
+#pragma unroll
+        for (int q = 0; q < MAXR; ++q)
+          if (q < (int)nr) {
+            fold(acc[0], 0, a.wr[0].dt, a.rd[q].dt, t0[q]);
+            if (nw > 1) fold(acc[1], 1, a.wr[1].dt, a.rd[q].dt, t0[q]);
+          }
+      }
+      if (ok1) {
+#pragma unroll
+        for (int q = 0; q < MAXR; ++q)
+          if (q < (int)nr) {
+            fold(acc[0], 0, a.wr[0].dt, a.rd[q].dt, t1[q]);
+            if (nw > 1) fold(acc[1], 1, a.wr[1].dt, a.rd[q].dt, t1[q]);
+          }
+      }
+    }
+    if (bad) atomicOr(a.err, 1u);
+  }
+  store_acc(a.buf, a.wr[0], i, acc[0]);
+  if (nw > 1) store_acc(a.buf, a.wr[1], i, acc[1]);
+}
+
+static SField sfield(const LayoutDesc &l, int f) {
+  const Group &g = l.groups[l.group_of[f]];
+  SField s{};
+  s.base = g.base;
+  s.TS = g.T * g.S;
+  s.pT = l.p[f] * g.T;
+  s.logT = g.logT;
+  s.e = l.shape.ebytes[f];
+  s.dt = (uint32_t)l.shape.dtype[f];
+  return s;
+}
+
+template <int OP, bool G>
+static void launch_maxr(uint32_t nr, dim3 grid, const SectionArgs &a, hipStream_t st) {
+  if (nr <= 4) hipLaunchKernelGGL((section_kernel<OP, G, 4>), grid, dim3(256), 0, st, a);
+  else if (nr <= 8) hipLaunchKernelGGL((section_kernel<OP, G, 8>), grid, dim3(256), 0, st, a);
+  else if (nr <= 16) hipLaunchKernelGGL((section_kernel<OP, G, 16>), grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((section_kernel<OP, G, 32>), grid, dim3(256), 0, st, a);
+}
+
+adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l, void *buf,
+                           const int32_t *idx, hipStream_t stream) {
+  const int64_t n = l.shape.n;
+  if (n == 0) return ADHA_OK;
+  SectionArgs a{};
+  a.buf = (uint8_t *)buf;
+  a.idx = idx;
+  a.err = ctx->err_flag;
+  a.n = n;
+  a.degree = sec.degree;
+  a.n_read = (uint32_t)sec.rd.size();
+  a.n_write = (uint32_t)sec.wr.size();
+  a.op = (uint32_t)sec.op;
+  for (size_t q = 0; q < sec.rd.size(); ++q) a.rd[q] = sfield(l, sec.rd[q]);
+  for (size_t k = 0; k < sec.wr.size(); ++k) a.wr[k] = sfield(l, sec.wr[k]);
+  const dim3 grid((uint32_t)((n + 255) / 256));
+  const uint32_t nr = a.n_read;
+  switch (sec.op) {
+    case ADHA_OP_GEN:
+      if (sec.degree) launch_maxr<ADHA_OP_GEN, true>(nr, grid, a, stream);
+      else launch_maxr<ADHA_OP_GEN, false>(nr, grid, a, stream);
+      break;
+    case ADHA_OP_SUM:
+      launch_maxr<ADHA_OP_SUM, false>(nr, grid, a, stream);
+      break;
+    case ADHA_OP_MULADD3:
+      hipLaunchKernelGGL((section_kernel<ADHA_OP_MULADD3, false, 4>), grid, dim3(256), 0, stream, a);
+      break;
+    case ADHA_OP_SUB2:
+      hipLaunchKernelGGL((section_kernel<ADHA_OP_SUB2, false, 4>), grid, dim3(256), 0, stream, a);
+      break;
+    default:
+      return fail(ADHA_ERR_UNSUPPORTED, "unknown op %d", sec.op);
+  }
+  ADHA_HIP(hipGetLastError());
+  return ADHA_OK;
+}
+
+// Uniform neighbour indices in [0, n) for timing gather sections when the
+// caller supplies none: SplitMix64 of the element index, multiply-shift.
+__global__ void fill_uniform_index_kernel(int32_t *idx, uint64_t count, uint64_t n, uint64_t seed) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t z = (seed + i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    idx[i] = (int32_t)(((z >> 32) * n) >> 32);
+  }
+}
+
+adha_status fill_uniform_index(int32_t *idx, uint64_t count, int64_t n, uint64_t seed, hipStream_t stream) {
+  if (count == 0) return ADHA_OK;
+  if (n <= 0 || n > (int64_t(1) << 31)) return fail(ADHA_ERR_INVALID, "index range %lld", (long long)n);
+  const uint64_t blocks = std::min<uint64_t>((count + 255) / 256, 65536);
+  hipLaunchKernelGGL(fill_uniform_index_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, idx, count,
+                     (uint64_t)n, seed << 32);
+  ADHA_HIP(hipGetLastError());
+  return ADHA_OK;
+}
+
+}  // namespace adha

@@ -1,0 +1,43 @@
+"""Helpers shared by the GPU tests: device buffers from oracle-packed host
+images, and comparison of device results with oracle results."""
+import sys
+
+import numpy as np
+import torch
+
+from oracle.layout import Layout as OLayout
+from paper_1407_4859_amd import adha as A
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev_bytes(host: np.ndarray, extra: int = 0, fill: int = 0xA5):
+    """uint8 device tensor holding `host` (plus `extra` bytes of `fill`)."""
+    t = torch.full((max(1, host.size + extra),), fill, dtype=torch.uint8, device="cuda")
+    if host.size:
+        t[: host.size].copy_(torch.from_numpy(host))
+    return t
+
+
+def dev_empty(n: int, fill: int = 0xA5):
+    return torch.full((max(1, n),), fill, dtype=torch.uint8, device="cuda")
+
+
+def host(t, n=None):
+    a = t.cpu().numpy()
+    return a if n is None else a[:n]
+
+
+def mirror(st: A.Struct, O: OLayout) -> A.Layout:
+    """The library layout with the oracle layout's partition and tiles."""
+    gof = [O.group_of[f] for f in range(len(O.elem_bytes))]
+    tiles = [t for _, t in O.groups]
+    return A.Layout.create(st, gof, tiles)
+
+
+def first_diff(a: np.ndarray, b: np.ndarray):
+    d = np.nonzero(a != b)[0]
+    return None if d.size == 0 else (int(d[0]), int(a[d[0]]), int(b[d[0]]), int(d.size))

@@ -1,0 +1,199 @@
+"""Host-side checks of the C-ABI library (no device work): it loads, exports
+every declared symbol, and its host logic (layout address map, affinity,
+greedy clustering, shortest path, features) agrees with the oracle."""
+import ctypes
+import random
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import planner as OP
+from oracle.layout import Layout as OLayout, aos as oaos, soa as osoa
+from paper_1407_4859_amd import adha as A
+from paper_1407_4859_amd import synth
+
+
+def test_library_exports_every_declared_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", A.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    declared = A.header_symbols()
+    assert len(declared) >= 45
+    missing = [s for s in declared if s not in exported]
+    assert not missing, missing
+    lib = A.lib()
+    for s in declared:
+        assert hasattr(lib, s)
+    assert set(A._SIGS) == set(declared)
+
+
+def test_status_strings_and_version():
+    lib = A.lib()
+    assert lib.adha_status_string(0) == b"ok"
+    assert lib.adha_status_string(-1) == b"invalid argument"
+    assert lib.adha_version() >= 10000
+
+
+def _rand_layout(rng, st, eb):
+    F = len(eb)
+    ng = rng.randint(1, F)
+    gof = [rng.randrange(ng) for _ in range(F)]
+    used = {g: i for i, g in enumerate(sorted(set(gof)))}
+    gof = [used[g] for g in gof]
+    tiles = [rng.choice([1, 2, 8, 64, 256]) for _ in used]
+    return gof, tiles
+
+
+def test_layout_address_map_matches_oracle():
+    rng = random.Random(3)
+    for trial in range(40):
+        F = rng.randint(1, 12)
+        eb = [rng.choice([1, 2, 4, 8]) for _ in range(F)]
+        dts = [A.RAW] * F
+        n = rng.choice([0, 1, 63, 64, 65, 1000, 1 << 20])
+        st = A.Struct(n, dts, eb)
+        gof, tiles = _rand_layout(rng, st, eb)
+        L = A.Layout.create(st, gof, tiles)
+        O = OLayout(n, eb, gof, tiles)
+        assert L.nbytes == O.nbytes
+        g_lib, t_lib = L.groups(F)
+        assert [O.group_of[f] for f in range(F)] == g_lib
+        assert [t for _, t in O.groups] == t_lib
+        for r in sorted({r for r in (0, 1, n // 2, n - 1) if 0 <= r < n}):
+            for f in range(F):
+                assert L.addr(r, f) == O.addr(r, f)
+    st = A.Struct(10, [A.F32] * 3)
+    assert A.Layout.aos(st).nbytes == oaos(10, [4] * 3).nbytes
+    assert A.Layout.soa(st).nbytes == osoa(10, [4] * 3).nbytes
+    assert A.Layout.create(st, [1, 0, 1], [1, 1]).equals(A.Layout.create(st, [0, 1, 0], [1, 1]))
+    assert not A.Layout.aos(st).equals(A.Layout.soa(st))
+
+
+def test_remap_launch_description_covers_every_byte():
+    """The host side of a remap launch: tiles of R records (a multiple of 64
+    and of every tile), LDS within 64 KiB, and the main kernel's tiles plus
+    the tail kernel's bytes cover the destination exactly."""
+    rng = random.Random(8)
+    for trial in range(300):
+        F = rng.randint(1, 24)
+        eb = [rng.choice([1, 2, 4, 8] if trial % 4 == 3 else [4, 8]) for _ in range(F)]
+        n = rng.choice([0, 1, 63, 64, 65, 4095, 100003, 1 << 22, (1 << 26) + 5])
+        st = A.Struct(n, [A.RAW] * F, eb)
+        la, lb = (A.Layout.create(st, *_rand_layout(rng, st, eb)) for _ in range(2))
+        info = A.describe(la, lb, 256)
+        O = OLayout(n, eb, *lb.groups(F))
+        R = info["tile_records"]
+        S = sum(eb)
+        if R:
+            tmax = max(max(la.groups(F)[1]), max(lb.groups(F)[1]))
+            assert R % max(64, tmax) == 0 and R * S <= 256 * info["slots"] * 16
+            assert info["lds_bytes"] <= 65536 and info["full_tiles"] == n // R
+            assert all(e in (4, 8) for e in eb)
+        else:
+            assert info["full_tiles"] == 0
+        assert info["full_tiles"] * R * S + info["tail_bytes"] == O.nbytes or n == 0
+        if info["full_tiles"]:
+            assert 1 <= info["grid"] <= 256 * info["wg_per_cu"]
+
+
+def test_invalid_host_arguments_are_rejected():
+    with pytest.raises(A.AdhaError) as e:
+        A.Struct(-1, [A.F32])
+    assert e.value.status == A.ERR_INVALID
+    for dt, eb in ((A.F32, 8), (A.F64, 4), (A.I32, 2), (A.RAW, 3), (7, 4)):
+        with pytest.raises(A.AdhaError):
+            A.Struct(10, [dt], [eb])
+    st = A.Struct(10, [A.F32, A.F32, A.F64, A.RAW], [4, 4, 8, 2])
+    for gof, tiles in (([0, 0, 0, 0], [3]), ([0, 0, 0, 0], [512]), ([0, 1, 0, 0], [1]),
+                       ([0, 2, 2, 2], [1, 1, 1]), ([0, 0, 0, 9], [1])):
+        with pytest.raises(A.AdhaError) as e:
+            A.Layout.create(st, gof, tiles)
+        assert e.value.status == A.ERR_INVALID
+    bad_sections = [
+        (A.OP_GEN, [], [1], 0), (A.OP_GEN, [0], [], 0), (A.OP_GEN, [0, 0], [1], 0),
+        (A.OP_GEN, [0], [9], 0), (A.OP_GEN, [0, 1], [1], 4),        # gather writes what it reads
+        (A.OP_GEN, [0], [1], 33), (A.OP_MULADD3, [0, 1], [2], 0), (A.OP_SUB2, [0, 1], [2], 2),
+        (A.OP_GEN, [3], [0], 0),                                     # RAW field in a section
+        (A.OP_SUM, [0, 1], [2, 1], 0), (9, [0], [1], 0)]
+    for op, rd, wr, d in bad_sections:
+        with pytest.raises(A.AdhaError):
+            A.Section(st, op, rd, wr, d)
+    with pytest.raises(A.AdhaError):
+        A.Section(A.Struct(4, [A.I32, A.I32]), A.OP_SUM, [0], [1])  # SUM needs an fp write
+    s = A.Section(st, A.OP_GEN, [0, 2], [1], 16)
+    assert s.bytes == 10 * (4 * 16 + 16 * 12 + 4)
+    with pytest.raises(A.AdhaError):
+        A.Layout.aos(st).addr(10, 0)
+
+
+def _prog(st_spec, secs):
+    st = A.Struct.from_spec(st_spec)
+    ss = [A.Section.from_spec(st, s) for s in secs]
+    return st, ss, A.Program(st, ss)
+
+
+def test_affinity_and_ods_match_oracle():
+    rng = random.Random(4)
+    spec = synth.config3_struct(1000)
+    for seed in range(1, 9):
+        secs = synth.random_program(seed, spec.n_fields)
+        st, ss, prog = _prog(spec, secs)
+        osecs = [(s.read, s.write, s.degree) for s in secs]
+        for _ in range(6):
+            i = rng.randrange(len(secs))
+            j = rng.randrange(i, len(secs))
+            assert prog.affinity(i, j) == OP.affinity(osecs[i:j + 1], spec.n_fields)
+            cap = rng.choice([16, 24, 32, 64, 128])
+            parts = OP.ods_greedy(osecs[i:j + 1], spec.elem_bytes, cap)
+            for tile in (1, 64):
+                L = prog.ods(i, j, cap, tile)
+                O = OP.from_partition(spec.n, spec.elem_bytes, parts, tile)
+                gof, tiles = L.groups(spec.n_fields)
+                assert gof == [O.group_of[f] for f in range(spec.n_fields)]
+                assert tiles == [t for _, t in O.groups]
+
+
+def test_table3_split_through_the_library():
+    spec = synth.StructSpec(100, [synth.F32] * 32, [4] * 32)
+    st, ss, prog = _prog(spec, [synth.SectionSpec(synth.OP_GEN, list(range(31)), [31])])
+    L = prog.ods(0, 0, 32, 1)
+    gof, tiles = L.groups(32)
+    assert gof == [f // 8 for f in range(32)] and tiles == [1, 1, 1, 1]
+
+
+def test_pdl_solve_matches_oracle_and_bruteforce():
+    rng = random.Random(6)
+    for _ in range(150):
+        k, C = rng.randint(1, 5), rng.randint(1, 6)
+        T = [[float(rng.randint(0, 40)) for _ in range(C)] for _ in range(k)]
+        R = [[0.0 if a == b else float(rng.randint(0, 40)) for b in range(C)] for a in range(C)]
+        R0 = [float(rng.randint(0, 40)) for _ in range(C)]
+        for r0 in (None, R0):
+            cost, path = A.pdl_solve(T, R, r0)
+            ocost, opath = OP.pdl_dp(T, R, r0)
+            assert cost == ocost and path == opath
+            if C ** k <= 4000:
+                assert cost == OP.pdl_bruteforce(T, R, r0)[0]
+
+
+def test_analytic_plan_catalogue_matches_oracle():
+    spec = synth.config3_struct(1 << 12)
+    secs = synth.random_program(3, spec.n_fields)
+    st, ss, prog = _prog(spec, secs)
+    opts = A.plan_opts(cost=A.COST_ANALYTIC, cap_bytes=64)
+    pl = A.Plan(ctypes.c_void_p(), len(secs))
+    h = ctypes.c_void_p()
+    A.check(A.lib().adha_plan_create(None, prog.h, ctypes.byref(opts), None, 0, None, ctypes.byref(h)))
+    pl.h = h
+    osecs = [(s.read, s.write, s.degree) for s in secs]
+    cat = OP.catalogue(osecs, spec.n, spec.elem_bytes, 64, full=True)
+    assert pl.n_candidates == len(cat)
+    for c, O in enumerate(cat):
+        gof, tiles = pl.candidate(c).groups(spec.n_fields)
+        assert gof == [O.group_of[f] for f in range(spec.n_fields)]
+        assert tiles == [t for _, t in O.groups]
+    T, R = pl.tables()
+    cost, path = OP.pdl_dp(T, R)
+    assert pl.choices() == path
+    assert abs(pl.cost - cost) <= 1e-9 * cost

@@ -1,0 +1,162 @@
+"""GPU parity of the remap kernels against the oracle (bit-exact)."""
+import random
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.layout import Layout as OLayout, aos as oaos, soa as osoa
+from paper_1407_4859_amd import adha as A
+from paper_1407_4859_amd import synth
+from gpu_util import dev_bytes, dev_empty, first_diff, host, mirror, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return A.Ctx(0)
+
+
+def _rand_layout(rng, n, eb, tiles=(1, 2, 4, 64, 128, 256)):
+    F = len(eb)
+    ng = rng.randint(1, F)
+    gof = [rng.randrange(ng) for _ in range(F)]
+    used = {g: i for i, g in enumerate(sorted(set(gof)))}
+    gof = [used[g] for g in gof]
+    return OLayout(n, eb, gof, [rng.choice(tiles) for _ in used])
+
+
+def _check_remap(ctx, st, OA, OB, cols, label):
+    src_h = oracle.pack(OA, cols)
+    want = oracle.remap(OA, src_h, OB)
+    src = dev_bytes(src_h)
+    dst = dev_empty(OB.nbytes)
+    LA, LB = mirror(st, OA), mirror(st, OB)
+    say("remap", label, OA, "->", OB, "n", OA.n)
+    A.remap(ctx, LA, src, LB, dst)
+    ctx.check()
+    got = host(dst, OB.nbytes)
+    assert first_diff(got, want) is None, (label, first_diff(got, want))
+    return LA, LB, src, dst
+
+
+def test_remap_random_layouts_match_oracle(ctx):
+    rng = random.Random(21)
+    for trial in range(40):
+        F = rng.randint(1, 12)
+        byte_mode = trial % 5 == 4
+        eb = [rng.choice([1, 2, 4, 8] if byte_mode else [4, 8]) for _ in range(F)]
+        n = rng.choice([1, 2, 63, 64, 65, 511, 513, 4097, 30011])
+        st = A.Struct(n, [A.RAW] * F, eb)
+        OA, OB = _rand_layout(rng, n, eb), _rand_layout(rng, n, eb)
+        cols = [synth.field_values(trial, f, n, synth.RAW, e) for f, e in enumerate(eb)]
+        _check_remap(ctx, st, OA, OB, cols, f"trial {trial}")
+
+
+@pytest.mark.parametrize("n", [64 * 512, (1 << 16) + 77])
+def test_config2_pairs_small(ctx, n):
+    spec = synth.config2_struct(n)
+    st = A.Struct.from_spec(spec)
+    eb = spec.elem_bytes
+    gof, tiles = synth.config2_aosoa()
+    cols = synth.record_matrix(2, n, spec.dtypes, eb)
+    OA, OS, OT = oaos(n, eb), osoa(n, eb), OLayout(n, eb, gof, tiles)
+    for a, b in ((OA, OS), (OS, OA), (OA, OT), (OT, OA), (OS, OT)):
+        _check_remap(ctx, st, a, b, cols, "config2")
+
+
+def test_random_bit_patterns_nan_and_subnormals(ctx):
+    n = 5000
+    eb = [4] * 8 + [8] * 4
+    st = A.Struct(n, [A.F32] * 8 + [A.F64] * 4, eb)
+    cols = [synth.field_values(7, f, n, synth.RAW, e) for f, e in enumerate(eb)]
+    # plant NaN payloads, -0.0 and subnormals
+    cols[0][:4] = np.frombuffer(np.array([0x7FC00001, 0x80000000, 0x00000001, 0xFF800000],
+                                         np.uint32).tobytes(), np.uint8).reshape(4, 4)
+    cols[8][:2] = np.frombuffer(np.array([0x7FF0000000000001, 0x8000000000000000],
+                                         np.uint64).tobytes(), np.uint8).reshape(2, 8)
+    _check_remap(ctx, st, oaos(n, eb), osoa(n, eb), cols, "bits")
+    _check_remap(ctx, st, osoa(n, eb), OLayout(n, eb, [0] * 6 + [1] * 6, [64, 1]), cols, "bits2")
+
+
+def test_forced_tile_shapes_agree(ctx):
+    n = 20000 + 33
+    spec = synth.config3_struct(n)
+    st = A.Struct.from_spec(spec)
+    eb = spec.elem_bytes
+    cols = synth.record_matrix(3, n, spec.dtypes, eb)
+    OA = oaos(n, eb)
+    OB = OLayout(n, eb, [f // 5 for f in range(32)], [64] * 7)
+    src_h = oracle.pack(OA, cols)
+    want = oracle.remap(OA, src_h, OB)
+    src = dev_bytes(src_h)
+    LA, LB = mirror(st, OA), mirror(st, OB)
+    for R, K, shift, wg in ((64, 8, 6, 4), (128, 8, 5, 2), (64, 4, 31, 8), (192, 8, 7, 1)):
+        say("shape", R, K, shift, wg)
+        A.set_shape(ctx, LA, LB, R, K, shift, wg)
+        assert A.get_shape(ctx, LA, LB) == dict(tile_records=R, slots=K, pad_shift=shift, wg_per_cu=wg)
+        dst = dev_empty(OB.nbytes)
+        A.remap(ctx, LA, src, LB, dst)
+        ctx.check()
+        assert first_diff(host(dst, OB.nbytes), want) is None
+    with pytest.raises(A.AdhaError):
+        A.set_shape(ctx, LA, LB, 100, 8, 6, 4)        # not a multiple of 64
+    with pytest.raises(A.AdhaError):
+        A.set_shape(ctx, LA, LB, 1024, 8, 6, 4)       # more chunks than slots
+
+
+def test_empty_and_invalid(ctx):
+    st0 = A.Struct(0, [A.F32, A.F32])
+    A.remap(ctx, A.Layout.aos(st0), None, A.Layout.soa(st0), None)
+    st = A.Struct(1000, [A.F32, A.I32])
+    La, Ls = A.Layout.aos(st), A.Layout.soa(st)
+    buf = torch.zeros(1 << 16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(A.AdhaError):                     # overlap
+        A.remap(ctx, La, buf[:8192], Ls, buf[4096:])
+    with pytest.raises(A.AdhaError):                     # capacity
+        A.remap(ctx, La, buf[:100], Ls, buf[8192:])
+    with pytest.raises(A.AdhaError):                     # misaligned
+        A.remap(ctx, La, buf[16:], Ls, buf[16384:])
+    other = A.Layout.soa(A.Struct(1000, [A.F32, A.F32]))
+    with pytest.raises(A.AdhaError):                     # different struct
+        A.remap(ctx, La, buf[:8192], other, buf[16384:])
+    ctx.check()
+
+
+def test_config2_full_size_sampled_and_round_trip(ctx):
+    n = 1 << 26
+    spec = synth.config2_struct(n)
+    st = A.Struct.from_spec(spec)
+    eb = spec.elem_bytes
+    OA, OS = oaos(n, eb), osoa(n, eb)
+    gof, tiles = synth.config2_aosoa()
+    OT = OLayout(n, eb, gof, tiles)
+    LA, LS, LT = mirror(st, OA), mirror(st, OS), mirror(st, OT)
+    say("config2 full: generating", n, "records")
+    src = torch.empty(OA.nbytes, dtype=torch.uint8, device="cuda")
+    view = src.view(n, 64)
+    chunk = 1 << 24
+    for f in range(16):
+        for s in range(0, n, chunk):
+            z = synth.splitmix64_torch(2, f, s, chunk, "cuda")
+            view[s:s + chunk, 4 * f:4 * f + 4] = synth.decode_torch(z, spec.dtypes[f])
+    dst = torch.empty(max(OS.nbytes, OT.nbytes), dtype=torch.uint8, device="cuda")
+    back = torch.empty(OA.nbytes, dtype=torch.uint8, device="cuda")
+    rng = np.random.default_rng(0)
+    recs = np.unique(np.concatenate([rng.integers(0, n, 4000), [0, 1, n - 1, n - 64, n // 2]]))
+    for OB, LB in ((OS, LS), (OT, LT)):
+        say("config2 full: AoS ->", OB)
+        A.remap(ctx, LA, src, LB, dst[: OB.nbytes])
+        ctx.check()
+        dh = dst[: OB.nbytes]
+        for f in range(16):
+            want = np.stack([synth.field_values(2, f, 1, spec.dtypes[f], 4, start=int(r))[0]
+                             for r in recs[:200]])
+            addr = torch.from_numpy(OB.addr_vec(recs[:200], f)).cuda()
+            got = torch.stack([dh[addr + b] for b in range(4)], 1).cpu().numpy()
+            assert np.array_equal(got, want), f
+        A.remap(ctx, LB, dh, LA, back)
+        ctx.check()
+        assert torch.equal(back, src)
