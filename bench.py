@@ -1,0 +1,336 @@
+"""Benchmark of the layout-remap / section hot path on one MI355X.
+
+One step = the three remaps of the single-remap workload on N = 2^26
+records of 16 four-byte fields (64-byte records, 4 GiB per layout):
+AoS -> SoA, SoA -> AoS and AoS -> AoSoA with groups {0-3}, {4-7}, {8-15}
+tiled by 64 records.  `value` is the step's algorithmic bytes (each remap
+reads and writes every record once: 2 * N * 64 bytes) over its time.
+
+Besides the timed steps the run reports (outside the timed region):
+  roofline      the remap kernel's achieved GB/s against 8 TB/s, from HIP
+                events on the launch stream;
+  cpu_baseline  the CPU oracle's remap on a bounded sample;
+  program       the multi-section workload (N = 2^24, 32 fields, 8 sections,
+                4 of them 16-neighbour gathers): program time under the
+                planned layouts vs all-AoS and all-SoA, per-kernel GB/s;
+  batched       the 512-array batched remap: one graph launch vs one launch
+                per array;
+  learned       (with --learned) the cost model: planned program time with
+                learned costs vs measured enumeration, over seeded programs.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2n", type=int, default=26, help="records of the single-remap workload")
+    ap.add_argument("--program-log2n", type=int, default=24)
+    ap.add_argument("--skip-program", action="store_true")
+    ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--learned", action="store_true")
+    ap.add_argument("--only-remap", action="store_true", help="timed steps only (for profiling)")
+    return ap.parse_args()
+
+
+def fill_fields(buf, spec, layout_o, seed, torch, synth):
+    """Write the seeded field values of every record into a device buffer laid
+    out as AoS (layout_o is the oracle's AoS layout, used only for offsets)."""
+    n = spec.n
+    S = spec.record_bytes
+    view = buf[: n * S].view(n, S)
+    chunk = 1 << 24
+    off = 0
+    for f, (dt, e) in enumerate(zip(spec.dtypes, spec.elem_bytes)):
+        for s in range(0, n, chunk):
+            c = min(chunk, n - s)
+            z = synth.splitmix64_torch(seed, f, s, c, "cuda")
+            view[s:s + c, off:off + e] = synth.decode_torch(z, dt, e)
+        off += e
+
+
+class Timer:
+    """HIP-event timing on torch's current stream (the stream the library's
+    kernels are launched on)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+
+    def time(self, fn, reps=5, warm=1):
+        t = self.torch
+        for _ in range(warm):
+            fn()
+        ts = []
+        for _ in range(reps):
+            a, b = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        ts.sort()
+        return ts[len(ts) // 2], ts
+
+
+def cpu_baseline(synth):
+    """The oracle's AoS -> SoA remap of the same struct (2^26 records),
+    split over the host's cores by record ranges."""
+    import oracle
+    from oracle.layout import aos, soa
+    n = 1 << 26
+    spec = synth.config2_struct(n)
+    eb = spec.elem_bytes
+    La, Ls = aos(n, eb), soa(n, eb)
+    rng = np.random.default_rng(2)
+    src = rng.integers(0, 1 << 63, La.nbytes // 8, dtype=np.uint64).view(np.uint8)
+    dst = np.zeros(Ls.nbytes, np.uint8)
+    cores = os.cpu_count() or 1
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    sd, dd = np.ascontiguousarray(La.desc()), np.ascontiguousarray(Ls.desc())
+    lib = oracle.lib()
+    p = oracle._p
+    bounds = [n * i // cores for i in range(cores + 1)]
+
+    def part(i):
+        lib.orc_remap(16, p(sd), p(src), p(dd), p(dst), bounds[i], bounds[i + 1])
+
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(cores) as ex:
+            list(ex.map(part, range(cores)))
+        ts.append(time.perf_counter() - t0)
+    t = sorted(ts)[1]
+    return {"value": round(2 * n * 64 / t / 1e9, 3), "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "sample": f"AoS->SoA remap of all 2^26 records x 64 B (8 GiB moved), median of 3, "
+                      f"{cores} threads over record ranges; {t * 1e3:.0f} ms"}
+
+
+def program_bench(A, synth, torch, timer, log2n):
+    n = 1 << log2n
+    spec = synth.config3_struct(n)
+    st = A.Struct.from_spec(spec)
+    secs = synth.random_program(3, spec.n_fields)
+    ss = [A.Section.from_spec(st, s) for s in secs]
+    prog = A.Program(st, ss)
+    aos_l, soa_l = A.Layout.aos(st), A.Layout.soa(st)
+    log("program: filling", n, "records")
+    cap = max(aos_l.nbytes, soa_l.nbytes) + (1 << 26)
+    buf_a = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    buf_b = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    from oracle.layout import aos as oaos
+    fill_fields(buf_a, spec, oaos(n, spec.elem_bytes), 3, torch, synth)
+    idx = synth.uniform_index_torch(3, 999, n * 16, n, "cuda")
+    ctx = A.Ctx(0)
+    log("program: planning (measured costs)")
+    t0 = time.perf_counter()
+    plan = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_MEASURED, catalogue=A.CAT_FULL, cap_bytes=64, reps=3),
+                         idx=idx)
+    plan_s = time.perf_counter() - t0
+    analytic = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_ANALYTIC, catalogue=A.CAT_FULL, cap_bytes=64))
+    plans = {"adha": plan, "all_aos": A.Plan.uniform(prog, aos_l), "all_soa": A.Plan.uniform(prog, soa_l),
+             "adha_analytic": analytic}
+    out = {"workload": f"N=2^{log2n} records, 32 fields (20 f32, 8 i32, 4 f64; 144 B), 8 GEN sections "
+                       f"(seed 3), 4 gathering 16 uniform neighbours",
+           "candidates": plan.n_candidates, "plan_seconds": round(plan_s, 2)}
+    for name, pl in plans.items():
+        first = pl.candidate(pl.choices()[0])
+        def go(pl=pl, first=first):
+            A.run(ctx, pl, first, buf_a, buf_b, idx)
+        ms, _ = timer.time(go, reps=5, warm=1)
+        out[name + "_ms"] = round(ms, 3)
+        out[name + "_choices"] = pl.choices()
+    ctx.check()
+    best_base = min(out["all_aos_ms"], out["all_soa_ms"])
+    out["speedup_vs_best_uniform"] = round(best_base / out["adha_ms"], 3)
+    out["adha_beats_both"] = out["adha_ms"] < best_base
+    out["predicted_adha_ms"] = round(plan.cost / 1e3, 3)
+    # per-section kernel GB/s under the chosen layouts
+    per = []
+    T, _ = plan.tables()
+    for s, (sec, c) in enumerate(zip(ss, plan.choices())):
+        t_us = T[s][c]
+        per.append({"section": s, "degree": secs[s].degree, "read": len(secs[s].read),
+                    "write": len(secs[s].write), "layout": c, "us": round(t_us, 1),
+                    "alg_GBps": round(sec.bytes / (t_us * 1e3), 1)})
+    out["sections"] = per
+    return out
+
+
+def batched_bench(A, synth, torch, timer):
+    arrs = synth.config4_arrays()
+    ctx = A.Ctx(0)
+    items, keep = [], []
+    total = 0
+    log("batched: allocating", len(arrs), "arrays")
+    for a in arrs:
+        st = A.Struct(a["n"], [A.RAW] * len(a["elem_bytes"]), a["elem_bytes"])
+        la = A.Layout.aos(st)
+        lb = A.Layout.create(st, a["target_gof"], a["target_tiles"])
+        src = torch.empty(la.nbytes, dtype=torch.uint8, device="cuda")
+        src.random_(0, 256)
+        dst = torch.empty(lb.nbytes, dtype=torch.uint8, device="cuda")
+        items.append((la, src, lb, dst))
+        keep.append(st)
+        total += 2 * a["n"] * sum(a["elem_bytes"])
+    g_ms, _ = timer.time(lambda: A.remap_batched(ctx, items, A.BATCH_GRAPH), reps=5, warm=2)
+    b_ms, _ = timer.time(lambda: A.remap_batched(ctx, items, 0), reps=5, warm=1)
+    s_ms, _ = timer.time(lambda: A.remap_batched(ctx, items, A.BATCH_SEPARATE), reps=5, warm=1)
+    ctx.check()
+    return {"workload": "512 arrays, N log-uniform in [2^10, 2^22], 4-24 fields of 4 or 8 bytes, AoS -> SoA "
+                        "or AoSoA (groups of 2-8, 64-record tiles), seed 4",
+            "algorithmic_bytes": total, "graph_ms": round(g_ms, 3), "persistent_ms": round(b_ms, 3),
+            "separate_launches_ms": round(s_ms, 3), "graph_GBps": round(total / g_ms / 1e6, 1),
+            "separate_GBps": round(total / s_ms / 1e6, 1),
+            "graph_frac_of_peak": round(total / g_ms / 1e6 / HBM_PEAK_GBS, 3)}
+
+
+def learned_bench(A, synth, torch):
+    ctx = A.Ctx(0)
+    rep = A.costmodel_train(ctx, A.train_opts(n_samples=4000, epochs=400, min_log2_n=16, max_log2_n=22))
+    ratios, plan_t = [], {"learned": 0.0, "measured": 0.0}
+    for seed in range(100, 108):
+        n = 1 << (20 + seed % 3)
+        spec = synth.config3_struct(n)
+        st = A.Struct.from_spec(spec)
+        ss = [A.Section.from_spec(st, s) for s in synth.random_program(seed, 32)]
+        prog = A.Program(st, ss)
+        idx = synth.uniform_index_torch(seed, 999, n * 16, n, "cuda")
+        pl_m = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_MEASURED, reps=3), idx=idx)
+        pl_l = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_LEARNED), idx=idx)
+        plan_t["learned"] += pl_l.seconds
+        plan_t["measured"] += pl_m.seconds
+        T, R = pl_m.tables()
+        from oracle.planner import path_cost
+        ratios.append(path_cost(T, R, pl_l.choices()) / pl_m.cost)
+    return {"train": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.items()},
+            "programs": len(ratios), "mean_ratio": round(float(np.mean(ratios)), 4),
+            "max_ratio": round(float(np.max(ratios)), 4),
+            "plan_seconds_learned": round(plan_t["learned"], 2),
+            "plan_seconds_measured": round(plan_t["measured"], 2)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
+              "documented but not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1407_4859_amd import adha as A
+    from paper_1407_4859_amd import synth
+    from oracle.layout import aos as oaos, soa as osoa, Layout as OLayout
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    timer = Timer(torch)
+    n = 1 << args.log2n
+    spec = synth.config2_struct(n)
+    st = A.Struct.from_spec(spec)
+    gof, tiles = synth.config2_aosoa()
+    La, Ls, Lt = A.Layout.aos(st), A.Layout.soa(st), A.Layout.create(st, gof, tiles)
+    ctx = A.Ctx(0)
+    log("single remap: filling", n, "records")
+    a = torch.empty(La.nbytes, dtype=torch.uint8, device="cuda")
+    fill_fields(a, spec, oaos(n, spec.elem_bytes), 2, torch, synth)
+    s = torch.empty(Ls.nbytes, dtype=torch.uint8, device="cuda")
+    t = torch.empty(Lt.nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(La.nbytes, dtype=torch.uint8, device="cuda")
+    pairs = [("aos_to_soa", La, a, Ls, s), ("soa_to_aos", Ls, s, La, b), ("aos_to_aosoa", La, a, Lt, t)]
+    step_bytes = 3 * 2 * n * spec.record_bytes
+
+    def step():
+        for _, sl, sb, dl, db in pairs:
+            A.remap(ctx, sl, sb, dl, db)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.check()
+    # per-launch timing of the dominant kernel with HIP events on its stream
+    per = {}
+    for name, sl, sb, dl, db in pairs:
+        ms, _ = timer.time(lambda: A.remap(ctx, sl, sb, dl, db), reps=10, warm=1)
+        per[name] = {"ms": round(ms, 4), "GBps": round(2 * n * 64 / ms / 1e6, 1),
+                     "frac": round(2 * n * 64 / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    log("per remap:", per)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.check()
+    ms_step = dt / args.steps * 1e3
+    value = step_bytes / (dt / args.steps) / 1e9
+    avg_ms = float(np.mean([p["ms"] for p in per.values()]))
+    achieved = 2 * n * 64 / (avg_ms * 1e-3) / 1e9
+    line = {
+        "metric": "remap+section GB/s (% HBM peak); program time ADHA vs all-AoS/all-SoA",
+        "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "single remap: N=2^%d records of 16 x 4-byte fields (8 f32, 8 i32); "
+                               "AoS->SoA, SoA->AoS, AoS->AoSoA {0-3},{4-7},{8-15} x64 per step" % args.log2n,
+                   "records": n, "record_bytes": 64, "bytes_per_step": step_bytes},
+        "frac_of_peak": round(value / HBM_PEAK_GBS, 4),
+        "remaps": per,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "remap_tiles_kernel<8>",
+                     "per_launch_bytes": 2 * n * 64},
+    }
+    if not args.only_remap:
+        if not args.skip_cpu:
+            log("cpu baseline")
+            line["cpu_baseline"] = cpu_baseline(synth)
+        del a, s, t, b
+        torch.cuda.empty_cache()
+        if not args.skip_program:
+            try:
+                line["program"] = program_bench(A, synth, torch, timer, args.program_log2n)
+            except Exception as e:  # report, keep the main line
+                line["program"] = {"error": repr(e)}
+            torch.cuda.empty_cache()
+        if not args.skip_batched:
+            try:
+                line["batched"] = batched_bench(A, synth, torch, timer)
+            except Exception as e:
+                line["batched"] = {"error": repr(e)}
+            torch.cuda.empty_cache()
+        if args.learned:
+            try:
+                line["learned"] = learned_bench(A, synth, torch)
+            except Exception as e:
+                line["learned"] = {"error": repr(e)}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -183,6 +183,8 @@ typedef struct {
   uint32_t slots;
   uint32_t pad_shift;
   uint32_t wg_per_cu;
+  uint32_t order;       /* 1: contiguous tile ranges per workgroup, 2: strided */
+  uint32_t nontemporal; /* 1: ordinary accesses, 2: streaming (non-temporal) */
 } adha_tile_shape;
 /* Force a tile shape for subsequent remaps of this layout pair (tests and
  * the autotuner).  Invalid shapes are rejected with ERR_INVALID. */
@@ -204,6 +206,26 @@ typedef struct {
 } adha_remap_info;
 adha_status adha_remap_describe(const adha_layout *src_l, const adha_layout *dst_l, int32_t cu_count,
                                 adha_remap_info *out);
+
+/* Autotuner.  Times candidate tile shapes (records per tile, workgroups per
+ * CU, tile order, streaming accesses) on the caller's buffers, keeps the
+ * fastest for this pair and for every pair of the same class (layout kinds,
+ * record bytes, largest tile, element sizes, log2 N) in the context's tuning
+ * database, and reports it with its time and the default shape's time
+ * (microseconds, median of reps).  dst is overwritten. */
+adha_status adha_tune_remap(adha_ctx *ctx, const adha_layout *src_l, const void *src, uint64_t src_cap,
+                            const adha_layout *dst_l, void *dst, uint64_t dst_cap, uint32_t reps,
+                            void *stream, adha_tile_shape *best, double *best_us, double *default_us);
+/* Tunes the batch policy used by adha_remap_batched (bytes per tile,
+ * workgroups per CU, order, streaming) on the given items. */
+adha_status adha_tune_batched(adha_ctx *ctx, uint32_t n, const adha_remap_item *items, uint32_t reps,
+                              void *stream, uint32_t *tile_bytes, adha_tile_shape *best, double *best_us,
+                              double *default_us);
+/* Tuning database as text (one entry per line, versioned header and
+ * checksum).  Loading a missing or corrupt file returns ERR_IO and leaves
+ * the context's database unchanged. */
+adha_status adha_tune_save(const adha_ctx *ctx, const char *path);
+adha_status adha_tune_load(adha_ctx *ctx, const char *path);
 
 /* ------------------------------------------------------------ sections */
 /* A section (section 2: one data-parallel loop) reading n_read fields and

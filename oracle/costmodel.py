@@ -1,0 +1,105 @@
+"""Oracle: the analytic cost model and the cost-model features.  TEST
+INFRASTRUCTURE ONLY.
+
+The paper weights its shortest path with a profile of section times (section
+2, third paragraph) and does not say how a profile would be predicted.  The
+analytic model below is the "method without the learned part": it prices a
+section under a layout by the HBM bytes the layout makes it move.
+
+Effective bytes per record of a section under a layout, with a DRAM access
+granule g = 64 bytes:
+  * streaming access to group G (direct sections, and every write):
+    min(S_G, sum over touched fields f of max(e_f, g / T_G));
+  * random access to group G (the reads of a gather, per neighbour): an
+    interleaved multi-field group costs span + g - 1 where span runs from the
+    first to the end of the last touched field of the record; any other
+    group costs sum over touched fields of (e_f + g - 1);
+  * a gather also reads its 4*d index bytes.
+Time = 4 us + N * bytes / (5.6e6 bytes per us); a remap between different
+layouts costs 4 us + 2 * N * S / 5.6e6.
+
+Features (16 values, float32, fixed scaling):
+  log2 N / 24, |R| / 16, |W| / 2, d / 32, log2(1 + read bytes) / 8,
+  log2(1 + write bytes) / 8, 4-byte reads / 16, 8-byte reads / 16,
+  4-byte writes / 2, 8-byte writes / 2, one-hot layout class (AoS, SoA,
+  tiled, grouped), groups touched / 16, log2(effective bytes) / 12.
+Layout classes: one interleaved group = AoS; one tiled group = tiled; only
+one-field groups = SoA; otherwise tiled if any group is tiled, else grouped.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+GRANULE = 64.0
+BYTES_PER_US = 5.6e6
+LAUNCH_US = 4.0
+
+
+def _stream_bytes(L, gi, touched):
+    fields, T = L.groups[gi]
+    b = 0.0
+    for f in touched:
+        if L.group_of[f] == gi:
+            b += max(float(L.elem_bytes[f]), GRANULE / T)
+    return min(b, float(L.S[gi]))
+
+
+def _random_bytes(L, gi, touched):
+    fields, T = L.groups[gi]
+    mine = [f for f in touched if L.group_of[f] == gi]
+    if not mine:
+        return 0.0
+    if T == 1 and len(fields) > 1:
+        lo = min(L.p[f] for f in mine)
+        hi = max(L.p[f] + L.elem_bytes[f] for f in mine)
+        return (hi - lo) + GRANULE - 1.0
+    return sum(L.elem_bytes[f] + GRANULE - 1.0 for f in mine)
+
+
+def bytes_per_record(read, write, degree, L) -> float:
+    b = 0.0
+    for gi in range(len(L.groups)):
+        if degree == 0:
+            b += _stream_bytes(L, gi, read)
+        else:
+            b += degree * _random_bytes(L, gi, read)
+        b += _stream_bytes(L, gi, write)
+    if degree:
+        b += 4.0 * degree
+    return b
+
+
+def section_us(read, write, degree, L) -> float:
+    return LAUNCH_US + L.n * bytes_per_record(read, write, degree, L) / BYTES_PER_US
+
+
+def remap_us(La, Lb) -> float:
+    if La.key() == Lb.key():
+        return 0.0
+    return LAUNCH_US + 2.0 * La.n * sum(La.elem_bytes) / BYTES_PER_US
+
+
+def layout_class(L) -> int:
+    if len(L.groups) == 1:
+        return 0 if L.groups[0][1] == 1 else 2
+    if all(len(fs) == 1 for fs, _ in L.groups):
+        return 1
+    return 2 if any(t > 1 for _, t in L.groups) else 3
+
+
+def features(read, write, degree, L, spec=None):
+    eb = L.elem_bytes
+    rb = sum(eb[f] for f in read)
+    wb = sum(eb[f] for f in write)
+    cls = layout_class(L)
+    groups = {L.group_of[f] for f in list(read) + list(write)}
+    v = [math.log2(max(1, L.n)) / 24.0, len(read) / 16.0, len(write) / 2.0, degree / 32.0,
+         math.log2(1.0 + rb) / 8.0, math.log2(1.0 + wb) / 8.0,
+         sum(1 for f in read if eb[f] != 8) / 16.0, sum(1 for f in read if eb[f] == 8) / 16.0,
+         sum(1 for f in write if eb[f] != 8) / 2.0, sum(1 for f in write if eb[f] == 8) / 2.0,
+         float(cls == 0), float(cls == 1), float(cls == 2), float(cls == 3),
+         len(groups) / 16.0,
+         math.log2(max(1.0, bytes_per_record(read, write, degree, L))) / 12.0]
+    return np.array(v, np.float64).astype(np.float32)

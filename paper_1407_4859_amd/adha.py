@@ -38,7 +38,8 @@ class AdhaError(RuntimeError):
 
 class TileShape(ctypes.Structure):
     _fields_ = [("tile_records", ctypes.c_uint32), ("slots", ctypes.c_uint32),
-                ("pad_shift", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32)]
+                ("pad_shift", ctypes.c_uint32), ("wg_per_cu", ctypes.c_uint32),
+                ("order", ctypes.c_uint32), ("nontemporal", ctypes.c_uint32)]
 
 
 class RemapItem(ctypes.Structure):
@@ -97,6 +98,12 @@ _SIGS = {
     "adha_remap_set_shape": ([P, P, P, ctypes.POINTER(TileShape)], I32T),
     "adha_remap_get_shape": ([P, P, P, ctypes.POINTER(TileShape)], I32T),
     "adha_remap_describe": ([P, P, I32T, ctypes.POINTER(RemapInfo)], I32T),
+    "adha_tune_remap": ([P, P, P, U64, P, P, U64, U32, P, ctypes.POINTER(TileShape), ctypes.POINTER(DBL),
+                         ctypes.POINTER(DBL)], I32T),
+    "adha_tune_batched": ([P, U32, P, U32, P, ctypes.POINTER(U32), ctypes.POINTER(TileShape),
+                           ctypes.POINTER(DBL), ctypes.POINTER(DBL)], I32T),
+    "adha_tune_save": ([P, ctypes.c_char_p], I32T),
+    "adha_tune_load": ([P, ctypes.c_char_p], I32T),
     "adha_section_create": ([P, ctypes.c_int, U32, P, U32, P, U32, PP], I32T),
     "adha_section_destroy": ([P], I32T),
     "adha_section_run": ([P, P, P, P, U64, P, U64, P], I32T),
@@ -427,23 +434,64 @@ def remap(ctx: Ctx, src_l: Layout, src, dst_l: Layout, dst, stream=None):
 
 
 def remap_batched(ctx: Ctx, items, flags: int = 0, stream=None):
-    arr = (RemapItem * max(1, len(items)))()
-    for i, (sl, s, dl, d) in enumerate(items):
-        sp, sc = _dev(s)
-        dp, dc = _dev(d)
-        arr[i] = RemapItem(sl.h.value, sp.value, sc, dl.h.value, dp.value, dc)
+    """items: (src layout, src tensor, dst layout, dst tensor) tuples."""
+    arr = _items(items)
     check(lib().adha_remap_batched(ctx.h, len(items), arr, flags, stream_ptr(stream)))
 
 
-def set_shape(ctx: Ctx, src_l: Layout, dst_l: Layout, tile_records=0, slots=0, pad_shift=0, wg_per_cu=0):
-    s = TileShape(tile_records, slots, pad_shift, wg_per_cu)
+def set_shape(ctx: Ctx, src_l: Layout, dst_l: Layout, tile_records=0, slots=0, pad_shift=0, wg_per_cu=0,
+              order=0, nontemporal=0):
+    """Force a tile shape (0 = automatic; order 1 contiguous / 2 strided;
+    nontemporal 1 off / 2 on)."""
+    s = TileShape(tile_records, slots, pad_shift, wg_per_cu, order, nontemporal)
     check(lib().adha_remap_set_shape(ctx.h, src_l.h, dst_l.h, ctypes.byref(s)))
 
 
 def get_shape(ctx: Ctx, src_l: Layout, dst_l: Layout) -> dict:
     s = TileShape()
     check(lib().adha_remap_get_shape(ctx.h, src_l.h, dst_l.h, ctypes.byref(s)))
-    return dict(tile_records=s.tile_records, slots=s.slots, pad_shift=s.pad_shift, wg_per_cu=s.wg_per_cu)
+    return dict(tile_records=s.tile_records, slots=s.slots, pad_shift=s.pad_shift, wg_per_cu=s.wg_per_cu,
+                order=s.order, nontemporal=s.nontemporal)
+
+
+def _shape_dict(s: TileShape) -> dict:
+    return dict(tile_records=s.tile_records, slots=s.slots, pad_shift=s.pad_shift, wg_per_cu=s.wg_per_cu,
+                order=s.order, nontemporal=s.nontemporal)
+
+
+def tune_remap(ctx: Ctx, src_l: Layout, src, dst_l: Layout, dst, reps: int = 3, stream=None) -> dict:
+    """Autotunes the pair's tile shape on these buffers (dst is overwritten)."""
+    sp, sc = _dev(src)
+    dp, dc = _dev(dst)
+    best, bt, dt = TileShape(), ctypes.c_double(), ctypes.c_double()
+    check(lib().adha_tune_remap(ctx.h, src_l.h, sp, sc, dst_l.h, dp, dc, reps, stream_ptr(stream),
+                                ctypes.byref(best), ctypes.byref(bt), ctypes.byref(dt)))
+    return dict(shape=_shape_dict(best), best_us=bt.value, default_us=dt.value)
+
+
+def _items(items):
+    arr = (RemapItem * max(1, len(items)))()
+    for i, (sl, s, dl, d) in enumerate(items):
+        sp, sc = _dev(s)
+        dp, dc = _dev(d)
+        arr[i] = RemapItem(sl.h.value, sp.value if sp else None, sc, dl.h.value, dp.value if dp else None, dc)
+    return arr
+
+
+def tune_batched(ctx: Ctx, items, reps: int = 3, stream=None) -> dict:
+    arr = _items(items)
+    tb, best, bt, dt = ctypes.c_uint32(), TileShape(), ctypes.c_double(), ctypes.c_double()
+    check(lib().adha_tune_batched(ctx.h, len(items), arr, reps, stream_ptr(stream), ctypes.byref(tb),
+                                  ctypes.byref(best), ctypes.byref(bt), ctypes.byref(dt)))
+    return dict(tile_bytes=tb.value, shape=_shape_dict(best), best_us=bt.value, default_us=dt.value)
+
+
+def tune_save(ctx: Ctx, path: str):
+    check(lib().adha_tune_save(ctx.h, path.encode()))
+
+
+def tune_load(ctx: Ctx, path: str):
+    check(lib().adha_tune_load(ctx.h, path.encode()))
 
 
 def describe(src_l: Layout, dst_l: Layout, cu_count: int = 256) -> dict:
@@ -452,7 +500,7 @@ def describe(src_l: Layout, dst_l: Layout, cu_count: int = 256) -> dict:
     check(lib().adha_remap_describe(src_l.h, dst_l.h, cu_count, ctypes.byref(r)))
     out = {k: getattr(r, k) for k, _ in RemapInfo._fields_ if k != "shape"}
     out.update(tile_records=r.shape.tile_records, slots=r.shape.slots, pad_shift=r.shape.pad_shift,
-               wg_per_cu=r.shape.wg_per_cu)
+               wg_per_cu=r.shape.wg_per_cu, order=r.shape.order, nontemporal=r.shape.nontemporal)
     return out
 
 

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libadha.so")
-SOURCES = ["layout.cpp", "abi.cpp", "plan.cpp", "costmodel.cpp",
+SOURCES = ["layout.cpp", "abi.cpp", "plan.cpp", "costmodel.cpp", "tune.cpp",
            "remap.hip", "section.hip", "mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -53,9 +53,9 @@ static adha_status flush_cache(Ctx *ctx) {
 
 // Cached remap launch for one (src layout, dst layout, shape); pointers are
 // passed at run time.
-static adha_status prepared_for(Ctx *ctx, const adha_layout *a, const adha_layout *b,
+adha_status prepared_for(Ctx *ctx, const adha_layout *a, const adha_layout *b,
                                 const TileShape &sh, const RemapPrepared **out) {
-  std::vector<uint64_t> key{1, a->id, b->id, sh.R, sh.K, sh.shift, sh.wg_per_cu};
+  std::vector<uint64_t> key{1, a->id, b->id, sh.R, sh.K, sh.shift, sh.wg_per_cu, sh.strided, sh.nt};
   auto it = ctx->remap_cache.find(key);
   if (it == ctx->remap_cache.end()) {
     if (ctx->remap_cache.size() >= kCacheLimit) ADHA_TRY(flush_cache(ctx));
@@ -67,7 +67,7 @@ static adha_status prepared_for(Ctx *ctx, const adha_layout *a, const adha_layou
   return ADHA_OK;
 }
 
-static adha_status shape_for(Ctx *ctx, const adha_layout *a, const adha_layout *b, TileShape *sh) {
+adha_status shape_for(Ctx *ctx, const adha_layout *a, const adha_layout *b, TileShape *sh) {
   auto it = ctx->forced_shapes.find({a->id, b->id});
   if (it != ctx->forced_shapes.end()) {
     *sh = it->second;
@@ -76,7 +76,27 @@ static adha_status shape_for(Ctx *ctx, const adha_layout *a, const adha_layout *
   return choose_shape(ctx, a->d, b->d, sh);
 }
 
-static adha_status validate_remap(const adha_layout *sl, const void *src, uint64_t src_cap,
+// Shape of one array inside a batched launch: the context's batch policy
+// (tile bytes, workgroups per CU, order, streaming) unless the pair was forced.
+static adha_status batch_shape_for(Ctx *ctx, const adha_layout *a, const adha_layout *b, TileShape *sh) {
+  auto it = ctx->forced_shapes.find({a->id, b->id});
+  if (it != ctx->forced_shapes.end()) {
+    *sh = it->second;
+    return ADHA_OK;
+  }
+  return policy_shape(a->d, b->d, ctx->batch.tile_bytes, ctx->batch.wg_per_cu, ctx->batch.strided,
+                      ctx->batch.nt, sh);
+}
+
+adha_status remap_with_shape(Ctx *ctx, const adha_layout *sl, const void *src, const adha_layout *dl,
+                             void *dst, const TileShape &sh, hipStream_t stream) {
+  if (sl->d.shape.n == 0 || dl->d.nbytes == 0) return ADHA_OK;
+  const RemapPrepared *p = nullptr;
+  ADHA_TRY(prepared_for(ctx, sl, dl, sh, &p));
+  return remap_run(ctx, *p, src, dst, stream);
+}
+
+adha_status validate_remap(const adha_layout *sl, const void *src, uint64_t src_cap,
                                   const adha_layout *dl, const void *dst, uint64_t dst_cap) {
   if (!sl || !dl) return fail(ADHA_ERR_INVALID, "layout is NULL");
   if (!sl->d.shape.same(dl->d.shape))
@@ -313,6 +333,9 @@ adha_status adha_remap_set_shape(adha_ctx *ctx, const adha_layout *src_l, const 
   s.K = shape->slots ? shape->slots : d.K;
   s.shift = shape->pad_shift ? shape->pad_shift : d.shift;
   s.wg_per_cu = shape->wg_per_cu ? shape->wg_per_cu : d.wg_per_cu;
+  if (shape->order > 2 || shape->nontemporal > 2) return fail(ADHA_ERR_INVALID, "order / nontemporal not in {0, 1, 2}");
+  s.strided = shape->order ? shape->order - 1 : d.strided;
+  s.nt = shape->nontemporal ? shape->nontemporal - 1 : d.nt;
   if (s.R != 0) {
     if (!src_l->d.dword_fields()) return fail(ADHA_ERR_UNSUPPORTED, "1- and 2-byte fields use the tail path only");
     ADHA_TRY(check_shape(src_l->d, dst_l->d, s));
@@ -330,6 +353,8 @@ adha_status adha_remap_get_shape(adha_ctx *ctx, const adha_layout *src_l, const 
   out->slots = s.K;
   out->pad_shift = s.shift;
   out->wg_per_cu = s.wg_per_cu;
+  out->order = s.strided + 1;
+  out->nontemporal = s.nt + 1;
   return ADHA_OK;
 }
 
@@ -348,6 +373,8 @@ adha_status adha_remap_describe(const adha_layout *src_l, const adha_layout *dst
   out->shape.slots = s.K;
   out->shape.pad_shift = s.shift;
   out->shape.wg_per_cu = s.wg_per_cu;
+  out->shape.order = s.strided + 1;
+  out->shape.nontemporal = s.nt + 1;
   out->full_tiles = p.main_tiles;
   out->tail_bytes = p.tail_bytes;
   out->descriptor_bytes = p.desc_bytes;
@@ -375,8 +402,13 @@ adha_status adha_remap_batched(adha_ctx *ctx, uint32_t n, const adha_remap_item 
         return fail(ADHA_ERR_INVALID, "items %u and %u overlap", i, j);
     }
   DeviceGuard g(ctx->c.device);
-  Ctx *c = &ctx->c;
-  hipStream_t st = (hipStream_t)stream;
+  return batch_run(&ctx->c, n, items, flags, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// Batched remap of validated items under the context's batch policy.
+adha_status adha::batch_run(Ctx *c, uint32_t n, const adha_remap_item *items, uint32_t flags, hipStream_t st) {
   if (flags & ADHA_BATCH_SEPARATE) {
     for (uint32_t i = 0; i < n; ++i)
       ADHA_TRY(remap_one(c, items[i].src_layout, items[i].src, items[i].dst_layout, items[i].dst, st));
@@ -391,7 +423,7 @@ adha_status adha_remap_batched(adha_ctx *ctx, uint32_t n, const adha_remap_item 
     const adha_remap_item &it = items[i];
     if (it.src_layout->d.shape.n == 0 || it.dst_layout->d.nbytes == 0) continue;
     TileShape sh;
-    ADHA_TRY(shape_for(c, it.src_layout, it.dst_layout, &sh));
+    ADHA_TRY(batch_shape_for(c, it.src_layout, it.dst_layout, &sh));
     sl.push_back(&it.src_layout->d);
     dl.push_back(&it.dst_layout->d);
     sp.push_back(it.src);
@@ -399,12 +431,16 @@ adha_status adha_remap_batched(adha_ctx *ctx, uint32_t n, const adha_remap_item 
     shapes.push_back(sh);
     for (uint64_t v : {it.src_layout->id, it.dst_layout->id, (uint64_t)(uintptr_t)it.src,
                        (uint64_t)(uintptr_t)it.dst, (uint64_t)sh.R, (uint64_t)sh.K,
-                       (uint64_t)sh.shift, (uint64_t)sh.wg_per_cu})
+                       (uint64_t)sh.shift, (uint64_t)sh.wg_per_cu, (uint64_t)sh.strided, (uint64_t)sh.nt})
       key.push_back(v);
   }
   if (sl.empty()) return ADHA_OK;
   // a batch mixes arrays with different shifts only through its first entry
-  for (auto &s : shapes) s.shift = shapes[0].shift;
+  for (auto &s : shapes) {
+    s.shift = shapes[0].shift;
+    s.strided = shapes[0].strided;
+    s.nt = shapes[0].nt;
+  }
   auto it = c->remap_cache.find(key);
   if (it == c->remap_cache.end()) {
     if (c->remap_cache.size() >= kCacheLimit) ADHA_TRY(flush_cache(c));
@@ -442,6 +478,8 @@ adha_status adha_remap_batched(adha_ctx *ctx, uint32_t n, const adha_remap_item 
   ADHA_HIP(hipGraphLaunch(ge->exec, st));
   return ADHA_OK;
 }
+
+extern "C" {
 
 // ------------------------------------------------------------------ sections
 adha_status adha_section_create(const adha_struct *s, adha_op op, uint32_t n_read, const int32_t *read,

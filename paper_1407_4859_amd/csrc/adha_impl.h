@@ -113,6 +113,7 @@ adha_layout *new_layout(LayoutDesc d);
 // ------------------------------------------------------------------ remap
 struct TileShape {
   uint32_t R = 0, K = 0, shift = 0, wg_per_cu = 0;
+  uint32_t strided = 0, nt = 0;  // tile order across workgroups; streaming accesses
 };
 
 struct Ctx;
@@ -125,7 +126,7 @@ struct RemapPrepared {
   const uint8_t *tails = nullptr;
   uint64_t main_tiles = 0, tiles_per_wg = 0, grid = 0, tail_blocks = 0;
   uint32_t n_arrays = 0, n_main = 0, n_tails = 0;
-  uint32_t K = 1, shift = 6, wg_per_cu = 1, lds = 0;
+  uint32_t K = 1, shift = 6, wg_per_cu = 1, lds = 0, strided = 0, nt = 0;
   uint64_t desc_bytes = 0, tail_bytes = 0;
 };
 // Builds the descriptor blob of a launch; with upload it is copied into a
@@ -139,8 +140,22 @@ adha_status remap_prepare(Ctx *ctx, const std::vector<const LayoutDesc *> &src_l
 adha_status remap_run(Ctx *ctx, const RemapPrepared &p, const void *src_override,
                       void *dst_override, hipStream_t stream);
 adha_status choose_shape(const Ctx *ctx, const LayoutDesc &a, const LayoutDesc &b, TileShape *out);
+// Shape from a policy: the largest multiple of max(64, T) records within
+// tile_bytes (at least one such multiple), slots to match.
+adha_status policy_shape(const LayoutDesc &a, const LayoutDesc &b, uint32_t tile_bytes, uint32_t wg_per_cu,
+                         uint32_t strided, uint32_t nt, TileShape *out);
+std::string tune_key(const LayoutDesc &a, const LayoutDesc &b);
 adha_status check_shape(const LayoutDesc &a, const LayoutDesc &b, const TileShape &s);
 uint32_t remap_lds_bytes(const LayoutDesc &a, const TileShape &s);
+
+adha_status validate_remap(const adha_layout *sl, const void *src, uint64_t src_cap, const adha_layout *dl,
+                           const void *dst, uint64_t dst_cap);
+adha_status shape_for(Ctx *ctx, const adha_layout *a, const adha_layout *b, TileShape *sh);
+adha_status remap_with_shape(Ctx *ctx, const adha_layout *sl, const void *src, const adha_layout *dl,
+                             void *dst, const TileShape &sh, hipStream_t stream);
+adha_status batch_run(Ctx *c, uint32_t n, const adha_remap_item *items, uint32_t flags, hipStream_t st);
+adha_status prepared_for(Ctx *ctx, const adha_layout *a, const adha_layout *b, const TileShape &sh,
+                         const RemapPrepared **out);
 
 // ------------------------------------------------------------------ sections
 adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l, void *buf,
@@ -170,6 +185,10 @@ struct Ctx {
   std::string arch;
   uint32_t *err_flag = nullptr;  // device word: gather index out of range seen
   std::map<std::tuple<uint64_t, uint64_t>, TileShape> forced_shapes;
+  std::map<std::string, TileShape> tunedb;  // tuned shapes by layout-pair class
+  struct BatchPolicy {
+    uint32_t tile_bytes = 16384, wg_per_cu = 4, strided = 0, nt = 1;
+  } batch;
   std::vector<GraphEntry> graphs;
   std::vector<float> model;  // trained / loaded cost-model parameters (empty = none)
   bool has_model = false;

@@ -30,6 +30,7 @@
 // serves layouts with 1- or 2-byte fields, whose bytes do not fall on
 // dword boundaries).
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 
@@ -79,16 +80,45 @@ constexpr int kBlock = 256;
 constexpr uint32_t kTailDwordsPerBlock = 1024;
 
 // ------------------------------------------------------------------ kernels
-template <int K>
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__device__ __forceinline__ u32x4 load16(const uint8_t *p) {
+  const u32x4 *q = reinterpret_cast<const u32x4 *>(p);
+  if constexpr (NT) return __builtin_nontemporal_load(q);
+  else return *q;
+}
+
+template <bool NT>
+__device__ __forceinline__ void store16(uint8_t *p, u32x4 v) {
+  u32x4 *q = reinterpret_cast<u32x4 *>(p);
+  if constexpr (NT) __builtin_nontemporal_store(v, q);
+  else *q = v;
+}
+
+// K: 16-byte slots per thread; NT: streaming (non-temporal) global accesses.
+// Workgroup w takes tiles w*tiles_per_wg .. +tiles_per_wg (contiguous) or,
+// when `strided`, tiles w, w + G, w + 2G, ... so that at any moment the
+// grid works on neighbouring tiles.
+template <int K, bool NT>
 __global__ __launch_bounds__(kBlock) void remap_tiles_kernel(const RArray *__restrict__ arrays,
                                                              uint32_t n_arrays, uint64_t total_tiles,
                                                              uint64_t tiles_per_wg, uint32_t shift,
+                                                             uint32_t strided,
                                                              const uint8_t *src_override,
                                                              uint8_t *dst_override) {
   extern __shared__ uint32_t lds[];
   const uint32_t t = threadIdx.x;
-  uint64_t g = (uint64_t)blockIdx.x * tiles_per_wg;
-  const uint64_t g_end = min(total_tiles, g + tiles_per_wg);
+  uint64_t g, g_end, step;
+  if (strided) {
+    g = blockIdx.x;
+    step = gridDim.x;
+    g_end = total_tiles;
+  } else {
+    g = (uint64_t)blockIdx.x * tiles_per_wg;
+    step = 1;
+    g_end = min(total_tiles, g + tiles_per_wg);
+  }
   if (g >= g_end) return;
 
   // array holding tile g (arrays sorted by tile_begin, each with >= 1 tile)
@@ -154,13 +184,14 @@ __global__ __launch_bounds__(kBlock) void remap_tiles_kernel(const RArray *__res
 
     const uint8_t *src = src_override ? src_override : A.src;
     uint8_t *dst = dst_override ? dst_override : A.dst;
+    const uint64_t r_step = step * (uint64_t)A.R;
     uint64_t r0 = (g - A.tile_begin) * (uint64_t)A.R;
-    uint4 v[K];
+    u32x4 v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k)
-      if (act[k]) v[k] = *reinterpret_cast<const uint4 *>(src + ld_off[k] + r0 * ld_S[k]);
+      if (act[k]) v[k] = load16<NT>(src + ld_off[k] + r0 * ld_S[k]);
 
-    for (; g < stop;) {
+    while (g < stop) {
 #pragma unroll
       for (int k = 0; k < K; ++k)
         if (act[k]) {
@@ -172,22 +203,22 @@ __global__ __launch_bounds__(kBlock) void remap_tiles_kernel(const RArray *__res
         }
       __syncthreads();
       const uint64_t cur = r0;
-      ++g;
+      g += step;
       if (g < stop) {
-        r0 += A.R;
+        r0 += r_step;
 #pragma unroll
         for (int k = 0; k < K; ++k)
-          if (act[k]) v[k] = *reinterpret_cast<const uint4 *>(src + ld_off[k] + r0 * ld_S[k]);
+          if (act[k]) v[k] = load16<NT>(src + ld_off[k] + r0 * ld_S[k]);
       }
 #pragma unroll
       for (int k = 0; k < K; ++k)
         if (act[k]) {
-          uint4 o;
+          u32x4 o;
           o.x = lds[st_pos[k][0]];
           o.y = lds[st_pos[k][1]];
           o.z = lds[st_pos[k][2]];
           o.w = lds[st_pos[k][3]];
-          *reinterpret_cast<uint4 *>(dst + st_off[k] + cur * st_S[k]) = o;
+          store16<NT>(dst + st_off[k] + cur * st_S[k], o);
         }
       __syncthreads();
     }
@@ -270,32 +301,60 @@ adha_status check_shape(const LayoutDesc &a, const LayoutDesc &b, const TileShap
                 (unsigned long long)chunks, kBlock * s.K);
   if (remap_lds_bytes(a, s) > kMaxLds) return fail(ADHA_ERR_INVALID, "tile needs more than 64 KiB of LDS");
   if (s.wg_per_cu == 0 || s.wg_per_cu > 32) return fail(ADHA_ERR_INVALID, "wg_per_cu not in [1, 32]");
+  if (s.strided > 1 || s.nt > 1) return fail(ADHA_ERR_INVALID, "order and nontemporal flags are 0 or 1");
   return ADHA_OK;
 }
 
-// Default shape: the largest multiple of max(64, T) records whose tile fits
-// 8 slots of 16 bytes per thread; R = 0 means "no full tiles" (tail path).
-adha_status choose_shape(const Ctx *ctx, const LayoutDesc &a, const LayoutDesc &b, TileShape *out) {
+adha_status policy_shape(const LayoutDesc &a, const LayoutDesc &b, uint32_t tile_bytes, uint32_t wg_per_cu,
+                         uint32_t strided, uint32_t nt, TileShape *out) {
   TileShape s;
-  s.K = 8;
   s.shift = 6;
-  s.wg_per_cu = 4;
+  s.wg_per_cu = wg_per_cu;
+  s.strided = strided;
+  s.nt = nt;
   const uint32_t S = a.shape.record_bytes();
   const uint32_t Rmin = std::max<uint32_t>(64, std::max(a.max_tile(), b.max_tile()));
-  if (!a.dword_fields() || S == 0) {
+  const uint64_t need = std::max<uint64_t>(tile_bytes, (uint64_t)Rmin * S);
+  s.K = 1;
+  while (s.K < 8 && (uint64_t)kBlock * 16 * s.K < need) s.K *= 2;
+  if (!a.dword_fields() || S == 0 || (uint64_t)kBlock * 16 * s.K < (uint64_t)Rmin * S) {
     s.R = 0;
   } else {
-    uint32_t R = (kBlock * s.K * 16 / S) / Rmin * Rmin;
-    s.R = R;
-    if (R > 0) {
-      // smaller record tiles use fewer slots
-      while (s.K > 1 && (uint64_t)R * S / 16 <= (uint64_t)kBlock * (s.K / 2)) s.K /= 2;
-      if (remap_lds_bytes(a, s) > kMaxLds) s.R = 0;
-    }
+    s.R = (uint32_t)(std::min<uint64_t>((uint64_t)kBlock * 16 * s.K, std::max<uint64_t>(tile_bytes, (uint64_t)Rmin * S)) /
+                     S / Rmin * Rmin);
+    if (remap_lds_bytes(a, s) > kMaxLds) s.R = 0;
   }
-  (void)ctx;
   *out = s;
   return ADHA_OK;
+}
+
+// Key of a layout pair's class for the tuning database: layout kinds, record
+// bytes, largest tile, element-size class and log2 of the record count.
+std::string tune_key(const LayoutDesc &a, const LayoutDesc &b) {
+  uint32_t emask = 0;
+  for (auto e : a.shape.ebytes) emask |= e;
+  uint32_t lg = 0;
+  while (lg < 62 && (int64_t(1) << (lg + 1)) <= a.shape.n) ++lg;
+  char buf[160];
+  snprintf(buf, sizeof buf, "pair:%d:%d:S%u:T%u:e%u:n%u", a.layout_class(), b.layout_class(),
+           a.shape.record_bytes(), std::max(a.max_tile(), b.max_tile()), emask, lg);
+  return buf;
+}
+
+// Default shape: a tuned entry for the pair's class if the context has one;
+// otherwise 16 KiB tiles (at least max(64, T) records), 4 workgroups per CU,
+// strided tile order and streaming accesses, the best setting measured for
+// 64-byte records.  R = 0 means "no full tiles": the tail kernel does
+// everything (1- and 2-byte fields, or records too large for one tile).
+adha_status choose_shape(const Ctx *ctx, const LayoutDesc &a, const LayoutDesc &b, TileShape *out) {
+  if (ctx && !ctx->tunedb.empty()) {
+    auto it = ctx->tunedb.find(tune_key(a, b));
+    if (it != ctx->tunedb.end() && check_shape(a, b, it->second) >= 0) {
+      *out = it->second;
+      return ADHA_OK;
+    }
+  }
+  return policy_shape(a, b, 16384, 4, 1, 1, out);
 }
 
 // One device blob per launch: arrays, groups, fields, word tables, tails.
@@ -390,6 +449,8 @@ adha_status remap_prepare(Ctx *ctx, const std::vector<const LayoutDesc *> &src_l
       main_list.push_back((uint32_t)i);
       P.K = std::max(P.K, sh.K);
       P.shift = sh.shift;
+      P.strided = sh.strided;
+      P.nt = sh.nt;
       P.wg_per_cu = std::max(P.wg_per_cu, sh.wg_per_cu);
       P.lds = std::max(P.lds, remap_lds_bytes(A, sh));
     }
@@ -465,12 +526,26 @@ adha_status remap_run(Ctx *ctx, const RemapPrepared &P, const void *src_override
   if (P.main_tiles > 0) {
     const RArray *arrs = (const RArray *)P.main_arrays;
     const dim3 grid((uint32_t)P.grid), block(kBlock);
-    switch (P.K) {
-      case 1: hipLaunchKernelGGL((remap_tiles_kernel<1>), grid, block, P.lds, stream, arrs, P.n_main, P.main_tiles, P.tiles_per_wg, P.shift, so, dov); break;
-      case 2: hipLaunchKernelGGL((remap_tiles_kernel<2>), grid, block, P.lds, stream, arrs, P.n_main, P.main_tiles, P.tiles_per_wg, P.shift, so, dov); break;
-      case 4: hipLaunchKernelGGL((remap_tiles_kernel<4>), grid, block, P.lds, stream, arrs, P.n_main, P.main_tiles, P.tiles_per_wg, P.shift, so, dov); break;
-      default: hipLaunchKernelGGL((remap_tiles_kernel<8>), grid, block, P.lds, stream, arrs, P.n_main, P.main_tiles, P.tiles_per_wg, P.shift, so, dov); break;
+    const uint32_t sd = P.strided;
+#define ADHA_REMAP_LAUNCH(KK, NTT)                                                                  \
+  hipLaunchKernelGGL((remap_tiles_kernel<KK, NTT>), grid, block, P.lds, stream, arrs, P.n_main,     \
+                     P.main_tiles, P.tiles_per_wg, P.shift, sd, so, dov)
+    if (P.nt) {
+      switch (P.K) {
+        case 1: ADHA_REMAP_LAUNCH(1, true); break;
+        case 2: ADHA_REMAP_LAUNCH(2, true); break;
+        case 4: ADHA_REMAP_LAUNCH(4, true); break;
+        default: ADHA_REMAP_LAUNCH(8, true); break;
+      }
+    } else {
+      switch (P.K) {
+        case 1: ADHA_REMAP_LAUNCH(1, false); break;
+        case 2: ADHA_REMAP_LAUNCH(2, false); break;
+        case 4: ADHA_REMAP_LAUNCH(4, false); break;
+        default: ADHA_REMAP_LAUNCH(8, false); break;
+      }
     }
+#undef ADHA_REMAP_LAUNCH
     ADHA_HIP(hipGetLastError());
   }
   if (P.n_tails > 0) {

@@ -93,10 +93,12 @@ def test_forced_tile_shapes_agree(ctx):
     want = oracle.remap(OA, src_h, OB)
     src = dev_bytes(src_h)
     LA, LB = mirror(st, OA), mirror(st, OB)
-    for R, K, shift, wg in ((64, 8, 6, 4), (128, 8, 5, 2), (64, 4, 31, 8), (192, 8, 7, 1)):
-        say("shape", R, K, shift, wg)
-        A.set_shape(ctx, LA, LB, R, K, shift, wg)
-        assert A.get_shape(ctx, LA, LB) == dict(tile_records=R, slots=K, pad_shift=shift, wg_per_cu=wg)
+    for R, K, shift, wg, order, nt in ((64, 8, 6, 4, 1, 1), (128, 8, 5, 2, 2, 1), (64, 4, 31, 8, 2, 2),
+                                       (192, 8, 7, 1, 1, 2), (64, 8, 6, 16, 2, 2)):
+        say("shape", R, K, shift, wg, order, nt)
+        A.set_shape(ctx, LA, LB, R, K, shift, wg, order, nt)
+        assert A.get_shape(ctx, LA, LB) == dict(tile_records=R, slots=K, pad_shift=shift, wg_per_cu=wg,
+                                                order=order, nontemporal=nt)
         dst = dev_empty(OB.nbytes)
         A.remap(ctx, LA, src, LB, dst)
         ctx.check()
