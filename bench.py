@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--learned", action="store_true")
     ap.add_argument("--only-remap", action="store_true", help="timed steps only (for profiling)")
+    ap.add_argument("--no-tune", action="store_true", help="use the default tile shapes")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB with a plain device copy (scale for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -269,6 +272,20 @@ def main():
         for _, sl, sb, dl, db in pairs:
             A.remap(ctx, sl, sb, dl, db)
 
+    tuning = {}
+    if not args.no_tune:
+        # the autotuner picks each pair's tile shape on these buffers (untimed)
+        for name, sl, sb, dl, db in pairs:
+            r = A.tune_remap(ctx, sl, sb, dl, db, reps=3)
+            tuning[name] = {"shape": r["shape"], "tuned_us": round(r["best_us"], 1),
+                            "default_us": round(r["default_us"], 1)}
+        log("tuned:", tuning)
+    if args.copy_calibration:
+        # a plain 1 GiB device copy: its FETCH_SIZE / WRITE_SIZE counters give
+        # the scale between counter units and bytes
+        log("copy calibration: 1 GiB")
+        b[: 1 << 30].copy_(a[: 1 << 30])
+        torch.cuda.synchronize()
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -301,9 +318,11 @@ def main():
                    "records": n, "record_bytes": 64, "bytes_per_step": step_bytes},
         "frac_of_peak": round(value / HBM_PEAK_GBS, 4),
         "remaps": per,
+        "tuning": tuning,
+        "shapes": {name: A.get_shape(ctx, sl, dl) for name, sl, _, dl, _ in pairs},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "remap_tiles_kernel<8>",
+                     "kernel": "remap_tiles_kernel (persistent LDS-transposing remap)",
                      "per_launch_bytes": 2 * n * 64},
     }
     if not args.only_remap:

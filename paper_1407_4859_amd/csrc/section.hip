@@ -97,7 +97,9 @@ __device__ __forceinline__ void store_acc(uint8_t *buf, const SField &W, uint64_
   }
 }
 
-template <int OP, bool GATHER, int MAXR>
+// DG = 0: direct section; otherwise a gather of at most DG neighbours.
+// MAXR: bound on the number of read fields (loads are unrolled to it).
+template <int OP, int DG, int MAXR>
 __global__ __launch_bounds__(256) void section_kernel(const SectionArgs a) {
   const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
   if (i >= (uint64_t)a.n) return;
@@ -105,7 +107,7 @@ __global__ __launch_bounds__(256) void section_kernel(const SectionArgs a) {
   Acc acc[2];
   acc[0] = acc[1] = Acc{0.0f, 0.0, 0u};
 
-  if constexpr (!GATHER) {
+  if constexpr (DG == 0) {
     uint64_t tv[MAXR];
 #pragma unroll
     for (int q = 0; q < MAXR; ++q)
@@ -134,39 +136,43 @@ __global__ __launch_bounds__(256) void section_kernel(const SectionArgs a) {
       }
     }
   } else {
-    const uint32_t deg = a.degree;
-    const int32_t *row = a.idx + i * deg;
+    // Neighbours are taken in batches of NB with all of a batch's field loads
+    // in flight together; the next batch's indices are loaded before the
+    // current batch's fields, so the two round trips overlap.  Terms are
+    // folded in neighbour order.
+    constexpr int NB = MAXR >= 32 ? 1 : 32 / MAXR;
+    const int deg = (int)a.degree;
+    const int32_t *row = a.idx + i * (uint64_t)deg;
+    int32_t cur[NB], nxt[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) cur[b] = b < deg ? row[b] : 0;
     bool bad = false;
-    for (uint32_t j = 0; j < deg; j += 2) {
-      const bool two = j + 1 < deg;
-      const int32_t n0 = row[j];
-      const int32_t n1 = two ? row[j + 1] : 0;
-      const bool ok0 = n0 >= 0 && (int64_t)n0 < a.n;
-      const bool ok1 = two && n1 >= 0 && (int64_t)n1 < a.n;
-      bad |= !ok0 || (two && !ok1);
-      uint64_t t0[MAXR], t1[MAXR];
+    for (int j0 = 0; j0 < deg; j0 += NB) {
 #pragma unroll
-      for (int q = 0; q < MAXR; ++q)
-        if (q < (int)nr) {
-          t0[q] = ok0 ? load_term(a.buf, a.rd[q], (uint64_t)n0) : 0;
-          t1[q] = ok1 ? load_term(a.buf, a.rd[q], (uint64_t)n1) : 0;
+      for (int b = 0; b < NB; ++b) nxt[b] = j0 + NB + b < deg ? row[j0 + NB + b] : 0;
+      uint64_t t[NB][MAXR];
+      bool ok[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const bool live = j0 + b < deg;
+        ok[b] = live && cur[b] >= 0 && (int64_t)cur[b] < a.n;
+        bad |= live && !ok[b];
+#pragma unroll
+        for (int q = 0; q < MAXR; ++q)
+          if (q < (int)nr) t[b][q] = ok[b] ? load_term(a.buf, a.rd[q], (uint64_t)cur[b]) : 0;
+      }
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        if (ok[b]) {
+#pragma unroll
+          for (int q = 0; q < MAXR; ++q)
+            if (q < (int)nr) {
+              fold(acc[0], 0, a.wr[0].dt, a.rd[q].dt, t[b][q]);
+              if (nw > 1) fold(acc[1], 1, a.wr[1].dt, a.rd[q].dt, t[b][q]);
+            }
         }
-      if (ok0) {
 #pragma unroll
-        for (int q = 0; q < MAXR; ++q)
-          if (q < (int)nr) {
-            fold(acc[0], 0, a.wr[0].dt, a.rd[q].dt, t0[q]);
-            if (nw > 1) fold(acc[1], 1, a.wr[1].dt, a.rd[q].dt, t0[q]);
-          }
-      }
-      if (ok1) {
-#pragma unroll
-        for (int q = 0; q < MAXR; ++q)
-          if (q < (int)nr) {
-            fold(acc[0], 0, a.wr[0].dt, a.rd[q].dt, t1[q]);
-            if (nw > 1) fold(acc[1], 1, a.wr[1].dt, a.rd[q].dt, t1[q]);
-          }
-      }
+      for (int b = 0; b < NB; ++b) cur[b] = nxt[b];
     }
     if (bad) atomicOr(a.err, 1u);
   }
@@ -186,12 +192,12 @@ static SField sfield(const LayoutDesc &l, int f) {
   return s;
 }
 
-template <int OP, bool G>
+template <int OP, int DG>
 static void launch_maxr(uint32_t nr, dim3 grid, const SectionArgs &a, hipStream_t st) {
-  if (nr <= 4) hipLaunchKernelGGL((section_kernel<OP, G, 4>), grid, dim3(256), 0, st, a);
-  else if (nr <= 8) hipLaunchKernelGGL((section_kernel<OP, G, 8>), grid, dim3(256), 0, st, a);
-  else if (nr <= 16) hipLaunchKernelGGL((section_kernel<OP, G, 16>), grid, dim3(256), 0, st, a);
-  else hipLaunchKernelGGL((section_kernel<OP, G, 32>), grid, dim3(256), 0, st, a);
+  if (nr <= 4) hipLaunchKernelGGL((section_kernel<OP, DG, 4>), grid, dim3(256), 0, st, a);
+  else if (nr <= 8) hipLaunchKernelGGL((section_kernel<OP, DG, 8>), grid, dim3(256), 0, st, a);
+  else if (nr <= 16) hipLaunchKernelGGL((section_kernel<OP, DG, 16>), grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((section_kernel<OP, DG, 32>), grid, dim3(256), 0, st, a);
 }
 
 adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l, void *buf,
@@ -213,17 +219,19 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
   const uint32_t nr = a.n_read;
   switch (sec.op) {
     case ADHA_OP_GEN:
-      if (sec.degree) launch_maxr<ADHA_OP_GEN, true>(nr, grid, a, stream);
-      else launch_maxr<ADHA_OP_GEN, false>(nr, grid, a, stream);
+      if (sec.degree == 0) launch_maxr<ADHA_OP_GEN, 0>(nr, grid, a, stream);
+      else if (sec.degree <= 8) launch_maxr<ADHA_OP_GEN, 8>(nr, grid, a, stream);
+      else if (sec.degree <= 16) launch_maxr<ADHA_OP_GEN, 16>(nr, grid, a, stream);
+      else launch_maxr<ADHA_OP_GEN, 32>(nr, grid, a, stream);
       break;
     case ADHA_OP_SUM:
-      launch_maxr<ADHA_OP_SUM, false>(nr, grid, a, stream);
+      launch_maxr<ADHA_OP_SUM, 0>(nr, grid, a, stream);
       break;
     case ADHA_OP_MULADD3:
-      hipLaunchKernelGGL((section_kernel<ADHA_OP_MULADD3, false, 4>), grid, dim3(256), 0, stream, a);
+      hipLaunchKernelGGL((section_kernel<ADHA_OP_MULADD3, 0, 4>), grid, dim3(256), 0, stream, a);
       break;
     case ADHA_OP_SUB2:
-      hipLaunchKernelGGL((section_kernel<ADHA_OP_SUB2, false, 4>), grid, dim3(256), 0, stream, a);
+      hipLaunchKernelGGL((section_kernel<ADHA_OP_SUB2, 0, 4>), grid, dim3(256), 0, stream, a);
       break;
     default:
       return fail(ADHA_ERR_UNSUPPORTED, "unknown op %d", sec.op);
