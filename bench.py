@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--learned", action="store_true")
     ap.add_argument("--only-remap", action="store_true", help="timed steps only (for profiling)")
     ap.add_argument("--no-tune", action="store_true", help="use the default tile shapes")
+    ap.add_argument("--save-tune", default=None, help="write the tuning database here after tuning")
+    ap.add_argument("--load-tune", default=None, help="load a tuning database instead of tuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB with a plain device copy (scale for HBM byte counters)")
     return ap.parse_args()
@@ -273,13 +275,18 @@ def main():
             A.remap(ctx, sl, sb, dl, db)
 
     tuning = {}
-    if not args.no_tune:
+    if args.load_tune:
+        A.tune_load(ctx, args.load_tune)
+        tuning["loaded"] = args.load_tune
+    elif not args.no_tune:
         # the autotuner picks each pair's tile shape on these buffers (untimed)
         for name, sl, sb, dl, db in pairs:
             r = A.tune_remap(ctx, sl, sb, dl, db, reps=3)
             tuning[name] = {"shape": r["shape"], "tuned_us": round(r["best_us"], 1),
                             "default_us": round(r["default_us"], 1)}
         log("tuned:", tuning)
+        if args.save_tune:
+            A.tune_save(ctx, args.save_tune)
     if args.copy_calibration:
         # a plain 1 GiB device copy: its FETCH_SIZE / WRITE_SIZE counters give
         # the scale between counter units and bytes

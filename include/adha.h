@@ -110,6 +110,13 @@ adha_status adha_ctx_check(adha_ctx *ctx, void *stream);
 /* Number of compute units (used to size persistent launches). */
 adha_status adha_ctx_cu_count(const adha_ctx *ctx, int32_t *out);
 
+typedef enum {
+  /* 1 (default): a gather whose read fields share one interleaved group
+   * fetches each neighbour's span with wide loads; 0: one load per field. */
+  ADHA_OPT_SPAN_GATHER = 1
+} adha_option;
+adha_status adha_ctx_set_option(adha_ctx *ctx, adha_option opt, int64_t value);
+
 /* ------------------------------------------------------------ struct */
 /* A struct of n_records records (n_records >= 0; 0 makes every operation a
  * no-op).  Fields are added in order and get ids 0, 1, ... */

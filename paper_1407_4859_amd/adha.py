@@ -26,6 +26,7 @@ COST_MEASURED, COST_ANALYTIC, COST_LEARNED = 0, 1, 2
 CAT_AOS_SOA, CAT_FULL = 0, 1
 INIT_FREE, INIT_AOS = 0, 1
 BATCH_GRAPH, BATCH_SEPARATE = 1, 2
+OPT_SPAN_GATHER = 1
 N_FEATURES = 16
 MLP_PARAMS = 64 * 16 + 64 + 64 * 64 + 64 + 64 * 64 + 64 + 64 + 1
 
@@ -81,6 +82,7 @@ _SIGS = {
     "adha_ctx_destroy": ([P], I32T),
     "adha_ctx_check": ([P, P], I32T),
     "adha_ctx_cu_count": ([P, ctypes.POINTER(I32T)], I32T),
+    "adha_ctx_set_option": ([P, ctypes.c_int, I64], I32T),
     "adha_struct_create": ([I64, PP], I32T),
     "adha_struct_add_field": ([P, ctypes.c_int, U32, ctypes.POINTER(I32T)], I32T),
     "adha_struct_destroy": ([P], I32T),
@@ -202,6 +204,9 @@ class Ctx:
 
     def check(self, stream=None):
         return check(lib().adha_ctx_check(self.h, stream_ptr(stream)))
+
+    def set_option(self, opt: int, value: int):
+        check(lib().adha_ctx_set_option(self.h, opt, value))
 
     @property
     def cu_count(self):

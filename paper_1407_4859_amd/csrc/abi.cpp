@@ -196,6 +196,18 @@ adha_status adha_ctx_cu_count(const adha_ctx *ctx, int32_t *out) {
   return ADHA_OK;
 }
 
+adha_status adha_ctx_set_option(adha_ctx *ctx, adha_option opt, int64_t value) {
+  if (!ctx) return fail(ADHA_ERR_INVALID, "ctx is NULL");
+  switch (opt) {
+    case ADHA_OPT_SPAN_GATHER:
+      if (value != 0 && value != 1) return fail(ADHA_ERR_INVALID, "span-gather option is 0 or 1");
+      ctx->c.no_span = value == 0;
+      return ADHA_OK;
+    default:
+      return fail(ADHA_ERR_INVALID, "unknown option %d", (int)opt);
+  }
+}
+
 // ------------------------------------------------------------------ struct
 adha_status adha_struct_create(int64_t n_records, adha_struct **out) {
   if (!out) return fail(ADHA_ERR_INVALID, "out is NULL");

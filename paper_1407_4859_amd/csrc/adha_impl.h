@@ -192,6 +192,7 @@ struct Ctx {
   std::vector<GraphEntry> graphs;
   std::vector<float> model;  // trained / loaded cost-model parameters (empty = none)
   bool has_model = false;
+  bool no_span = false;      // gathers always take the per-field path
   ~Ctx();
 };
 

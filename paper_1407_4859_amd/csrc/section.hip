@@ -18,6 +18,8 @@
 
 namespace adha {
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 struct SField {
   uint64_t base;
   uint32_t TS;    // T * S_g
@@ -180,6 +182,151 @@ __global__ __launch_bounds__(256) void section_kernel(const SectionArgs a) {
   if (nw > 1) store_acc(a.buf, a.wr[1], i, acc[1]);
 }
 
+// Gather whose read fields all sit in one interleaved group: per neighbour
+// the span of the group record that holds them is fetched with VEC-byte
+// vector loads (VEC divides the record size, so every load is aligned) into
+// registers, and each term is picked out of those words.  One neighbour then
+// costs ceil(span / VEC) wide loads instead of one load per field.
+struct SpanArgs {
+  uint64_t gbase;              // byte offset of the group
+  uint32_t S;                  // group record bytes
+  uint32_t lo;                 // first byte of the span (a multiple of VEC)
+  uint32_t nvec;               // VEC-byte loads per neighbour
+  uint32_t word[ADHA_MAX_READ];  // dword index of each read field inside the span
+};
+
+template <int VEC>
+__device__ __forceinline__ void load_span(const uint8_t *p, uint32_t *w, int k) {
+  if constexpr (VEC == 16) {
+    const u32x4 v = *reinterpret_cast<const u32x4 *>(p + 16 * k);
+    w[4 * k] = v.x;
+    w[4 * k + 1] = v.y;
+    w[4 * k + 2] = v.z;
+    w[4 * k + 3] = v.w;
+  } else if constexpr (VEC == 8) {
+    const uint2 v = *reinterpret_cast<const uint2 *>(p + 8 * k);
+    w[2 * k] = v.x;
+    w[2 * k + 1] = v.y;
+  } else {
+    w[k] = *reinterpret_cast<const uint32_t *>(p + 4 * k);
+  }
+}
+
+// w[wi] for a wave-uniform wi, as a chain of selects with constant indices
+// (keeps w in registers).
+template <int MAXW>
+__device__ __forceinline__ uint32_t pick(const uint32_t (&w)[MAXW], uint32_t wi) {
+  uint32_t r = w[0];
+#pragma unroll
+  for (int k = 1; k < MAXW; ++k) r = wi == (uint32_t)k ? w[k] : r;
+  return r;
+}
+
+// One neighbour's span: VEC-byte loads into w (zeros when !ok).
+template <int VEC, int MAXW>
+__device__ __forceinline__ void span_load(const uint8_t *gb, const SpanArgs &sp, int32_t r, bool ok,
+                                          uint32_t (&w)[MAXW]) {
+  constexpr int WPV = VEC / 4, MAXV = MAXW / WPV;
+  const uint8_t *p = gb + (uint64_t)(ok ? r : 0) * sp.S;
+#pragma unroll
+  for (int k = 0; k < MAXV; ++k)
+    if (k < (int)sp.nvec) {
+      if (ok) load_span<VEC>(p, w, k);
+      else {
+#pragma unroll
+        for (int x = 0; x < WPV; ++x) w[WPV * k + x] = 0;
+      }
+    }
+}
+
+// Fold one neighbour's terms, picked out of its span in read-field order.
+template <int MAXW, int MAXR>
+__device__ __forceinline__ void span_fold(const SectionArgs &a, const SpanArgs &sp, const uint32_t (&w)[MAXW],
+                                          Acc (&acc)[2]) {
+  const uint32_t nr = a.n_read, nw = a.n_write;
+  uint64_t t[MAXR];
+#pragma unroll
+  for (int q = 0; q < MAXR; ++q)
+    if (q < (int)nr) {
+      const uint32_t wi = sp.word[q];
+      t[q] = pick<MAXW>(w, wi);
+      if (a.rd[q].e == 8) t[q] |= (uint64_t)pick<MAXW>(w, wi + 1) << 32;
+    }
+#pragma unroll
+  for (int q = 0; q < MAXR; ++q)
+    if (q < (int)nr) {
+      fold(acc[0], 0, a.wr[0].dt, a.rd[q].dt, t[q]);
+      if (nw > 1) fold(acc[1], 1, a.wr[1].dt, a.rd[q].dt, t[q]);
+    }
+}
+
+// One neighbour at a time (a single register array keeps the span out of
+// scratch); the next neighbour's index is loaded before the current span.
+// Occupancy provides the memory-level parallelism.
+template <int VEC, int MAXW, int MAXR>
+__global__ __launch_bounds__(256) void section_span_kernel(const SectionArgs a, const SpanArgs sp) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  if (i >= (uint64_t)a.n) return;
+  Acc acc[2];
+  acc[0] = acc[1] = Acc{0.0f, 0.0, 0u};
+  const int deg = (int)a.degree;
+  const int32_t *row = a.idx + i * (uint64_t)deg;
+  const uint8_t *gb = a.buf + sp.gbase + sp.lo;
+  int32_t cur = deg > 0 ? row[0] : 0;
+  bool bad = false;
+  for (int j = 0; j < deg; ++j) {
+    const int32_t nxt = j + 1 < deg ? row[j + 1] : 0;
+    const bool ok = cur >= 0 && (int64_t)cur < a.n;
+    bad |= !ok;
+    uint32_t w[MAXW];
+    span_load<VEC, MAXW>(gb, sp, cur, ok, w);
+    if (ok) span_fold<MAXW, MAXR>(a, sp, w, acc);
+    cur = nxt;
+  }
+  if (bad) atomicOr(a.err, 1u);
+  store_acc(a.buf, a.wr[0], i, acc[0]);
+  if (a.n_write > 1) store_acc(a.buf, a.wr[1], i, acc[1]);
+}
+
+// The span plan of a gather, or false when its reads are not all in one
+// interleaved group (or the span is wider than 16 dwords).
+static bool span_plan(const SectionDesc &sec, const LayoutDesc &l, SpanArgs *sp, uint32_t *vec) {
+  const uint32_t g = l.group_of[sec.rd[0]];
+  for (int f : sec.rd)
+    if (l.group_of[f] != g) return false;
+  const Group &G = l.groups[g];
+  if (G.T != 1) return false;
+  uint32_t lo = ~0u, hi = 0;
+  for (int f : sec.rd) {
+    lo = std::min(lo, l.p[f]);
+    hi = std::max(hi, l.p[f] + l.shape.ebytes[f]);
+  }
+  const uint32_t A = G.S % 16 == 0 ? 16 : G.S % 8 == 0 ? 8 : 4;
+  const uint32_t lo_a = lo / A * A;
+  const uint32_t nvec = (hi - lo_a + A - 1) / A;
+  if (nvec * A / 4 > 16) return false;
+  sp->gbase = G.base;
+  sp->S = G.S;
+  sp->lo = lo_a;
+  sp->nvec = nvec;
+  for (size_t q = 0; q < sec.rd.size(); ++q) sp->word[q] = (l.p[sec.rd[q]] - lo_a) / 4;
+  *vec = A;
+  return true;
+}
+
+template <int VEC, int MAXW>
+static void launch_span_maxr(uint32_t nr, dim3 grid, const SectionArgs &a, const SpanArgs &sp, hipStream_t st) {
+  if (nr <= 4) hipLaunchKernelGGL((section_span_kernel<VEC, MAXW, 4>), grid, dim3(256), 0, st, a, sp);
+  else if (nr <= 8) hipLaunchKernelGGL((section_span_kernel<VEC, MAXW, 8>), grid, dim3(256), 0, st, a, sp);
+  else if (nr <= 16) hipLaunchKernelGGL((section_span_kernel<VEC, MAXW, 16>), grid, dim3(256), 0, st, a, sp);
+  else hipLaunchKernelGGL((section_span_kernel<VEC, MAXW, 32>), grid, dim3(256), 0, st, a, sp);
+}
+
+template <int VEC>
+static void launch_span(uint32_t nr, dim3 grid, const SectionArgs &a, const SpanArgs &sp, hipStream_t st) {
+  launch_span_maxr<VEC, 16>(nr, grid, a, sp, st);
+}
+
 static SField sfield(const LayoutDesc &l, int f) {
   const Group &g = l.groups[l.group_of[f]];
   SField s{};
@@ -218,12 +365,21 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
   const dim3 grid((uint32_t)((n + 255) / 256));
   const uint32_t nr = a.n_read;
   switch (sec.op) {
-    case ADHA_OP_GEN:
+    case ADHA_OP_GEN: {
+      SpanArgs sp{};
+      uint32_t vec = 0;
+      if (sec.degree > 0 && !ctx->no_span && span_plan(sec, l, &sp, &vec)) {
+        if (vec == 16) launch_span<16>(nr, grid, a, sp, stream);
+        else if (vec == 8) launch_span<8>(nr, grid, a, sp, stream);
+        else launch_span<4>(nr, grid, a, sp, stream);
+        break;
+      }
       if (sec.degree == 0) launch_maxr<ADHA_OP_GEN, 0>(nr, grid, a, stream);
       else if (sec.degree <= 8) launch_maxr<ADHA_OP_GEN, 8>(nr, grid, a, stream);
       else if (sec.degree <= 16) launch_maxr<ADHA_OP_GEN, 16>(nr, grid, a, stream);
       else launch_maxr<ADHA_OP_GEN, 32>(nr, grid, a, stream);
       break;
+    }
     case ADHA_OP_SUM:
       launch_maxr<ADHA_OP_SUM, 0>(nr, grid, a, stream);
       break;

@@ -137,6 +137,31 @@ def test_wide_read_sets(ctx):
     _run_sections(ctx, spec, oaos(n, spec.elem_bytes), secs, cols, idx, "wide")
 
 
+@pytest.mark.parametrize("group,rd", [
+    ([0, 1, 2, 3, 4], [0, 2, 3]),          # 24-byte records (8-byte loads), f64 in the middle
+    ([1, 2, 3, 5, 6, 7], [1, 3, 6, 7]),    # 28 bytes (4-byte loads)
+    ([0, 1, 3, 4, 5, 6], [0, 1, 3, 5, 6]), # 32 bytes (16-byte loads)
+    ([3], [3]),                            # a lone f64 column
+])
+def test_span_gathers_match_oracle_and_per_field_path(ctx, group, rd):
+    n = 3001
+    spec = synth.StructSpec(n, [synth.F32, synth.I32, synth.F32, synth.F64, synth.F32, synth.I32,
+                                synth.F32, synth.F32, synth.F32, synth.F64],
+                            [4, 4, 4, 8, 4, 4, 4, 4, 4, 8])
+    cols = synth.record_matrix(21, n, spec.dtypes, spec.elem_bytes)
+    wr = [8, 9]
+    secs = [synth.SectionSpec(synth.OP_GEN, rd, wr, d) for d in (1, 5, 16, 32)]
+    idx = synth.uniform_index(21, 3, n * 32, n)
+    O = from_partition(n, spec.elem_bytes, [group] if len(group) > 1 else [], 1)
+    got_span = _run_sections(ctx, spec, O, secs, cols, idx, "span")
+    ctx.set_option(A.OPT_SPAN_GATHER, 0)
+    try:
+        got_field = _run_sections(ctx, spec, O, secs, cols, idx, "per-field")
+    finally:
+        ctx.set_option(A.OPT_SPAN_GATHER, 1)
+    assert np.array_equal(got_span, got_field)
+
+
 def test_gather_out_of_range_indices_are_skipped_and_reported(ctx):
     n = 512
     spec = synth.StructSpec(n, [synth.F32, synth.F32], [4, 4])
