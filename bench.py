@@ -51,6 +51,13 @@ def parse():
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--learned", action="store_true")
+    ap.add_argument("--only-learned", action="store_true", help="skip everything but the cost-model leg")
+    ap.add_argument("--train-samples", type=int, default=20000)
+    ap.add_argument("--train-epochs", type=int, default=300)
+    ap.add_argument("--programs", type=int, default=64)
+    ap.add_argument("--program-seed0", type=int, default=1000)
+    ap.add_argument("--save-model", default=None)
+    ap.add_argument("--load-model", default=None)
     ap.add_argument("--only-remap", action="store_true", help="timed steps only (for profiling)")
     ap.add_argument("--no-tune", action="store_true", help="use the default tile shapes")
     ap.add_argument("--save-tune", default=None, help="write the tuning database here after tuning")
@@ -215,29 +222,57 @@ def batched_bench(A, synth, torch, timer):
             "graph_frac_of_peak": round(total / g_ms / 1e6 / HBM_PEAK_GBS, 3)}
 
 
-def learned_bench(A, synth, torch):
+def path_cost(T, R, path):
+    """Cost of a layout choice per section under tables T (k x C) and R (C x C)."""
+    c = T[0][path[0]]
+    for s in range(1, len(path)):
+        c += R[path[s - 1]][path[s]] + T[s][path[s]]
+    return c
+
+
+def learned_bench(A, synth, torch, args):
+    """Trains the cost model on timings of generated sections, then plans
+    seeded 8-section programs with learned, analytic and measured costs; each
+    plan is scored under the measured tables (the enumeration's ground truth)."""
     ctx = A.Ctx(0)
-    rep = A.costmodel_train(ctx, A.train_opts(n_samples=4000, epochs=400, min_log2_n=16, max_log2_n=22))
-    ratios, plan_t = [], {"learned": 0.0, "measured": 0.0}
-    for seed in range(100, 108):
-        n = 1 << (20 + seed % 3)
+    if args.load_model:
+        A.costmodel_load(ctx, args.load_model)
+        rep = {"loaded": args.load_model}
+    else:
+        log("learned: generating and timing", args.train_samples, "sections")
+        rep = A.costmodel_train(ctx, A.train_opts(n_samples=args.train_samples, epochs=args.train_epochs,
+                                                  min_log2_n=16, max_log2_n=23, reps=3))
+        rep = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.items()}
+        if args.save_model:
+            A.costmodel_save(ctx, args.save_model)
+    rows = []
+    for seed in range(args.program_seed0, args.program_seed0 + args.programs):
+        z = synth.splitmix64(5, seed, 0, 1)
+        n = 1 << (20 + int(((int(z[0]) >> 32) * 5) >> 32))
         spec = synth.config3_struct(n)
         st = A.Struct.from_spec(spec)
-        ss = [A.Section.from_spec(st, s) for s in synth.random_program(seed, 32)]
+        ss = [A.Section.from_spec(st, s) for s in synth.random_program(seed % 256, 32)]
         prog = A.Program(st, ss)
-        idx = synth.uniform_index_torch(seed, 999, n * 16, n, "cuda")
+        idx = synth.uniform_index_torch(seed % 256, 999, n * 16, n, "cuda")
         pl_m = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_MEASURED, reps=3), idx=idx)
         pl_l = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_LEARNED), idx=idx)
-        plan_t["learned"] += pl_l.seconds
-        plan_t["measured"] += pl_m.seconds
+        pl_a = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_ANALYTIC))
         T, R = pl_m.tables()
-        from oracle.planner import path_cost
-        ratios.append(path_cost(T, R, pl_l.choices()) / pl_m.cost)
-    return {"train": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.items()},
-            "programs": len(ratios), "mean_ratio": round(float(np.mean(ratios)), 4),
-            "max_ratio": round(float(np.max(ratios)), 4),
-            "plan_seconds_learned": round(plan_t["learned"], 2),
-            "plan_seconds_measured": round(plan_t["measured"], 2)}
+        rows.append(dict(seed=seed, log2n=n.bit_length() - 1, measured_us=round(pl_m.cost, 1),
+                         learned_ratio=round(path_cost(T, R, pl_l.choices()) / pl_m.cost, 4),
+                         analytic_ratio=round(path_cost(T, R, pl_a.choices()) / pl_m.cost, 4),
+                         plan_s_measured=round(pl_m.seconds, 3), plan_s_learned=round(pl_l.seconds, 4)))
+        log("learned:", rows[-1])
+        del idx
+        torch.cuda.empty_cache()
+    lr = [r["learned_ratio"] for r in rows]
+    ar = [r["analytic_ratio"] for r in rows]
+    return {"train": rep, "programs": len(rows),
+            "learned_mean_ratio": round(float(np.mean(lr)), 4), "learned_max_ratio": round(float(np.max(lr)), 4),
+            "analytic_mean_ratio": round(float(np.mean(ar)), 4), "analytic_max_ratio": round(float(np.max(ar)), 4),
+            "plan_seconds_measured": round(sum(r["plan_s_measured"] for r in rows), 2),
+            "plan_seconds_learned": round(sum(r["plan_s_learned"] for r in rows), 3),
+            "rows": rows}
 
 
 def main():
@@ -255,6 +290,9 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     timer = Timer(torch)
+    if args.only_learned:
+        print(json.dumps({"learned": learned_bench(A, synth, torch, args)}), flush=True)
+        return
     n = 1 << args.log2n
     spec = synth.config2_struct(n)
     st = A.Struct.from_spec(spec)
@@ -352,7 +390,7 @@ def main():
             torch.cuda.empty_cache()
         if args.learned:
             try:
-                line["learned"] = learned_bench(A, synth, torch)
+                line["learned"] = learned_bench(A, synth, torch, args)
             except Exception as e:
                 line["learned"] = {"error": repr(e)}
     print(json.dumps(line), flush=True)

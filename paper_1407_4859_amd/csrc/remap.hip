@@ -63,7 +63,8 @@ struct RArray {
   uint64_t tile_begin;  // global index of this array's first tile
   uint32_t R;           // records per tile
   uint32_t n_chunks;    // 16-byte chunks per tile
-  uint32_t nsg, ndg, nf, pad;
+  uint32_t nsg, ndg, nf;
+  uint32_t dword;  // every field is 4 or 8 bytes (word_field is filled)
   const RGroup *sgrp;
   const RGroup *dgrp;
   const RField *fld;
@@ -254,7 +255,18 @@ __global__ __launch_bounds__(kBlock) void remap_tail_kernel(const RArray *__rest
     if (off >= Rg.end) break;
     uint32_t word = 0;
     const uint64_t rel = off - D.base;
-    if (rel < D.bytes) {
+    if (rel < D.bytes && A.dword) {
+      // 4- and 8-byte fields: the dword belongs to one field; decode it once
+      const uint64_t w = rel >> 2, Sw = D.S >> 2;
+      const uint64_t q = w / (T * Sw);
+      const uint64_t within = w - q * T * Sw;
+      const RField &F = A.fld[A.word_field[D.word_off + (uint32_t)(within >> D.logT)]];
+      const uint64_t ew = F.e >> 2;
+      const uint64_t local = within - ((uint64_t)(F.dp >> 2) << D.logT);
+      const uint64_t rec = q * T + local / ew;
+      const uint64_t jj = local % ew;
+      if ((int64_t)rec < A.n) word = *reinterpret_cast<const uint32_t *>(src + src_addr(A, F, rec) + 4 * jj);
+    } else if (rel < D.bytes) {
       for (uint32_t bi = 0; bi < 4; ++bi) {
         const uint64_t byte = rel + bi;
         const uint64_t q = byte / tileB;
@@ -439,6 +451,7 @@ adha_status remap_prepare(Ctx *ctx, const std::vector<const LayoutDesc *> &src_l
     Q.arr.nsg = (uint32_t)sg.size();
     Q.arr.ndg = (uint32_t)dg.size();
     Q.arr.nf = (uint32_t)F;
+    Q.arr.dword = B.dword_fields() ? 1u : 0u;
     Q.sg_at = blob.add(sg.data(), sg.size() * sizeof(RGroup));
     Q.dg_at = blob.add(dg.data(), dg.size() * sizeof(RGroup));
     Q.fl_at = blob.add(fl.data(), fl.size() * sizeof(RField));

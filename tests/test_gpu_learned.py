@@ -1,0 +1,43 @@
+"""The learned cost model against the method without it.
+
+Plans of seeded 8-section programs are scored under the measured tables (the
+enumeration's ground truth).  The network trained on the device's own
+timings must plan within a few percent of the enumeration optimum, in a
+fraction of the planning time, and no worse than the analytic bytes model
+that stands in for it when there is no network."""
+import numpy as np
+import pytest
+
+from oracle import planner as OP
+from paper_1407_4859_amd import adha as A
+from paper_1407_4859_amd import synth
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_learned_costs_plan_close_to_measured_enumeration():
+    ctx = A.Ctx(0)
+    rep = A.costmodel_train(ctx, A.train_opts(n_samples=2500, epochs=200, min_log2_n=15, max_log2_n=19, reps=3,
+                                              seed=11))
+    say("train", rep)
+    rows = []
+    for seed in range(40, 46):
+        n = 1 << (18 + seed % 2)
+        spec = synth.config3_struct(n)
+        st = A.Struct.from_spec(spec)
+        prog = A.Program(st, [A.Section.from_spec(st, s) for s in synth.random_program(seed, 32)])
+        idx = synth.uniform_index_torch(seed, 999, n * 16, n, "cuda")
+        pm = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_MEASURED, reps=3), idx=idx)
+        pl = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_LEARNED), idx=idx)
+        pa = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_ANALYTIC))
+        T, R = pm.tables()
+        rows.append((OP.path_cost(T, R, pl.choices()) / pm.cost, OP.path_cost(T, R, pa.choices()) / pm.cost,
+                     pm.seconds, pl.seconds))
+        say("program", seed, "learned", rows[-1][0], "analytic", rows[-1][1], "plan s", rows[-1][2:])
+    lr = np.array([r[0] for r in rows])
+    ar = np.array([r[1] for r in rows])
+    say("learned mean", lr.mean(), "max", lr.max(), "analytic mean", ar.mean(), "max", ar.max())
+    assert lr.mean() <= 1.10 and lr.max() <= 1.25
+    assert lr.mean() <= ar.mean() + 0.02
+    assert sum(r[3] for r in rows) * 10 < sum(r[2] for r in rows)
