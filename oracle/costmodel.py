@@ -20,9 +20,11 @@ layouts costs 4 us + 2 * N * S / 5.6e6.
 
 Features (16 values, float32, fixed scaling):
   log2 N / 24, |R| / 16, |W| / 2, d / 32, log2(1 + read bytes) / 8,
-  log2(1 + write bytes) / 8, 4-byte reads / 16, 8-byte reads / 16,
-  4-byte writes / 2, 8-byte writes / 2, one-hot layout class (AoS, SoA,
-  tiled, grouped), groups touched / 16, log2(effective bytes) / 12.
+  log2(1 + write bytes) / 8, groups holding R / 16, groups holding W / 2,
+  whether a gather's reads share one interleaved group spanning <= 64 bytes
+  (fetched whole per neighbour), those wide loads per neighbour / 16,
+  one-hot layout class (AoS, SoA, tiled, grouped), share of read fields in
+  tiled groups, log2(effective bytes) / 12.
 Layout classes: one interleaved group = AoS; one tiled group = tiled; only
 one-field groups = SoA; otherwise tiled if any group is tiled, else grouped.
 """
@@ -89,17 +91,40 @@ def layout_class(L) -> int:
     return 2 if any(t > 1 for _, t in L.groups) else 3
 
 
+def span_loads(read, degree, L) -> int:
+    """Wide loads per neighbour of a gather whose reads all sit in one
+    interleaved group spanning at most 64 bytes (A-byte loads, A the largest
+    of 16, 8, 4 dividing the group record); 0 when that does not apply."""
+    if degree == 0 or not read:
+        return 0
+    groups = {L.group_of[f] for f in read}
+    if len(groups) != 1:
+        return 0
+    g = groups.pop()
+    if L.groups[g][1] != 1:
+        return 0
+    S = L.S[g]
+    lo = min(L.p[f] for f in read)
+    hi = max(L.p[f] + L.elem_bytes[f] for f in read)
+    A = 16 if S % 16 == 0 else 8 if S % 8 == 0 else 4
+    lo_a = lo // A * A
+    nvec = -(-(hi - lo_a) // A)
+    return 0 if nvec * A // 4 > 16 else nvec
+
+
 def features(read, write, degree, L, spec=None):
     eb = L.elem_bytes
     rb = sum(eb[f] for f in read)
     wb = sum(eb[f] for f in write)
     cls = layout_class(L)
-    groups = {L.group_of[f] for f in list(read) + list(write)}
+    rg = {L.group_of[f] for f in read}
+    wg = {L.group_of[f] for f in write}
+    tiled = sum(1 for f in read if L.groups[L.group_of[f]][1] > 1)
+    sl = span_loads(read, degree, L)
     v = [math.log2(max(1, L.n)) / 24.0, len(read) / 16.0, len(write) / 2.0, degree / 32.0,
          math.log2(1.0 + rb) / 8.0, math.log2(1.0 + wb) / 8.0,
-         sum(1 for f in read if eb[f] != 8) / 16.0, sum(1 for f in read if eb[f] == 8) / 16.0,
-         sum(1 for f in write if eb[f] != 8) / 2.0, sum(1 for f in write if eb[f] == 8) / 2.0,
+         len(rg) / 16.0, len(wg) / 2.0, float(sl > 0), sl / 16.0,
          float(cls == 0), float(cls == 1), float(cls == 2), float(cls == 3),
-         len(groups) / 16.0,
+         tiled / len(read) if read else 0.0,
          math.log2(max(1.0, bytes_per_record(read, write, degree, L))) / 12.0]
     return np.array(v, np.float64).astype(np.float32)

@@ -164,9 +164,11 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
 // ------------------------------------------------------------------ MLP
 adha_status mlp_forward(Ctx *ctx, const float *params, const float *x, uint32_t batch, float *y,
                         hipStream_t stream);
+// scratch holds scratch_floats floats; the call fails (before any launch)
+// when the batch needs more than that (mlp_scratch_floats(batch)).
 adha_status mlp_backward(Ctx *ctx, const float *params, const float *x, const float *target,
                          uint32_t batch, float *grad, float *loss, float *scratch,
-                         hipStream_t stream);
+                         size_t scratch_floats, hipStream_t stream);
 adha_status mlp_adam(Ctx *ctx, float *params, const float *grad, float *m, float *v, float lr,
                      float b1, float b2, float eps, uint32_t t, hipStream_t stream);
 size_t mlp_scratch_floats(uint32_t batch);

@@ -20,27 +20,49 @@ adha_status fill_uniform_index(int32_t *idx, uint64_t count, int64_t n, uint64_t
 std::vector<std::vector<int>> ods_parts(const std::vector<SectionDesc> &secs, size_t first, size_t last,
                                         const Shape &sh, uint32_t cap);
 
+// Wide loads per neighbour when a gather's reads all sit in one interleaved
+// group and span at most 64 bytes (the span-gather kernel); 0 otherwise.
+static uint32_t span_loads(const SectionDesc &s, const LayoutDesc &l) {
+  if (s.degree == 0 || s.rd.empty()) return 0;
+  const uint32_t g = l.group_of[s.rd[0]];
+  for (int f : s.rd)
+    if (l.group_of[f] != g) return 0;
+  const Group &G = l.groups[g];
+  if (G.T != 1) return 0;
+  uint32_t lo = ~0u, hi = 0;
+  for (int f : s.rd) {
+    lo = std::min(lo, l.p[f]);
+    hi = std::max(hi, l.p[f] + l.shape.ebytes[f]);
+  }
+  const uint32_t A = G.S % 16 == 0 ? 16 : G.S % 8 == 0 ? 8 : 4;
+  const uint32_t lo_a = lo / A * A, nvec = (hi - lo_a + A - 1) / A;
+  return nvec * A / 4 > 16 ? 0 : nvec;
+}
+
 // Features (all scaled to roughly [0, 1]):
 //  0 log2 N / 24            1 |R| / 16               2 |W| / 2
 //  3 d / 32                 4 log2(1 + read bytes) / 8   5 log2(1 + write bytes) / 8
-//  6 4-byte reads / 16      7 8-byte reads / 16      8 4-byte writes / 2
-//  9 8-byte writes / 2      10..13 layout class one-hot (AoS, SoA, tiled, grouped)
-//  14 groups touched / 16   15 log2(analytic bytes per record) / 12
+//  6 groups holding R / 16  7 groups holding W / 2
+//  8 span gather applies    9 span loads per neighbour / 16
+//  10..13 layout class one-hot (AoS, SoA, tiled, grouped)
+//  14 share of read fields in tiled groups
+//  15 log2(analytic bytes per record) / 12
 void section_features(const SectionDesc &s, const LayoutDesc &l, float *out) {
-  double rb = 0, wb = 0, r4 = 0, r8 = 0, w4 = 0, w8 = 0;
+  double rb = 0, wb = 0, tiled = 0;
   for (int f : s.rd) {
     rb += l.shape.ebytes[f];
-    (l.shape.ebytes[f] == 8 ? r8 : r4) += 1;
+    if (l.groups[l.group_of[f]].T > 1) tiled += 1;
   }
-  for (int f : s.wr) {
-    wb += l.shape.ebytes[f];
-    (l.shape.ebytes[f] == 8 ? w8 : w4) += 1;
+  for (int f : s.wr) wb += l.shape.ebytes[f];
+  std::vector<char> rg(l.groups.size(), 0), wg(l.groups.size(), 0);
+  for (int f : s.rd) rg[l.group_of[f]] = 1;
+  for (int f : s.wr) wg[l.group_of[f]] = 1;
+  double nrg = 0, nwg = 0;
+  for (size_t g = 0; g < l.groups.size(); ++g) {
+    nrg += rg[g];
+    nwg += wg[g];
   }
-  std::vector<char> touched(l.groups.size(), 0);
-  for (int f : s.rd) touched[l.group_of[f]] = 1;
-  for (int f : s.wr) touched[l.group_of[f]] = 1;
-  double ng = 0;
-  for (char c : touched) ng += c;
+  const uint32_t sl = span_loads(s, l);
   const int cls = l.layout_class();
   const double v[ADHA_N_FEATURES] = {
       std::log2((double)std::max<int64_t>(1, l.shape.n)) / 24.0,
@@ -49,15 +71,15 @@ void section_features(const SectionDesc &s, const LayoutDesc &l, float *out) {
       s.degree / 32.0,
       std::log2(1.0 + rb) / 8.0,
       std::log2(1.0 + wb) / 8.0,
-      r4 / 16.0,
-      r8 / 16.0,
-      w4 / 2.0,
-      w8 / 2.0,
+      nrg / 16.0,
+      nwg / 2.0,
+      sl ? 1.0 : 0.0,
+      sl / 16.0,
       cls == 0 ? 1.0 : 0.0,
       cls == 1 ? 1.0 : 0.0,
       cls == 2 ? 1.0 : 0.0,
       cls == 3 ? 1.0 : 0.0,
-      ng / 16.0,
+      s.rd.empty() ? 0.0 : tiled / (double)s.rd.size(),
       std::log2(std::max(1.0, analytic_bytes_per_record(s, l))) / 12.0};
   for (int i = 0; i < ADHA_N_FEATURES; ++i) out[i] = (float)v[i];
 }
@@ -130,13 +152,23 @@ static SectionDesc random_section(Rng &g, const Shape &sh) {
 }
 
 static LayoutDesc random_layout(Rng &g, const Shape &sh, const SectionDesc &sec) {
-  switch (g.below(6)) {
+  switch (g.below(8)) {
     case 0: return layout_aos(sh);
     case 1: return layout_soa(sh);
     case 2: return layout_aos(sh, 64);
     case 3: {
       static const uint32_t caps[] = {16, 32, 64, 128};
       auto parts = ods_parts({sec}, 0, 0, sh, caps[g.below(4)]);
+      return layout_from_parts(sh, parts, g.below(2) ? 64 : 1);
+    }
+    case 4:
+    case 5: {
+      // the kind of layout the planner's catalogue holds: the ODS of a run of
+      // sections that includes this one
+      std::vector<SectionDesc> run;
+      const uint32_t others = 1 + g.below(3), at = g.below(others + 1);
+      for (uint32_t q = 0; q <= others; ++q) run.push_back(q == at ? sec : random_section(g, sh));
+      auto parts = ods_parts(run, 0, run.size() - 1, sh, 64);
       return layout_from_parts(sh, parts, g.below(2) ? 64 : 1);
     }
     default: {
@@ -193,7 +225,7 @@ adha_status adha_mlp_backward(adha_ctx *ctx, const float *params, const float *x
   hipStream_t st = (hipStream_t)stream;
   float *s = nullptr;
   ADHA_HIP(hipMallocAsync((void **)&s, mlp_scratch_floats(batch) * 4, st));
-  adha_status r = mlp_backward(&ctx->c, params, x, target, batch, grad, loss, s, st);
+  adha_status r = mlp_backward(&ctx->c, params, x, target, batch, grad, loss, s, mlp_scratch_floats(batch), st);
   (void)hipFreeAsync(s, st);
   return r;
 }
@@ -298,8 +330,11 @@ adha_status adha_costmodel_train(adha_ctx *ctx, const adha_train_opts *o, adha_t
   }
   float *dP = nullptr, *dG = nullptr, *dM = nullptr, *dV = nullptr, *dX = nullptr, *dY = nullptr, *dS = nullptr,
         *dL = nullptr;
+  // scratch for the largest batch any call below uses: the mini-batches (B),
+  // the whole training set (train loss) and the validation set
+  const size_t scratch_floats = mlp_scratch_floats(std::max(std::max(B, nval), ntr));
   size_t need[8] = {ADHA_MLP_PARAMS, ADHA_MLP_PARAMS, ADHA_MLP_PARAMS, ADHA_MLP_PARAMS, X.size(), Y.size(),
-                    mlp_scratch_floats(std::max(B, nval)), 4};
+                    scratch_floats, 4};
   float **ptrs[8] = {&dP, &dG, &dM, &dV, &dX, &dY, &dS, &dL};
   adha_status result = ADHA_OK;
   for (int q = 0; q < 8; ++q)
@@ -313,12 +348,12 @@ adha_status adha_costmodel_train(adha_ctx *ctx, const adha_train_opts *o, adha_t
     uint32_t step = 0;
     for (uint32_t ep = 0; ep < o->epochs && result >= 0; ++ep)
       for (uint32_t b0 = 0; b0 + B <= ntr && result >= 0; b0 += B) {
-        result = mlp_backward(c, dP, dX + (size_t)b0 * ADHA_N_FEATURES, dY + b0, B, dG, dL, dS, st);
+        result = mlp_backward(c, dP, dX + (size_t)b0 * ADHA_N_FEATURES, dY + b0, B, dG, dL, dS, scratch_floats, st);
         if (result >= 0) result = mlp_adam(c, dP, dG, dM, dV, o->lr, 0.9f, 0.999f, 1e-8f, ++step, st);
       }
     float tl = 0.f;
     if (result >= 0) {
-      result = mlp_backward(c, dP, dX, dY, ntr, dG, dL, dS, st);
+      result = mlp_backward(c, dP, dX, dY, ntr, dG, dL, dS, scratch_floats, st);
       (void)hipStreamSynchronize(st);
       (void)hipMemcpy(&tl, dL, 4, hipMemcpyDeviceToHost);
     }

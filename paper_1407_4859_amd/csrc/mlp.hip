@@ -115,9 +115,12 @@ adha_status mlp_forward(Ctx *ctx, const float *params, const float *x, uint32_t 
 }
 
 adha_status mlp_backward(Ctx *ctx, const float *P, const float *x, const float *target, uint32_t B, float *grad,
-                         float *loss, float *s, hipStream_t st) {
+                         float *loss, float *s, size_t scratch_floats, hipStream_t st) {
   (void)ctx;
   if (B == 0) return fail(ADHA_ERR_INVALID, "batch must be positive");
+  if (mlp_scratch_floats(B) > scratch_floats)
+    return fail(ADHA_ERR_INVALID, "backward scratch holds %zu floats, a batch of %u needs %zu", scratch_floats, B,
+                mlp_scratch_floats(B));
   float *Z1 = s, *A1 = Z1 + B * kH, *Z2 = A1 + B * kH, *A2 = Z2 + B * kH, *Z3 = A2 + B * kH,
         *A3 = Z3 + B * kH, *y = A3 + B * kH, *d3 = y + B, *d2 = d3 + B, *d1 = d2 + B * kH, *d0 = d1 + B * kH;
   forward_into(P, x, B, Z1, A1, Z2, A2, Z3, A3, y, st);

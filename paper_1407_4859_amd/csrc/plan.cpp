@@ -260,7 +260,7 @@ struct DevBuf {
 static adha_status measured_costs(Ctx *ctx, const Shape &sh, const std::vector<SectionDesc> &secs,
                                   const std::vector<adha_layout *> &cands, uint32_t reps,
                                   const int32_t *idx_in, uint64_t idx_count, hipStream_t stream,
-                                  std::vector<double> *T, std::vector<double> *R) {
+                                  std::vector<double> *T, std::vector<double> *R, bool sections = true) {
   const size_t k = secs.size(), C = cands.size();
   uint64_t maxb = 0;
   uint32_t maxd = 0;
@@ -271,13 +271,13 @@ static adha_status measured_costs(Ctx *ctx, const Shape &sh, const std::vector<S
   ADHA_TRY(b.alloc(maxb));
   ADHA_HIP(hipMemsetAsync(a.p, 0, maxb, stream));
   const int32_t *idx = idx_in;
-  if (maxd > 0 && sh.n > 0 && (!idx_in || idx_count < (uint64_t)sh.n * maxd)) {
+  if (sections && maxd > 0 && sh.n > 0 && (!idx_in || idx_count < (uint64_t)sh.n * maxd)) {
     ADHA_TRY(ix.alloc((size_t)sh.n * maxd * 4));
     ADHA_TRY(fill_uniform_index((int32_t *)ix.p, (uint64_t)sh.n * maxd, sh.n, 0x5eedULL, stream));
     idx = (const int32_t *)ix.p;
   }
-  T->assign(k * C, 0.0);
-  for (size_t c = 0; c < C; ++c)
+  if (sections) T->assign(k * C, 0.0);
+  for (size_t c = 0; c < C && sections; ++c)
     for (size_t s = 0; s < k; ++s) {
       // a gather section's index array is [N][d]; a wider one is read as [N][d] too
       ADHA_TRY(time_us(stream, reps,
@@ -414,9 +414,10 @@ adha_status adha_plan_create(adha_ctx *ctx, const adha_program *p, const adha_pl
       std::vector<double> us;
       ADHA_TRY(predict_costs(&ctx->c, feats, &us, st));
       pl->T = us;
-      pl->R.assign(C * C, 0.0);
-      for (size_t a = 0; a < C; ++a)
-        for (size_t b = 0; b < C; ++b) pl->R[a * C + b] = analytic_remap_us(pl->cands[a]->d, pl->cands[b]->d);
+      // remap weights: a few measured whole-struct remaps (milliseconds of
+      // device time), the same figure the measured provider uses
+      ADHA_TRY(measured_costs(&ctx->c, p->shape, p->secs, pl->cands, std::max<uint32_t>(1, o->reps), idx,
+                              idx_count, st, &pl->T, &pl->R, false));
     }
   }
   if (src == ADHA_COST_ANALYTIC) {

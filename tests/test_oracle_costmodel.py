@@ -35,9 +35,21 @@ def test_features_by_hand():
     n = 1 << 18
     f = OC.features([0, 3], [4], 16, soa(n, eb))
     want = [18 / 24, 2 / 16, 1 / 2, 16 / 32, math.log2(13) / 8, math.log2(5) / 8,
-            1 / 16, 1 / 16, 1 / 2, 0.0, 0, 1, 0, 0, 3 / 16,
+            2 / 16, 1 / 2, 0.0, 0.0, 0, 1, 0, 0, 0.0,
             math.log2(16 * (67 + 71) + 4 + 64) / 12]
     assert np.array_equal(f, np.array(want, np.float64).astype(np.float32))
+    # reads {0, 3} in the interleaved group {0..3} (20-byte records, so 4-byte
+    # loads): the span runs over bytes 0..20, five loads per neighbour
+    L = from_partition(n, eb, [[0, 1, 2, 3]], 1)
+    g = OC.features([0, 3], [4], 16, L)
+    assert OC.span_loads([0, 3], 16, L) == 5 and g[8] == 1.0 and g[9] == np.float32(5 / 16)
+    assert g[6] == np.float32(1 / 16) and g[13] == 1.0
+    assert OC.span_loads([0, 3], 0, L) == 0                               # direct
+    assert OC.span_loads([0, 3], 16, from_partition(n, eb, [[0, 1, 2, 3]], 64)) == 0  # tiled
+    # 32-byte records with 16-byte loads: reads at bytes 20..28 need one load at 16..32
+    eb2 = [4, 4, 4, 4, 4, 8, 4]
+    L2 = from_partition(n, eb2, [[0, 1, 2, 3, 4, 5, 6]], 1)
+    assert OC.span_loads([5], 4, L2) == 1 and OC.span_loads([0, 6], 4, L2) == 2
     assert OC.layout_class(aos(n, eb)) == 0 and OC.layout_class(soa(n, eb)) == 1
     assert OC.layout_class(Layout(n, eb, [0] * 5, [64])) == 2
     assert OC.layout_class(from_partition(n, eb, [[0, 1]], 1)) == 3
