@@ -35,6 +35,25 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of one remap_tiles_kernel launch on this workload: rocprofv3
+# --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean over the remap
+# dispatches), each scaled by what the same counter reads for a plain 1 GiB
+# device copy (fetch 524311.4 KiB, write 1048576 KiB).  It holds only for the
+# kernel source it was taken on; any other source reports null.
+REMAP_TRAFFIC = {"source_sha1": "0353914cd5d84e2020971dcf1f4e27cfefa5a8d0",
+                 "fetch_kib": 2097220.2, "write_kib": 4194323.4,
+                 "copy_fetch_kib": 524311.4, "copy_write_kib": 1048576.0, "copy_bytes": 1 << 30}
+
+
+def remap_traffic_bytes():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1407_4859_amd", "csrc", "remap.hip"), "rb") as f:
+        if hashlib.sha1(f.read()).hexdigest() != REMAP_TRAFFIC["source_sha1"]:
+            return None
+    t = REMAP_TRAFFIC
+    kib = t["copy_bytes"] / 1024.0
+    return round((t["fetch_kib"] * kib / t["copy_fetch_kib"] + t["write_kib"] * kib / t["copy_write_kib"]) * 1024)
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -369,7 +388,8 @@ def main():
         "tuning": tuning,
         "shapes": {name: A.get_shape(ctx, sl, dl) for name, sl, _, dl, _ in pairs},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": remap_traffic_bytes() if args.log2n == 26 else None, "traffic_unit": "B per launch",
                      "kernel": "remap_tiles_kernel (persistent LDS-transposing remap)",
                      "per_launch_bytes": 2 * n * 64},
     }
