@@ -86,9 +86,10 @@ def parse():
     return ap.parse_args()
 
 
-def fill_fields(buf, spec, layout_o, seed, torch, synth):
-    """Write the seeded field values of every record into a device buffer laid
-    out as AoS (layout_o is the oracle's AoS layout, used only for offsets)."""
+def fill_fields(buf, spec, seed, torch, synth):
+    """Write the seeded field values of every record into a device buffer,
+    packed in field order (field f of record r at r * S + the sizes of the
+    fields before f)."""
     n = spec.n
     S = spec.record_bytes
     view = buf[: n * S].view(n, S)
@@ -174,8 +175,7 @@ def program_bench(A, synth, torch, timer, log2n):
     cap = max(aos_l.nbytes, soa_l.nbytes) + (1 << 26)
     buf_a = torch.empty(cap, dtype=torch.uint8, device="cuda")
     buf_b = torch.empty(cap, dtype=torch.uint8, device="cuda")
-    from oracle.layout import aos as oaos
-    fill_fields(buf_a, spec, oaos(n, spec.elem_bytes), 3, torch, synth)
+    fill_fields(buf_a, spec, 3, torch, synth)
     idx = synth.uniform_index_torch(3, 999, n * 16, n, "cuda")
     ctx = A.Ctx(0)
     log("program: planning (measured costs)")
@@ -208,7 +208,8 @@ def program_bench(A, synth, torch, timer, log2n):
         t_us = T[s][c]
         per.append({"section": s, "degree": secs[s].degree, "read": len(secs[s].read),
                     "write": len(secs[s].write), "layout": c, "us": round(t_us, 1),
-                    "alg_GBps": round(sec.bytes / (t_us * 1e3), 1)})
+                    "alg_GBps": round(sec.bytes / (t_us * 1e3), 1),
+                    "eff_GBps": round(sec.effective_bytes(plan.candidate(c)) / (t_us * 1e3), 1)})
     out["sections"] = per
     return out
 
@@ -260,7 +261,8 @@ def learned_bench(A, synth, torch, args):
     else:
         log("learned: generating and timing", args.train_samples, "sections")
         rep = A.costmodel_train(ctx, A.train_opts(n_samples=args.train_samples, epochs=args.train_epochs,
-                                                  min_log2_n=16, max_log2_n=23, reps=3))
+                                                  min_log2_n=16, max_log2_n=23, reps=3,
+                                                  progress_every=1000))
         rep = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.items()}
         if args.save_model:
             A.costmodel_save(ctx, args.save_model)
@@ -306,7 +308,6 @@ def main():
     import torch
     from paper_1407_4859_amd import adha as A
     from paper_1407_4859_amd import synth
-    from oracle.layout import aos as oaos, soa as osoa, Layout as OLayout
 
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
@@ -323,7 +324,7 @@ def main():
     ctx = A.Ctx(0)
     log("single remap: filling", n, "records")
     a = torch.empty(La.nbytes, dtype=torch.uint8, device="cuda")
-    fill_fields(a, spec, oaos(n, spec.elem_bytes), 2, torch, synth)
+    fill_fields(a, spec, 2, torch, synth)
     s = torch.empty(Ls.nbytes, dtype=torch.uint8, device="cuda")
     t = torch.empty(Lt.nbytes, dtype=torch.uint8, device="cuda")
     b = torch.empty(La.nbytes, dtype=torch.uint8, device="cuda")

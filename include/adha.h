@@ -251,6 +251,13 @@ adha_status adha_section_run(adha_ctx *ctx, const adha_section *sec, const adha_
 /* Algorithmic bytes one run moves: N*(read + write bytes) for direct
  * sections, N*(4*d + d*read + write bytes) for gathers. */
 adha_status adha_section_bytes(const adha_section *sec, uint64_t *out);
+/* Effective HBM bytes one run moves under layout l, counted in 64-byte
+ * access granules: a streamed group costs min(S_g, sum over touched fields
+ * of max(e_f, 64/T)) per record; a gathered neighbour costs the touched
+ * span of an interleaved group plus 63 bytes, else e_f + 63 per field; a
+ * gather also reads 4*d index bytes.  This is the analytic cost model's
+ * byte count (the unit of the gathers' transaction roofline). */
+adha_status adha_section_effective_bytes(const adha_section *sec, const adha_layout *l, double *out);
 
 /* ------------------------------------------------------------ programs */
 adha_status adha_program_create(const adha_struct *s, uint32_t k, const adha_section *const *secs,
@@ -360,6 +367,7 @@ typedef struct {
   uint64_t seed;
   int32_t min_log2_n, max_log2_n; /* record counts of generated sections */
   uint32_t reps;       /* timing: median of reps */
+  uint32_t progress_every; /* >0: one line on stderr per that many timed sections */
 } adha_train_opts;
 typedef struct {
   double gen_seconds, train_seconds;

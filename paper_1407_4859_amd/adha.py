@@ -61,7 +61,7 @@ class PlanOpts(ctypes.Structure):
 class TrainOpts(ctypes.Structure):
     _fields_ = [("n_samples", ctypes.c_uint32), ("epochs", ctypes.c_uint32), ("batch", ctypes.c_uint32),
                 ("lr", ctypes.c_float), ("seed", ctypes.c_uint64), ("min_log2_n", ctypes.c_int32),
-                ("max_log2_n", ctypes.c_int32), ("reps", ctypes.c_uint32)]
+                ("max_log2_n", ctypes.c_int32), ("reps", ctypes.c_uint32), ("progress_every", ctypes.c_uint32)]
 
 
 class TrainReport(ctypes.Structure):
@@ -110,6 +110,7 @@ _SIGS = {
     "adha_section_destroy": ([P], I32T),
     "adha_section_run": ([P, P, P, P, U64, P, U64, P], I32T),
     "adha_section_bytes": ([P, ctypes.POINTER(U64)], I32T),
+    "adha_section_effective_bytes": ([P, P, ctypes.POINTER(ctypes.c_double)], I32T),
     "adha_program_create": ([P, U32, P, PP], I32T),
     "adha_program_destroy": ([P], I32T),
     "adha_affinity": ([P, U32, U32, P], I32T),
@@ -313,6 +314,11 @@ class Section:
     def bytes(self) -> int:
         v = ctypes.c_uint64()
         check(lib().adha_section_bytes(self.h, ctypes.byref(v)))
+        return v.value
+
+    def effective_bytes(self, layout: Layout) -> float:
+        v = ctypes.c_double()
+        check(lib().adha_section_effective_bytes(self.h, layout.h, ctypes.byref(v)))
         return v.value
 
     def features(self, layout: Layout):

@@ -207,6 +207,13 @@ adha_status adha_features(const adha_section *sec, const adha_layout *l, float *
   return ADHA_OK;
 }
 
+adha_status adha_section_effective_bytes(const adha_section *sec, const adha_layout *l, double *out) {
+  if (!sec || !l || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (!sec->d.shape.same(l->d.shape)) return fail(ADHA_ERR_INVALID, "section and layout describe different structs");
+  *out = (double)l->d.shape.n * analytic_bytes_per_record(sec->d, l->d);
+  return ADHA_OK;
+}
+
 static bool dev_ok(const void *p) { return p && ((uintptr_t)p & 3u) == 0; }
 
 adha_status adha_mlp_forward(adha_ctx *ctx, const float *params, const float *x, uint32_t batch, float *y,
@@ -248,6 +255,7 @@ adha_status adha_train_opts_default(adha_train_opts *o) {
   o->min_log2_n = 16;
   o->max_log2_n = 22;
   o->reps = 3;
+  o->progress_every = 0;
   return ADHA_OK;
 }
 
@@ -305,6 +313,8 @@ adha_status adha_costmodel_train(adha_ctx *ctx, const adha_train_opts *o, adha_t
     section_features(sec, lay, f);
     X.insert(X.end(), f, f + ADHA_N_FEATURES);
     Y.push_back((float)std::log(std::max(1e-3, ts[ts.size() / 2])));
+    if (o->progress_every && (i + 1) % o->progress_every == 0)
+      std::fprintf(stderr, "costmodel: timed %u of %u sections\n", i + 1, o->n_samples);
   }
   (void)hipEventDestroy(ea);
   (void)hipEventDestroy(eb);

@@ -42,8 +42,13 @@ def _key(seed: int, stream: int) -> int:
 # ---------------------------------------------------------------- numpy side
 def splitmix64(seed: int, stream: int, start: int, count: int) -> np.ndarray:
     """Draws start..start+count-1 of (seed, stream) as uint64."""
+    return splitmix64_at(seed, stream, np.arange(start, start + count, dtype=np.uint64))
+
+
+def splitmix64_at(seed: int, stream: int, counters) -> np.ndarray:
+    """Draws number counters[k] of (seed, stream), for any counters, as uint64."""
     with np.errstate(over="ignore"):
-        i = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+        i = np.asarray(counters, dtype=np.uint64) + np.uint64(1)
         z = (np.uint64(_key(seed, stream)) + i) * np.uint64(GAMMA)
         z = (z ^ (z >> np.uint64(30))) * np.uint64(M1)
         z = (z ^ (z >> np.uint64(27))) * np.uint64(M2)
@@ -85,6 +90,17 @@ def decode(z: np.ndarray, dtype: int, elem_bytes: int = 4) -> np.ndarray:
 def field_values(seed: int, stream: int, n: int, dtype: int, elem_bytes: int = 4,
                  start: int = 0) -> np.ndarray:
     return decode(splitmix64(seed, stream, start, n), dtype, elem_bytes)
+
+
+def field_values_at(seed: int, stream: int, records, dtype: int, elem_bytes: int = 4) -> np.ndarray:
+    """Values of the given records only (same draws as field_values)."""
+    return decode(splitmix64_at(seed, stream, records), dtype, elem_bytes)
+
+
+def uniform_index_at(seed: int, stream: int, counters, n: int) -> np.ndarray:
+    """Draws number counters[k] of U[0, n), as uniform_index gives them."""
+    z = splitmix64_at(seed, stream, counters)
+    return (((z >> np.uint64(32)) * np.uint64(n)) >> np.uint64(32)).astype(np.int32)
 
 
 def uniform_index(seed: int, stream: int, count: int, n: int, start: int = 0) -> np.ndarray:

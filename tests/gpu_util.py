@@ -7,6 +7,7 @@ import torch
 
 from oracle.layout import Layout as OLayout
 from paper_1407_4859_amd import adha as A
+from paper_1407_4859_amd import synth
 
 
 def say(*a):
@@ -41,3 +42,21 @@ def mirror(st: A.Struct, O: OLayout) -> A.Layout:
 def first_diff(a: np.ndarray, b: np.ndarray):
     d = np.nonzero(a != b)[0]
     return None if d.size == 0 else (int(d[0]), int(a[d[0]]), int(b[d[0]]), int(d.size))
+
+
+def fill_aos_device(spec, seed: int, extra: int = 0):
+    """Device buffer holding the seeded values of every record packed in field
+    order (field f of record r at r * S + sum of the earlier element sizes),
+    drawn on the device by the torch form of the generator."""
+    n, S = spec.n, spec.record_bytes
+    t = torch.zeros(max(1, n * S + extra), dtype=torch.uint8, device="cuda")
+    view = t[: n * S].view(n, S)
+    chunk = 1 << 24
+    off = 0
+    for f, (dt, e) in enumerate(zip(spec.dtypes, spec.elem_bytes)):
+        for s in range(0, n, chunk):
+            c = min(chunk, n - s)
+            z = synth.splitmix64_torch(seed, f, s, c, "cuda")
+            view[s:s + c, off:off + e] = synth.decode_torch(z, dt, e)
+        off += e
+    return t

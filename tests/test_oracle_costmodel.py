@@ -80,3 +80,5 @@ def test_library_analytic_tables_and_features_match_oracle():
             got = np.array(sec.features(pl.candidate(c)), np.float32)
             want = OC.features(s.read, s.write, s.degree, cat[c])
             assert np.array_equal(got, want)
+            assert sec.effective_bytes(pl.candidate(c)) == pytest.approx(
+                spec.n * OC.bytes_per_record(s.read, s.write, s.degree, cat[c]), rel=1e-12)

@@ -26,6 +26,18 @@ def test_forms_agree():
             assert np.array_equal(d, dtt)
 
 
+def test_draws_at_counters_match_the_sequence():
+    rng = np.random.default_rng(0)
+    recs = rng.integers(0, 1 << 24, 300)
+    full = synth.splitmix64(3, 7, 0, 1 << 24)
+    assert np.array_equal(synth.splitmix64_at(3, 7, recs), full[recs])
+    for dt, e in ((synth.F32, 4), (synth.F64, 8), (synth.I32, 4)):
+        assert np.array_equal(synth.field_values_at(3, 7, recs, dt, e), synth.decode(full[recs], dt, e))
+    ix = synth.uniform_index(3, 999, 1 << 20, 12345)
+    c = rng.integers(0, 1 << 20, 500)
+    assert np.array_equal(synth.uniform_index_at(3, 999, c, 12345), ix[c])
+
+
 def test_value_ranges():
     f = synth.field_values(2, 0, 100000, synth.F32).view(np.float32)
     assert f.min() >= -1.0 and f.max() < 1.0
