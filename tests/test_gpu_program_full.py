@@ -47,9 +47,10 @@ def test_device_fill_is_the_packed_record_image():
     dev = fill_aos_device(spec, 3)
     want = synth.pack_aos(synth.record_matrix(3, 1000, spec.dtypes, spec.elem_bytes), 1000).reshape(-1)
     assert np.array_equal(dev.cpu().numpy(), want)
+    # the oracle's AoS image is the same bytes followed by zero padding to 256
     O = oaos(1000, spec.elem_bytes)
-    assert O.nbytes == want.size
-    assert np.array_equal(oracle.pack(O, synth.record_matrix(3, 1000, spec.dtypes, spec.elem_bytes)), want)
+    img = oracle.pack(O, synth.record_matrix(3, 1000, spec.dtypes, spec.elem_bytes))
+    assert O.nbytes == 144128 and np.array_equal(img[: want.size], want) and not img[want.size:].any()
 
 
 @pytest.mark.timeout(900)
