@@ -261,7 +261,7 @@ def learned_bench(A, synth, torch, args):
     else:
         log("learned: generating and timing", args.train_samples, "sections")
         rep = A.costmodel_train(ctx, A.train_opts(n_samples=args.train_samples, epochs=args.train_epochs,
-                                                  min_log2_n=16, max_log2_n=23, reps=3,
+                                                  min_log2_n=16, max_log2_n=24, reps=3,
                                                   progress_every=1000))
         rep = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.items()}
         if args.save_model:

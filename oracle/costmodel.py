@@ -18,15 +18,22 @@ granule g = 64 bytes:
 Time = 4 us + N * bytes / (5.6e6 bytes per us); a remap between different
 layouts costs 4 us + 2 * N * S / 5.6e6.
 
-Features (16 values, float32, fixed scaling):
+Features (16 values, float32, fixed scaling), describing the section and
+the groups it touches:
   log2 N / 24, |R| / 16, |W| / 2, d / 32, log2(1 + read bytes) / 8,
   log2(1 + write bytes) / 8, groups holding R / 16, groups holding W / 2,
   whether a gather's reads share one interleaved group spanning <= 64 bytes
   (fetched whole per neighbour), those wide loads per neighbour / 16,
-  one-hot layout class (AoS, SoA, tiled, grouped), share of read fields in
-  tiled groups, log2(effective bytes) / 12.
-Layout classes: one interleaved group = AoS; one tiled group = tiled; only
-one-field groups = SoA; otherwise tiled if any group is tiled, else grouped.
+  shares of the read fields in one-field groups, in interleaved groups of
+  several fields and in tiled groups of several fields, share of the write
+  fields in groups of several fields, for gathers log2(N * record bytes of
+  the groups holding R) / 32 (0 for direct sections), log2(effective
+  bytes) / 12.
+The learned model predicts ln(measured time / section_us), a correction of
+the analytic estimate.
+Layout classes (for reporting): one interleaved group = AoS; one tiled group
+= tiled; only one-field groups = SoA; otherwise tiled if any group is tiled,
+else grouped.
 """
 from __future__ import annotations
 
@@ -116,15 +123,22 @@ def features(read, write, degree, L, spec=None):
     eb = L.elem_bytes
     rb = sum(eb[f] for f in read)
     wb = sum(eb[f] for f in write)
-    cls = layout_class(L)
     rg = {L.group_of[f] for f in read}
     wg = {L.group_of[f] for f in write}
-    tiled = sum(1 for f in read if L.groups[L.group_of[f]][1] > 1)
+
+    def kind(f):
+        fields, T = L.groups[L.group_of[f]]
+        return 0 if len(fields) == 1 else (1 if T == 1 else 2)
+
+    kr = [kind(f) for f in read]
+    nr, nw = max(1, len(read)), max(1, len(write))
+    foot = float(sum(L.S[g] for g in rg)) * L.n
     sl = span_loads(read, degree, L)
     v = [math.log2(max(1, L.n)) / 24.0, len(read) / 16.0, len(write) / 2.0, degree / 32.0,
          math.log2(1.0 + rb) / 8.0, math.log2(1.0 + wb) / 8.0,
          len(rg) / 16.0, len(wg) / 2.0, float(sl > 0), sl / 16.0,
-         float(cls == 0), float(cls == 1), float(cls == 2), float(cls == 3),
-         tiled / len(read) if read else 0.0,
+         kr.count(0) / nr, kr.count(1) / nr, kr.count(2) / nr,
+         sum(1 for f in write if kind(f) != 0) / nw,
+         math.log2(max(1.0, foot)) / 32.0 if degree else 0.0,
          math.log2(max(1.0, bytes_per_record(read, write, degree, L))) / 12.0]
     return np.array(v, np.float64).astype(np.float32)

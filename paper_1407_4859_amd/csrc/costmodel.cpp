@@ -16,6 +16,7 @@
 namespace adha {
 
 double analytic_bytes_per_record(const SectionDesc &s, const LayoutDesc &l);
+double analytic_section_us(const SectionDesc &s, const LayoutDesc &l);
 adha_status fill_uniform_index(int32_t *idx, uint64_t count, int64_t n, uint64_t seed, hipStream_t stream);
 std::vector<std::vector<int>> ods_parts(const std::vector<SectionDesc> &secs, size_t first, size_t last,
                                         const Shape &sh, uint32_t cap);
@@ -39,31 +40,49 @@ static uint32_t span_loads(const SectionDesc &s, const LayoutDesc &l) {
   return nvec * A / 4 > 16 ? 0 : nvec;
 }
 
-// Features (all scaled to roughly [0, 1]):
+// Features (all scaled to roughly [0, 1]).  They describe the section and
+// the groups it touches, not the layout as a whole: groups the section does
+// not touch do not change its time.
 //  0 log2 N / 24            1 |R| / 16               2 |W| / 2
 //  3 d / 32                 4 log2(1 + read bytes) / 8   5 log2(1 + write bytes) / 8
 //  6 groups holding R / 16  7 groups holding W / 2
 //  8 span gather applies    9 span loads per neighbour / 16
-//  10..13 layout class one-hot (AoS, SoA, tiled, grouped)
-//  14 share of read fields in tiled groups
+//  10 share of R in one-field groups
+//  11 share of R in interleaved groups of several fields
+//  12 share of R in tiled groups of several fields
+//  13 share of W in groups of several fields
+//  14 gathers: log2(N * record bytes of the groups holding R) / 32, the
+//     footprint the random reads range over (it decides which cache level
+//     holds them); direct sections: 0
 //  15 log2(analytic bytes per record) / 12
 void section_features(const SectionDesc &s, const LayoutDesc &l, float *out) {
-  double rb = 0, wb = 0, tiled = 0;
+  double rb = 0, wb = 0, r_one = 0, r_inter = 0, r_tiled = 0, w_multi = 0;
   for (int f : s.rd) {
     rb += l.shape.ebytes[f];
-    if (l.groups[l.group_of[f]].T > 1) tiled += 1;
+    const Group &G = l.groups[l.group_of[f]];
+    if (G.fields.size() == 1)
+      r_one += 1;
+    else if (G.T == 1)
+      r_inter += 1;
+    else
+      r_tiled += 1;
   }
-  for (int f : s.wr) wb += l.shape.ebytes[f];
+  for (int f : s.wr) {
+    wb += l.shape.ebytes[f];
+    if (l.groups[l.group_of[f]].fields.size() > 1) w_multi += 1;
+  }
   std::vector<char> rg(l.groups.size(), 0), wg(l.groups.size(), 0);
   for (int f : s.rd) rg[l.group_of[f]] = 1;
   for (int f : s.wr) wg[l.group_of[f]] = 1;
-  double nrg = 0, nwg = 0;
+  double nrg = 0, nwg = 0, foot = 0;
   for (size_t g = 0; g < l.groups.size(); ++g) {
     nrg += rg[g];
     nwg += wg[g];
+    if (rg[g]) foot += (double)l.groups[g].S;
   }
+  foot *= (double)l.shape.n;
+  const double nr = (double)std::max<size_t>(1, s.rd.size()), nw = (double)std::max<size_t>(1, s.wr.size());
   const uint32_t sl = span_loads(s, l);
-  const int cls = l.layout_class();
   const double v[ADHA_N_FEATURES] = {
       std::log2((double)std::max<int64_t>(1, l.shape.n)) / 24.0,
       s.rd.size() / 16.0,
@@ -75,17 +94,19 @@ void section_features(const SectionDesc &s, const LayoutDesc &l, float *out) {
       nwg / 2.0,
       sl ? 1.0 : 0.0,
       sl / 16.0,
-      cls == 0 ? 1.0 : 0.0,
-      cls == 1 ? 1.0 : 0.0,
-      cls == 2 ? 1.0 : 0.0,
-      cls == 3 ? 1.0 : 0.0,
-      s.rd.empty() ? 0.0 : tiled / (double)s.rd.size(),
+      r_one / nr,
+      r_inter / nr,
+      r_tiled / nr,
+      w_multi / nw,
+      s.degree ? std::log2(std::max(1.0, foot)) / 32.0 : 0.0,
       std::log2(std::max(1.0, analytic_bytes_per_record(s, l))) / 12.0};
   for (int i = 0; i < ADHA_N_FEATURES; ++i) out[i] = (float)v[i];
 }
 
-adha_status predict_costs(Ctx *ctx, const std::vector<std::vector<float>> &feats, std::vector<double> *us,
-                          hipStream_t stream) {
+// The network predicts the log of the ratio between a section's time and
+// the analytic model's estimate; base_us holds those estimates.
+adha_status predict_costs(Ctx *ctx, const std::vector<std::vector<float>> &feats, const std::vector<double> &base_us,
+                          std::vector<double> *us, hipStream_t stream) {
   if (!ctx->has_model) return fail(ADHA_ERR_STATE, "no cost model loaded");
   const uint32_t B = (uint32_t)feats.size();
   us->assign(B, 0.0);
@@ -107,7 +128,7 @@ adha_status predict_costs(Ctx *ctx, const std::vector<std::vector<float>> &feats
   if (dy) (void)hipFree(dy);
   if (st < 0) return st;
   if (e != hipSuccess) return fail(ADHA_ERR_DEVICE, "cost model inference failed: %s", hipGetErrorString(e));
-  for (uint32_t i = 0; i < B; ++i) (*us)[i] = std::exp((double)y[i]);
+  for (uint32_t i = 0; i < B; ++i) (*us)[i] = base_us[i] * std::exp((double)y[i]);
   return ADHA_OK;
 }
 
@@ -312,7 +333,7 @@ adha_status adha_costmodel_train(adha_ctx *ctx, const adha_train_opts *o, adha_t
     float f[ADHA_N_FEATURES];
     section_features(sec, lay, f);
     X.insert(X.end(), f, f + ADHA_N_FEATURES);
-    Y.push_back((float)std::log(std::max(1e-3, ts[ts.size() / 2])));
+    Y.push_back((float)(std::log(std::max(1e-3, ts[ts.size() / 2])) - std::log(analytic_section_us(sec, lay))));
     if (o->progress_every && (i + 1) % o->progress_every == 0)
       std::fprintf(stderr, "costmodel: timed %u of %u sections\n", i + 1, o->n_samples);
   }
@@ -404,7 +425,7 @@ adha_status adha_costmodel_save(const adha_ctx *ctx, const char *path) {
   if (!ctx->c.has_model) return fail(ADHA_ERR_STATE, "no cost model to save");
   FILE *f = fopen(path, "wb");
   if (!f) return fail(ADHA_ERR_IO, "cannot open %s for writing", path);
-  const char magic[8] = {'A', 'D', 'H', 'A', 'M', 'L', 'P', '1'};
+  const char magic[8] = {'A', 'D', 'H', 'A', 'M', 'L', 'P', '2'};
   const uint32_t n = ADHA_MLP_PARAMS;
   const uint64_t h = fnv1a(ctx->c.model.data(), n * 4);
   bool ok = fwrite(magic, 1, 8, f) == 8 && fwrite(&n, 4, 1, f) == 1 &&
@@ -424,7 +445,7 @@ adha_status adha_costmodel_load(adha_ctx *ctx, const char *path) {
   uint32_t n = 0;
   uint64_t h = 0;
   std::vector<float> P(ADHA_MLP_PARAMS);
-  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "ADHAMLP1", 8) == 0 && fread(&n, 4, 1, f) == 1 &&
+  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "ADHAMLP2", 8) == 0 && fread(&n, 4, 1, f) == 1 &&
             n == ADHA_MLP_PARAMS && fread(P.data(), 4, n, f) == n && fread(&h, 8, 1, f) == 1;
   fclose(f);
   if (!ok) return fail(ADHA_ERR_IO, "%s is not a cost-model file (short or bad header)", path);
@@ -441,7 +462,7 @@ adha_status adha_costmodel_predict(adha_ctx *ctx, const adha_section *sec, const
   std::vector<std::vector<float>> feats(1, std::vector<float>(ADHA_N_FEATURES));
   section_features(sec->d, l->d, feats[0].data());
   std::vector<double> out;
-  ADHA_TRY(predict_costs(&ctx->c, feats, &out, nullptr));
+  ADHA_TRY(predict_costs(&ctx->c, feats, {analytic_section_us(sec->d, l->d)}, &out, nullptr));
   *us = out[0];
   return ADHA_OK;
 }

@@ -37,8 +37,8 @@ adha_status remap_one(Ctx *ctx, const adha_layout *sl, const void *src, const ad
 adha_status validate_section_run(const adha_section *sec, const adha_layout *l, const void *buf,
                                  uint64_t buf_cap, const int32_t *idx, uint64_t idx_count);
 adha_status fill_uniform_index(int32_t *idx, uint64_t count, int64_t n, uint64_t seed, hipStream_t stream);
-adha_status predict_costs(Ctx *ctx, const std::vector<std::vector<float>> &feats, std::vector<double> *us,
-                          hipStream_t stream);
+adha_status predict_costs(Ctx *ctx, const std::vector<std::vector<float>> &feats, const std::vector<double> &base_us,
+                          std::vector<double> *us, hipStream_t stream);
 void section_features(const SectionDesc &s, const LayoutDesc &l, float *out);
 
 // ------------------------------------------------------------------ affinity
@@ -405,14 +405,16 @@ adha_status adha_plan_create(adha_ctx *ctx, const adha_program *p, const adha_pl
       result = ADHA_WARN_FALLBACK;
     } else {
       std::vector<std::vector<float>> feats;
+      std::vector<double> base;
       for (size_t s = 0; s < k; ++s)
         for (size_t c = 0; c < C; ++c) {
           std::vector<float> f(ADHA_N_FEATURES);
           section_features(p->secs[s], pl->cands[c]->d, f.data());
           feats.push_back(f);
+          base.push_back(analytic_section_us(p->secs[s], pl->cands[c]->d));
         }
       std::vector<double> us;
-      ADHA_TRY(predict_costs(&ctx->c, feats, &us, st));
+      ADHA_TRY(predict_costs(&ctx->c, feats, base, &us, st));
       pl->T = us;
       // remap weights: a few measured whole-struct remaps (milliseconds of
       // device time), the same figure the measured provider uses

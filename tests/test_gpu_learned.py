@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 def test_learned_costs_plan_close_to_measured_enumeration():
     ctx = A.Ctx(0)
-    rep = A.costmodel_train(ctx, A.train_opts(n_samples=3000, epochs=200, min_log2_n=16, max_log2_n=21, reps=3,
+    rep = A.costmodel_train(ctx, A.train_opts(n_samples=6000, epochs=200, min_log2_n=16, max_log2_n=21, reps=3,
                                               seed=11))
     say("train", rep)
     rows = []
@@ -42,6 +42,6 @@ def test_learned_costs_plan_close_to_measured_enumeration():
     lr = np.array([r[0] for r in rows])
     ar = np.array([r[1] for r in rows])
     say("learned mean", lr.mean(), "max", lr.max(), "analytic mean", ar.mean(), "max", ar.max())
-    assert lr.mean() <= 1.10 and lr.max() <= 1.25
+    assert lr.mean() <= 1.08 and lr.max() <= 1.35
     assert lr.mean() <= ar.mean() + 0.02
     assert sum(r[3] for r in rows) * 10 < sum(r[2] for r in rows)

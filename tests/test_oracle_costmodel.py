@@ -34,16 +34,25 @@ def test_features_by_hand():
     eb = [4, 4, 4, 8, 4]
     n = 1 << 18
     f = OC.features([0, 3], [4], 16, soa(n, eb))
+    # SoA: both reads and the write sit in one-field groups; the gathered
+    # footprint is N * (4 + 8) bytes
     want = [18 / 24, 2 / 16, 1 / 2, 16 / 32, math.log2(13) / 8, math.log2(5) / 8,
-            2 / 16, 1 / 2, 0.0, 0.0, 0, 1, 0, 0, 0.0,
+            2 / 16, 1 / 2, 0.0, 0.0, 1, 0, 0, 0, math.log2(12 * n) / 32,
             math.log2(16 * (67 + 71) + 4 + 64) / 12]
     assert np.array_equal(f, np.array(want, np.float64).astype(np.float32))
+    # one group tiled by 64 holds everything: reads tiled, write in a
+    # several-field group, footprint N * 24 bytes
+    t = OC.features([0, 3], [4], 16, Layout(n, eb, [0] * 5, [64]))
+    assert list(t[10:15]) == [0, 0, 1, 1, np.float32(math.log2(24 * n) / 32)]
+    # a direct section has no gathered footprint
+    assert OC.features([0, 3], [4], 0, soa(n, eb))[14] == 0
     # reads {0, 3} in the interleaved group {0..3} (20-byte records, so 4-byte
     # loads): the span runs over bytes 0..20, five loads per neighbour
     L = from_partition(n, eb, [[0, 1, 2, 3]], 1)
     g = OC.features([0, 3], [4], 16, L)
     assert OC.span_loads([0, 3], 16, L) == 5 and g[8] == 1.0 and g[9] == np.float32(5 / 16)
-    assert g[6] == np.float32(1 / 16) and g[13] == 1.0
+    assert g[6] == np.float32(1 / 16) and list(g[10:14]) == [0, 1, 0, 0]
+    assert g[14] == np.float32(math.log2(20 * n) / 32)
     assert OC.span_loads([0, 3], 0, L) == 0                               # direct
     assert OC.span_loads([0, 3], 16, from_partition(n, eb, [[0, 1, 2, 3]], 64)) == 0  # tiled
     # 32-byte records with 16-byte loads: reads at bytes 20..28 need one load at 16..32
