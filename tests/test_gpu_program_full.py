@@ -92,8 +92,10 @@ def test_config3_full_size_plans_match_oracle(ctx):
         buf_a[: La.nbytes].copy_(src)
         out_h, in_b = A.run(ctx, plan, La, buf_a, buf_b, idx)
         ctx.check()
-        out_l = [plan.candidate(c) for c in range(plan.n_candidates) if plan.candidate(c).h.value == out_h]
-        assert len(out_l) == 1
+        # the data ends in one of the plan's layouts, or stays in the input
+        # layout when the plan never leaves it
+        out_l = [L for L in [La] + [plan.candidate(c) for c in range(plan.n_candidates)] if L.h.value == out_h]
+        assert len(out_l) >= 1
         res = buf_b if in_b else buf_a
         if out_l[0].equals(La):
             got = res[: La.nbytes].cpu().numpy()
