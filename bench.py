@@ -78,6 +78,9 @@ def parse():
     ap.add_argument("--save-model", default=None)
     ap.add_argument("--load-model", default=None)
     ap.add_argument("--only-remap", action="store_true", help="timed steps only (for profiling)")
+    ap.add_argument("--only-program", action="store_true", help="the program leg only (for profiling)")
+    ap.add_argument("--program-cost", choices=["measured", "analytic"], default="measured",
+                    help="cost tables of the program leg's plan (analytic: no timing runs while planning)")
     ap.add_argument("--no-tune", action="store_true", help="use the default tile shapes")
     ap.add_argument("--save-tune", default=None, help="write the tuning database here after tuning")
     ap.add_argument("--load-tune", default=None, help="load a tuning database instead of tuning")
@@ -163,7 +166,7 @@ def cpu_baseline(synth):
                       f"{cores} threads over record ranges; {t * 1e3:.0f} ms"}
 
 
-def program_bench(A, synth, torch, timer, log2n):
+def program_bench(A, synth, torch, timer, log2n, cost="measured"):
     n = 1 << log2n
     spec = synth.config3_struct(n)
     st = A.Struct.from_spec(spec)
@@ -178,10 +181,10 @@ def program_bench(A, synth, torch, timer, log2n):
     fill_fields(buf_a, spec, 3, torch, synth)
     idx = synth.uniform_index_torch(3, 999, n * 16, n, "cuda")
     ctx = A.Ctx(0)
-    log("program: planning (measured costs)")
+    log("program: planning (%s costs)" % cost)
     t0 = time.perf_counter()
-    plan = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_MEASURED, catalogue=A.CAT_FULL, cap_bytes=64, reps=3),
-                         idx=idx)
+    src = A.COST_MEASURED if cost == "measured" else A.COST_ANALYTIC
+    plan = A.Plan.create(ctx, prog, A.plan_opts(cost=src, catalogue=A.CAT_FULL, cap_bytes=64, reps=3), idx=idx)
     plan_s = time.perf_counter() - t0
     analytic = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_ANALYTIC, catalogue=A.CAT_FULL, cap_bytes=64))
     plans = {"adha": plan, "all_aos": A.Plan.uniform(prog, aos_l), "all_soa": A.Plan.uniform(prog, soa_l),
@@ -201,15 +204,19 @@ def program_bench(A, synth, torch, timer, log2n):
     out["speedup_vs_best_uniform"] = round(best_base / out["adha_ms"], 3)
     out["adha_beats_both"] = out["adha_ms"] < best_base
     out["predicted_adha_ms"] = round(plan.cost / 1e3, 3)
-    # per-section kernel GB/s under the chosen layouts
+    # per-section kernel time under the chosen layouts (HIP events around
+    # each launch; timings do not depend on the buffer's values)
     per = []
-    T, _ = plan.tables()
     for s, (sec, c) in enumerate(zip(ss, plan.choices())):
-        t_us = T[s][c]
+        lay = plan.candidate(c)
+        ms, _ = timer.time(lambda: A.section_run(ctx, sec, lay, buf_a, idx if secs[s].degree else None),
+                           reps=7, warm=1)
+        t_us = ms * 1e3
         per.append({"section": s, "degree": secs[s].degree, "read": len(secs[s].read),
                     "write": len(secs[s].write), "layout": c, "us": round(t_us, 1),
                     "alg_GBps": round(sec.bytes / (t_us * 1e3), 1),
-                    "eff_GBps": round(sec.effective_bytes(plan.candidate(c)) / (t_us * 1e3), 1)})
+                    "eff_GBps": round(sec.effective_bytes(lay) / (t_us * 1e3), 1)})
+    ctx.check()
     out["sections"] = per
     return out
 
@@ -315,6 +322,10 @@ def main():
     timer = Timer(torch)
     if args.only_learned:
         print(json.dumps({"learned": learned_bench(A, synth, torch, args)}), flush=True)
+        return
+    if args.only_program:
+        print(json.dumps({"program": program_bench(A, synth, torch, timer, args.program_log2n, args.program_cost)}),
+              flush=True)
         return
     n = 1 << args.log2n
     spec = synth.config2_struct(n)
