@@ -74,7 +74,13 @@ typedef enum { ADHA_F32 = 0, ADHA_F64 = 1, ADHA_I32 = 2, ADHA_RAW = 3 } adha_dty
  *   SUB2:       w = a - b, read set {a < b}, direct only;
  *   SUM:        w = ((t0 + t1) + ...) left to right, direct only.
  * MULADD3, SUB2 and SUM need one fp write field. */
-typedef enum { ADHA_OP_GEN = 0, ADHA_OP_MULADD3 = 1, ADHA_OP_SUB2 = 2, ADHA_OP_SUM = 3 } adha_op;
+typedef enum {
+  ADHA_OP_GEN = 0,
+  ADHA_OP_MULADD3 = 1,
+  ADHA_OP_SUB2 = 2,
+  ADHA_OP_SUM = 3,
+  ADHA_OP_REDUCE = 4 /* a reduction over the records: adha_section_create_reduce */
+} adha_op;
 
 #define ADHA_MAX_FIELDS 64
 #define ADHA_MAX_READ 32
@@ -82,6 +88,7 @@ typedef enum { ADHA_OP_GEN = 0, ADHA_OP_MULADD3 = 1, ADHA_OP_SUB2 = 2, ADHA_OP_S
 #define ADHA_MAX_DEGREE 32
 #define ADHA_MAX_TILE 256
 #define ADHA_MAX_SECTIONS 64
+#define ADHA_MAX_REDUCE_CELLS 4096 /* n_keys * (n_read + 1) of a reduction */
 
 typedef struct adha_ctx adha_ctx;
 typedef struct adha_struct adha_struct;
@@ -104,8 +111,9 @@ int32_t adha_version(void);
 adha_status adha_ctx_create(int32_t device, adha_ctx **out);
 adha_status adha_ctx_destroy(adha_ctx *ctx);
 /* Waits for `stream`, then reports: ERR_DEVICE on a HIP error, ERR_INVALID
- * if a gather section met an index outside [0, N) since the last check
- * (such terms are skipped), else OK.  Clears the gather-index flag. */
+ * if a gather section met an index outside [0, N) or a reduction a key
+ * outside [0, n_keys) since the last check (such terms or records are
+ * left out), else OK.  Clears that flag. */
 adha_status adha_ctx_check(adha_ctx *ctx, void *stream);
 /* Number of compute units (used to size persistent launches). */
 adha_status adha_ctx_cu_count(const adha_ctx *ctx, int32_t *out);
@@ -238,10 +246,32 @@ adha_status adha_tune_load(adha_ctx *ctx, const char *path);
 /* A section (section 2: one data-parallel loop) reading n_read fields and
  * writing n_write fields, direct (degree 0) or gathering `degree` neighbours
  * per record through an int32 index array [N][degree].  Gather sections
- * must not write a field they read.  Ids are sorted internally. */
+ * must not write a field they read.  Ids are sorted internally.  op is
+ * GEN, MULADD3, SUB2 or SUM; reductions come from adha_section_create_reduce. */
 adha_status adha_section_create(const adha_struct *s, adha_op op, uint32_t n_read,
                                 const int32_t *read, uint32_t n_write, const int32_t *write,
                                 uint32_t degree, adha_section **out);
+/* A reduction section (section 3: the second K-Means section reduces all
+ * the features over the points).  It reads n_read fields (F32, F64 or I32)
+ * of every record and, when key_field >= 0, the I32 key field, and adds
+ * the values of the records whose key is k into row k of a table of
+ * n_keys rows of n_read + 1 eight-byte cells, written to the device array
+ * `out` (caller-owned, 256-byte aligned, out_cap >= n_keys*(n_read+1)*8):
+ *   cell [k][j], j < n_read: the sum over those records of read field j
+ *     (ascending id): an IEEE double for F32/F64 fields, accumulated in
+ *     double; a two's-complement int64 for I32 fields (exact);
+ *   cell [k][n_read]: the number of those records (uint64).
+ * Without a key every record has key 0 and n_keys must be 1.  Records whose
+ * key is outside [0, n_keys) are left out and reported by adha_ctx_check.
+ * Double sums are exact when every partial sum is a double (for example
+ * F32 values that are multiples of 2^-23 with partial sums below 2^30 in
+ * magnitude); otherwise they lie within (m-1)*2^-53 * sum|x| of the exact
+ * sum of the m values (any summation order).
+ * n_keys*(n_read+1) <= ADHA_MAX_REDUCE_CELLS.  The key may not be read.
+ * Each run overwrites the whole table; `out` must not overlap the data. */
+adha_status adha_section_create_reduce(const adha_struct *s, uint32_t n_read, const int32_t *read,
+                                       int32_t key_field, uint32_t n_keys, void *out, uint64_t out_cap,
+                                       adha_section **out_sec);
 adha_status adha_section_destroy(adha_section *sec);
 /* Runs the section in place on buf laid out by l.  idx (device, int32,
  * idx_count >= N*degree) is needed only for gather sections. */
@@ -249,7 +279,8 @@ adha_status adha_section_run(adha_ctx *ctx, const adha_section *sec, const adha_
                              void *buf, uint64_t buf_cap, const int32_t *idx, uint64_t idx_count,
                              void *stream);
 /* Algorithmic bytes one run moves: N*(read + write bytes) for direct
- * sections, N*(4*d + d*read + write bytes) for gathers. */
+ * sections, N*(4*d + d*read + write bytes) for gathers, N*(read + key
+ * bytes) for reductions. */
 adha_status adha_section_bytes(const adha_section *sec, uint64_t *out);
 /* Effective HBM bytes one run moves under layout l, counted in 64-byte
  * access granules: a streamed group costs min(S_g, sum over touched fields

@@ -21,7 +21,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "adha.h")
 OK, WARN_FALLBACK = 0, 1
 ERR_INVALID, ERR_OOM, ERR_DEVICE, ERR_STATE, ERR_UNSUPPORTED, ERR_IO = -1, -2, -3, -4, -5, -6
 F32, F64, I32, RAW = 0, 1, 2, 3
-OP_GEN, OP_MULADD3, OP_SUB2, OP_SUM = 0, 1, 2, 3
+OP_GEN, OP_MULADD3, OP_SUB2, OP_SUM, OP_REDUCE = 0, 1, 2, 3, 4
+MAX_REDUCE_CELLS = 4096
 COST_MEASURED, COST_ANALYTIC, COST_LEARNED = 0, 1, 2
 CAT_AOS_SOA, CAT_FULL = 0, 1
 INIT_FREE, INIT_AOS = 0, 1
@@ -107,6 +108,7 @@ _SIGS = {
     "adha_tune_save": ([P, ctypes.c_char_p], I32T),
     "adha_tune_load": ([P, ctypes.c_char_p], I32T),
     "adha_section_create": ([P, ctypes.c_int, U32, P, U32, P, U32, PP], I32T),
+    "adha_section_create_reduce": ([P, U32, P, ctypes.c_int32, U32, P, U64, PP], I32T),
     "adha_section_destroy": ([P], I32T),
     "adha_section_run": ([P, P, P, P, U64, P, U64, P], I32T),
     "adha_section_bytes": ([P, ctypes.POINTER(U64)], I32T),
@@ -303,7 +305,24 @@ class Section:
 
     @classmethod
     def from_spec(cls, st: Struct, spec):
+        if spec.op == OP_REDUCE:
+            raise ValueError("reduction specs need a result table: use Section.reduce")
         return cls(st, spec.op, spec.read, spec.write, spec.degree)
+
+    @classmethod
+    def reduce(cls, st: Struct, read, key: int, n_keys: int, out):
+        """A reduction of the read fields over the records, per key (key -1:
+        one row); `out` is a device tensor of at least n_keys*(len(read)+1)
+        eight-byte cells that every run overwrites."""
+        op, oc = _dev(out)
+        h = ctypes.c_void_p()
+        check(lib().adha_section_create_reduce(st.h, len(read), _i32(read), key, n_keys, op, oc,
+                                               ctypes.byref(h)))
+        self = cls.__new__(cls)
+        self.h = h
+        self.op, self.read, self.write, self.degree = OP_REDUCE, sorted(read), [], 0
+        self.key, self.n_keys, self.out = key, n_keys, out
+        return self
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

@@ -185,7 +185,9 @@ adha_status adha_ctx_check(adha_ctx *ctx, void *stream) {
   ADHA_HIP(hipMemcpy(&flag, ctx->c.err_flag, 4, hipMemcpyDeviceToHost));
   if (flag) {
     ADHA_HIP(hipMemset(ctx->c.err_flag, 0, 4));
-    return fail(ADHA_ERR_INVALID, "a gather section met an index outside [0, N); those terms were skipped");
+    return fail(ADHA_ERR_INVALID,
+                "a gather met an index outside [0, N) or a reduction a key outside [0, n_keys); "
+                "those terms or records were left out");
   }
   return ADHA_OK;
 }
@@ -540,6 +542,8 @@ adha_status adha_section_create(const adha_struct *s, adha_op op, uint32_t n_rea
       if (sh.dtype[d.wr[0]] == ADHA_I32) return fail(ADHA_ERR_UNSUPPORTED, "op needs a floating-point write field");
       break;
     }
+    case ADHA_OP_REDUCE:
+      return fail(ADHA_ERR_INVALID, "reductions are created by adha_section_create_reduce");
     default:
       return fail(ADHA_ERR_INVALID, "unknown op %d", (int)op);
   }
@@ -547,6 +551,52 @@ adha_status adha_section_create(const adha_struct *s, adha_op op, uint32_t n_rea
   if (!sec) return fail(ADHA_ERR_OOM, "section allocation failed");
   sec->d = std::move(d);
   *out = sec;
+  return ADHA_OK;
+}
+
+adha_status adha_section_create_reduce(const adha_struct *s, uint32_t n_read, const int32_t *read,
+                                       int32_t key_field, uint32_t n_keys, void *out, uint64_t out_cap,
+                                       adha_section **out_sec) {
+  if (!s || !out_sec) return fail(ADHA_ERR_INVALID, "NULL argument");
+  const Shape &sh = s->shape;
+  const int F = sh.nfields();
+  if (n_read == 0 || n_read > ADHA_MAX_READ)
+    return fail(ADHA_ERR_INVALID, "n_read %u not in [1, %d]", n_read, ADHA_MAX_READ);
+  if (!read) return fail(ADHA_ERR_INVALID, "read array is NULL");
+  SectionDesc d;
+  d.shape = sh;
+  d.op = ADHA_OP_REDUCE;
+  d.rd.assign(read, read + n_read);
+  std::sort(d.rd.begin(), d.rd.end());
+  for (size_t i = 0; i < d.rd.size(); ++i) {
+    const int f = d.rd[i];
+    if (f < 0 || f >= F) return fail(ADHA_ERR_INVALID, "field id %d out of range", f);
+    if (i && d.rd[i - 1] == f) return fail(ADHA_ERR_INVALID, "field id %d listed twice", f);
+    if (sh.dtype[f] == ADHA_RAW) return fail(ADHA_ERR_UNSUPPORTED, "field %d is RAW; sections need typed fields", f);
+  }
+  if (key_field >= 0) {
+    if (key_field >= F) return fail(ADHA_ERR_INVALID, "key field %d out of range", key_field);
+    if (sh.dtype[key_field] != ADHA_I32) return fail(ADHA_ERR_INVALID, "key field %d is not I32", key_field);
+    if (std::find(d.rd.begin(), d.rd.end(), key_field) != d.rd.end())
+      return fail(ADHA_ERR_INVALID, "key field %d is also read", key_field);
+  } else if (key_field != -1) {
+    return fail(ADHA_ERR_INVALID, "key field %d: use -1 for no key", key_field);
+  } else if (n_keys != 1) {
+    return fail(ADHA_ERR_INVALID, "a reduction without a key has one row, not %u", n_keys);
+  }
+  if (n_keys == 0) return fail(ADHA_ERR_INVALID, "n_keys is 0");
+  if ((uint64_t)n_keys * (n_read + 1) > ADHA_MAX_REDUCE_CELLS)
+    return fail(ADHA_ERR_INVALID, "table of %u x %u cells exceeds %d", n_keys, n_read + 1, ADHA_MAX_REDUCE_CELLS);
+  d.key = key_field;
+  d.n_keys = n_keys;
+  const uint64_t need = (uint64_t)d.reduce_cells() * 8;
+  ADHA_TRY(check_dev_buf("out", out, out_cap, need));
+  d.out = out;
+  d.out_cap = out_cap;
+  auto *sec = new (std::nothrow) adha_section;
+  if (!sec) return fail(ADHA_ERR_OOM, "section allocation failed");
+  sec->d = std::move(d);
+  *out_sec = sec;
   return ADHA_OK;
 }
 
@@ -577,6 +627,8 @@ adha_status validate_section_run(const adha_section *sec, const adha_layout *l, 
                   (unsigned long long)idx_count, (unsigned long long)l->d.shape.n * sec->d.degree);
     if (overlap(idx, idx_count * 4, buf, l->d.nbytes)) return fail(ADHA_ERR_INVALID, "idx overlaps buf");
   }
+  if (sec->d.op == ADHA_OP_REDUCE && overlap(sec->d.out, (uint64_t)sec->d.reduce_cells() * 8, buf, l->d.nbytes))
+    return fail(ADHA_ERR_INVALID, "the reduction's result table overlaps buf");
   return ADHA_OK;
 }
 }  // namespace adha

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <map>
 #include <memory>
@@ -84,7 +85,23 @@ struct SectionDesc {
   int32_t op = 0;
   std::vector<int32_t> rd, wr;
   uint32_t degree = 0;
+  // reductions: key field (-1: none), key count, result table (device)
+  int32_t key = -1;
+  uint32_t n_keys = 1;
+  void *out = nullptr;
+  uint64_t out_cap = 0;
   uint64_t algorithmic_bytes() const;
+  // every field read at the record itself in a direct pass: the read
+  // fields plus a reduction's key
+  std::vector<int32_t> streamed_reads() const {
+    std::vector<int32_t> v = rd;
+    if (key >= 0) {
+      v.push_back(key);
+      std::sort(v.begin(), v.end());
+    }
+    return v;
+  }
+  uint32_t reduce_cells() const { return n_keys * ((uint32_t)rd.size() + 1); }
 };
 
 }  // namespace adha
@@ -159,7 +176,7 @@ adha_status prepared_for(Ctx *ctx, const adha_layout *a, const adha_layout *b, c
 
 // ------------------------------------------------------------------ sections
 adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l, void *buf,
-                           const int32_t *idx, hipStream_t stream);
+                           const int32_t *idx, hipStream_t stream, void *out_override = nullptr);
 
 // ------------------------------------------------------------------ MLP
 adha_status mlp_forward(Ctx *ctx, const float *params, const float *x, uint32_t batch, float *y,

@@ -177,6 +177,7 @@ uint64_t SectionDesc::algorithmic_bytes() const {
   for (int f : rd) rb += shape.ebytes[f];
   for (int f : wr) wb += shape.ebytes[f];
   uint64_t n = (uint64_t)shape.n;
+  if (key >= 0) rb += shape.ebytes[key];
   if (degree == 0) return n * (rb + wb);
   return n * (4ull * degree + (uint64_t)degree * rb + wb);
 }

@@ -54,7 +54,7 @@ std::vector<uint64_t> affinity(const std::vector<SectionDesc> &secs, size_t firs
   for (size_t s = first; s <= last; ++s) {
     const SectionDesc &d = secs[s];
     if (d.degree == 0) {
-      std::vector<int32_t> all = d.rd;
+      std::vector<int32_t> all = d.streamed_reads();
       for (int f : d.wr)
         if (std::find(all.begin(), all.end(), f) == all.end()) all.push_back(f);
       std::sort(all.begin(), all.end());
@@ -200,8 +200,9 @@ static double group_random_bytes(const LayoutDesc &l, size_t gi, const std::vect
 
 double analytic_bytes_per_record(const SectionDesc &s, const LayoutDesc &l) {
   double b = 0.0;
+  const std::vector<int32_t> streamed = s.streamed_reads();
   for (size_t gi = 0; gi < l.groups.size(); ++gi) {
-    if (s.degree == 0) b += group_stream_bytes(l, gi, s.rd);
+    if (s.degree == 0) b += group_stream_bytes(l, gi, streamed);
     else b += s.degree * group_random_bytes(l, gi, s.rd);
     b += group_stream_bytes(l, gi, s.wr);
   }
@@ -257,18 +258,26 @@ struct DevBuf {
   }
 };
 
+// Which section times measured_costs takes on the device (the remap figure
+// is always measured).
+enum TimeSections { kTimeAll, kTimeNone, kTimeReductions };
+
 static adha_status measured_costs(Ctx *ctx, const Shape &sh, const std::vector<SectionDesc> &secs,
                                   const std::vector<adha_layout *> &cands, uint32_t reps,
                                   const int32_t *idx_in, uint64_t idx_count, hipStream_t stream,
-                                  std::vector<double> *T, std::vector<double> *R, bool sections = true) {
+                                  std::vector<double> *T, std::vector<double> *R, TimeSections which = kTimeAll) {
   const size_t k = secs.size(), C = cands.size();
+  const bool sections = which != kTimeNone;
   uint64_t maxb = 0;
   uint32_t maxd = 0;
   for (auto *l : cands) maxb = std::max(maxb, l->d.nbytes);
   for (auto &s : secs) maxd = std::max(maxd, s.degree);
-  DevBuf a, b, ix;
+  DevBuf a, b, ix, tab;
   ADHA_TRY(a.alloc(maxb));
   ADHA_TRY(b.alloc(maxb));
+  // reductions write their tables here while being timed, not into the
+  // caller's result arrays
+  ADHA_TRY(tab.alloc(ADHA_MAX_REDUCE_CELLS * 8));
   ADHA_HIP(hipMemsetAsync(a.p, 0, maxb, stream));
   const int32_t *idx = idx_in;
   if (sections && maxd > 0 && sh.n > 0 && (!idx_in || idx_count < (uint64_t)sh.n * maxd)) {
@@ -276,12 +285,13 @@ static adha_status measured_costs(Ctx *ctx, const Shape &sh, const std::vector<S
     ADHA_TRY(fill_uniform_index((int32_t *)ix.p, (uint64_t)sh.n * maxd, sh.n, 0x5eedULL, stream));
     idx = (const int32_t *)ix.p;
   }
-  if (sections) T->assign(k * C, 0.0);
+  if (which == kTimeAll) T->assign(k * C, 0.0);
   for (size_t c = 0; c < C && sections; ++c)
     for (size_t s = 0; s < k; ++s) {
+      if (which == kTimeReductions && secs[s].op != ADHA_OP_REDUCE) continue;
       // a gather section's index array is [N][d]; a wider one is read as [N][d] too
       ADHA_TRY(time_us(stream, reps,
-                       [&] { return section_launch(ctx, secs[s], cands[c]->d, a.p, idx, stream); },
+                       [&] { return section_launch(ctx, secs[s], cands[c]->d, a.p, idx, stream, tab.p); },
                        &(*T)[s * C + c]));
     }
   // The remap always moves the whole struct: one measured figure, from a
@@ -418,8 +428,12 @@ adha_status adha_plan_create(adha_ctx *ctx, const adha_program *p, const adha_pl
       pl->T = us;
       // remap weights: a few measured whole-struct remaps (milliseconds of
       // device time), the same figure the measured provider uses
+      // the network was trained on loops that write per record; reductions
+      // are timed on the device
+      bool any_reduce = false;
+      for (const SectionDesc &d : p->secs) any_reduce |= d.op == ADHA_OP_REDUCE;
       ADHA_TRY(measured_costs(&ctx->c, p->shape, p->secs, pl->cands, std::max<uint32_t>(1, o->reps), idx,
-                              idx_count, st, &pl->T, &pl->R, false));
+                              idx_count, st, &pl->T, &pl->R, any_reduce ? kTimeReductions : kTimeNone));
     }
   }
   if (src == ADHA_COST_ANALYTIC) {
@@ -533,6 +547,13 @@ adha_status adha_run(adha_ctx *ctx, const adha_plan *pl, const adha_layout *in_l
     uintptr_t x = (uintptr_t)buf_a, y = (uintptr_t)buf_b;
     if (x < y + need && y < x + need) return fail(ADHA_ERR_INVALID, "buf_a and buf_b overlap");
   }
+  for (const SectionDesc &d : pl->secs)
+    if (d.op == ADHA_OP_REDUCE && need) {
+      const uintptr_t o = (uintptr_t)d.out, no = (uintptr_t)d.reduce_cells() * 8;
+      for (const void *b : {(const void *)buf_a, needs_b ? (const void *)buf_b : nullptr})
+        if (b && o < (uintptr_t)b + need && (uintptr_t)b < o + no)
+          return fail(ADHA_ERR_INVALID, "a reduction's result table overlaps the data buffers");
+    }
   DeviceGuard g(ctx->c.device);
   hipStream_t st = (hipStream_t)stream;
   cur = in_layout;

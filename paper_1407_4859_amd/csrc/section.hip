@@ -347,9 +347,174 @@ static void launch_maxr(uint32_t nr, dim3 grid, const SectionArgs &a, hipStream_
   else hipLaunchKernelGGL((section_kernel<OP, DG, 32>), grid, dim3(256), 0, st, a);
 }
 
-adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l, void *buf,
-                           const int32_t *idx, hipStream_t stream) {
+// ------------------------------------------------------------ reductions
+// A reduction adds the read fields of every record into row `key` of a small
+// table.  Pass 1: each workgroup accumulates its records into its own copy
+// of the table in LDS and writes that copy out; pass 2 adds the copies in
+// workgroup order.  Floating-point fields are summed in double and integer
+// fields in int64 (two's complement), the last column counts records.
+// Inside a workgroup, lanes of a wave whose records share one key are first
+// summed across the wave (a butterfly over the 64 lanes), so a table with
+// few rows does not serialise on LDS atomics to the same cell.
+struct ReduceArgs {
+  const uint8_t *buf;
+  uint32_t *err;
+  uint64_t *partials;  // [gridDim.x][cells]
+  int64_t n;
+  uint32_t n_read, n_keys, cells, has_key;
+  uint32_t fp_mask;    // bit q: read field q is floating point
+  SField rd[ADHA_MAX_READ];
+  SField key;
+};
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += (uint64_t)__shfl_xor((long long)v, m, 64);
+  return v;
+}
+
+template <int MAXR>
+__global__ __launch_bounds__(256) void reduce_partial_kernel(const ReduceArgs a) {
+  extern __shared__ uint64_t tab[];
+  const uint32_t nr = a.n_read, cols = nr + 1;
+  for (uint32_t c = threadIdx.x; c < a.cells; c += 256) tab[c] = 0;
+  __syncthreads();
+  const uint32_t lane = threadIdx.x & 63u;
+  bool bad = false;
+  const uint64_t stride = (uint64_t)gridDim.x * 256u;
+  // the loop bound is the same for every lane of the workgroup, so the
+  // wave-wide steps below run with all 64 lanes
+  for (uint64_t i0 = (uint64_t)blockIdx.x * 256u; i0 < (uint64_t)a.n; i0 += stride) {
+    const uint64_t i = i0 + threadIdx.x;
+    const bool live = i < (uint64_t)a.n;
+    int32_t k = 0;
+    if (a.has_key && live) k = (int32_t)(uint32_t)load_term(a.buf, a.key, i);
+    const bool ok = live && k >= 0 && (uint32_t)k < a.n_keys;
+    bad |= live && !ok;
+    uint64_t t[MAXR];
+#pragma unroll
+    for (int q = 0; q < MAXR; ++q)
+      if (q < (int)nr) t[q] = ok ? load_term(a.buf, a.rd[q], i) : 0;
+    const uint64_t okm = __ballot(ok);
+    if (okm == 0) continue;
+    const int lead = __ffsll((unsigned long long)okm) - 1;
+    const int32_t k0 = __shfl(k, lead, 64);
+    const bool uniform = __ballot(ok && k != k0) == 0;
+    if (uniform) {
+      uint64_t *row = tab + (uint32_t)k0 * cols;
+#pragma unroll
+      for (int q = 0; q < MAXR; ++q)
+        if (q < (int)nr) {
+          if (a.fp_mask >> q & 1u) {
+            const double v = wave_sum_f64(ok ? to_f64(a.rd[q].dt, t[q]) : 0.0);
+            if ((int)lane == lead) atomicAdd(reinterpret_cast<double *>(row + q), v);
+          } else {
+            const uint64_t v = wave_sum_u64(ok ? (uint64_t)(int64_t)(int32_t)(uint32_t)t[q] : (uint64_t)0);
+            if ((int)lane == lead) atomicAdd(reinterpret_cast<unsigned long long *>(row + q), (unsigned long long)v);
+          }
+        }
+      if ((int)lane == lead)
+        atomicAdd(reinterpret_cast<unsigned long long *>(row + nr), (unsigned long long)__popcll(okm));
+    } else if (ok) {
+      uint64_t *row = tab + (uint32_t)k * cols;
+#pragma unroll
+      for (int q = 0; q < MAXR; ++q)
+        if (q < (int)nr) {
+          if (a.fp_mask >> q & 1u)
+            atomicAdd(reinterpret_cast<double *>(row + q), to_f64(a.rd[q].dt, t[q]));
+          else
+            atomicAdd(reinterpret_cast<unsigned long long *>(row + q),
+                      (unsigned long long)(int64_t)(int32_t)(uint32_t)t[q]);
+        }
+      atomicAdd(reinterpret_cast<unsigned long long *>(row + nr), 1ull);
+    }
+  }
+  __syncthreads();
+  uint64_t *mine = a.partials + (uint64_t)blockIdx.x * a.cells;
+  for (uint32_t c = threadIdx.x; c < a.cells; c += 256) mine[c] = tab[c];
+  if (bad) atomicOr(a.err, 1u);
+}
+
+// Pass 2: one thread per cell adds the workgroups' copies in order.
+__global__ __launch_bounds__(256) void reduce_final_kernel(const uint64_t *partials, uint32_t groups, uint32_t cells,
+                                                           uint32_t cols, uint32_t fp_mask, uint64_t *out) {
+  const uint32_t c = blockIdx.x * 256u + threadIdx.x;
+  if (c >= cells) return;
+  const uint32_t q = c % cols;
+  if (q + 1 < cols && (fp_mask >> q & 1u)) {
+    double s = 0.0;
+    for (uint32_t g = 0; g < groups; ++g) s += __longlong_as_double((long long)partials[(uint64_t)g * cells + c]);
+    out[c] = (uint64_t)__double_as_longlong(s);
+  } else {
+    uint64_t s = 0;
+    for (uint32_t g = 0; g < groups; ++g) s += partials[(uint64_t)g * cells + c];
+    out[c] = s;
+  }
+}
+
+static adha_status reduce_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l, const void *buf,
+                                 void *out, hipStream_t stream) {
   const int64_t n = l.shape.n;
+  ReduceArgs a{};
+  a.buf = (const uint8_t *)buf;
+  a.err = ctx->err_flag;
+  a.n = n;
+  a.n_read = (uint32_t)sec.rd.size();
+  a.n_keys = sec.n_keys;
+  a.cells = sec.reduce_cells();
+  a.has_key = sec.key >= 0;
+  for (size_t q = 0; q < sec.rd.size(); ++q) {
+    a.rd[q] = sfield(l, sec.rd[q]);
+    if (l.shape.dtype[sec.rd[q]] != ADHA_I32) a.fp_mask |= 1u << q;
+  }
+  if (sec.key >= 0) a.key = sfield(l, sec.key);
+  // a fixed grid for a given N, so the order of pass 2 is fixed too
+  const uint64_t want = std::max<uint64_t>(1, ((uint64_t)n + 255) / 256);
+  const uint32_t groups = (uint32_t)std::min<uint64_t>(want, (uint64_t)std::max(1, ctx->cu_count) * 4);
+  uint64_t *partials = nullptr;
+  ADHA_HIP(hipMallocAsync((void **)&partials, (size_t)groups * a.cells * 8, stream));
+  a.partials = partials;
+  const size_t lds = (size_t)a.cells * 8;
+  const uint32_t nr = a.n_read;
+  if (nr <= 4) hipLaunchKernelGGL((reduce_partial_kernel<4>), dim3(groups), dim3(256), lds, stream, a);
+  else if (nr <= 8) hipLaunchKernelGGL((reduce_partial_kernel<8>), dim3(groups), dim3(256), lds, stream, a);
+  else if (nr <= 16) hipLaunchKernelGGL((reduce_partial_kernel<16>), dim3(groups), dim3(256), lds, stream, a);
+  else hipLaunchKernelGGL((reduce_partial_kernel<32>), dim3(groups), dim3(256), lds, stream, a);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess)
+    hipLaunchKernelGGL(reduce_final_kernel, dim3((a.cells + 255) / 256), dim3(256), 0, stream,
+                       (const uint64_t *)partials, groups, a.cells, nr + 1, a.fp_mask, (uint64_t *)out);
+  if (e == hipSuccess) e = hipGetLastError();
+  (void)hipFreeAsync(partials, stream);
+  if (e != hipSuccess) return fail(ADHA_ERR_DEVICE, "reduction launch failed: %s", hipGetErrorString(e));
+  return ADHA_OK;
+}
+
+// A reduction over no records writes a table of zeros.
+__global__ void zero_u64_kernel(uint64_t *p, uint32_t n) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l, void *buf,
+                           const int32_t *idx, hipStream_t stream, void *out_override) {
+  const int64_t n = l.shape.n;
+  if (sec.op == ADHA_OP_REDUCE) {
+    void *out = out_override ? out_override : sec.out;
+    if (n == 0) {
+      hipLaunchKernelGGL(zero_u64_kernel, dim3((sec.reduce_cells() + 255) / 256), dim3(256), 0, stream,
+                         (uint64_t *)out, sec.reduce_cells());
+      ADHA_HIP(hipGetLastError());
+      return ADHA_OK;
+    }
+    return reduce_launch(ctx, sec, l, buf, out, stream);
+  }
   if (n == 0) return ADHA_OK;
   SectionArgs a{};
   a.buf = (uint8_t *)buf;
