@@ -13,6 +13,9 @@ Besides the timed steps the run reports (outside the timed region):
   program       the multi-section workload (N = 2^24, 32 fields, 8 sections,
                 4 of them 16-neighbour gathers): program time under the
                 planned layouts vs all-AoS and all-SoA, per-kernel GB/s;
+  kmeans        the K-Means-shaped program (2^23 points, a direct loop and a
+                per-cluster reduction of 32 features): planned vs all-AoS and
+                all-SoA, per-section GB/s;
   batched       the 512-array batched remap: one graph launch vs one launch
                 per array;
   learned       (with --learned) the cost model: planned program time with
@@ -68,6 +71,8 @@ def parse():
     ap.add_argument("--program-log2n", type=int, default=24)
     ap.add_argument("--skip-program", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-kmeans", action="store_true")
+    ap.add_argument("--only-kmeans", action="store_true", help="the K-Means-shaped leg only (for profiling)")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--learned", action="store_true")
     ap.add_argument("--only-learned", action="store_true", help="skip everything but the cost-model leg")
@@ -221,6 +226,53 @@ def program_bench(A, synth, torch, timer, log2n, cost="measured"):
     return out
 
 
+def kmeans_bench(A, synth, torch, timer, log2n=23):
+    """The K-Means-shaped program: a direct loop over 32 features, then a
+    reduction of the features per cluster (5 keys), planned with measured
+    costs and compared with all-AoS and all-SoA."""
+    n = 1 << log2n
+    spec = synth.kmeans_struct(n)
+    st = A.Struct.from_spec(spec)
+    gen_spec, (rd, key, nk) = synth.kmeans_sections()
+    out = torch.zeros(nk * (len(rd) + 1) * 8, dtype=torch.uint8, device="cuda")
+    gen = A.Section.from_spec(st, gen_spec)
+    red = A.Section.reduce(st, rd, key, nk, out)
+    prog = A.Program(st, [gen, red])
+    aos_l, soa_l = A.Layout.aos(st), A.Layout.soa(st)
+    cap = max(aos_l.nbytes, soa_l.nbytes) + (1 << 26)
+    buf_a = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    buf_b = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    log("kmeans: filling", n, "records")
+    fill_fields(buf_a, spec, 6, torch, synth)
+    keys = synth.uniform_index_torch(6, 77, n, nk, "cuda")
+    buf_a[: n * spec.record_bytes].view(n, spec.record_bytes)[:, 4 * key:4 * key + 4] = \
+        keys.view(torch.uint8).view(n, 4)
+    ctx = A.Ctx(0)
+    t0 = time.perf_counter()
+    plan = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_MEASURED, catalogue=A.CAT_FULL, cap_bytes=64, reps=3))
+    plan_s = time.perf_counter() - t0
+    res = {"workload": f"N=2^{log2n} points, 32 f32 features + i32 cluster key (5 clusters) + f32 result "
+                       f"(136 B); GEN over the features, then their per-cluster reduction",
+           "candidates": plan.n_candidates, "plan_seconds": round(plan_s, 2)}
+    for name, pl in (("adha", plan), ("all_aos", A.Plan.uniform(prog, aos_l)),
+                     ("all_soa", A.Plan.uniform(prog, soa_l))):
+        first = pl.candidate(pl.choices()[0])
+        ms, _ = timer.time(lambda: A.run(ctx, pl, first, buf_a, buf_b), reps=5, warm=1)
+        res[name + "_ms"] = round(ms, 3)
+        res[name + "_choices"] = pl.choices()
+    ctx.check()
+    res["speedup_vs_best_uniform"] = round(min(res["all_aos_ms"], res["all_soa_ms"]) / res["adha_ms"], 3)
+    per = []
+    for s, sec in enumerate((gen, red)):
+        for lname, lay in (("planned", plan.candidate(plan.choices()[s])), ("aos", aos_l), ("soa", soa_l)):
+            ms, _ = timer.time(lambda: A.section_run(ctx, sec, lay, buf_a), reps=7, warm=1)
+            per.append({"section": s, "layout": lname, "us": round(ms * 1e3, 1),
+                        "alg_GBps": round(sec.bytes / (ms * 1e6), 1)})
+    ctx.check()
+    res["sections"] = per
+    return res
+
+
 def batched_bench(A, synth, torch, timer):
     arrs = synth.config4_arrays()
     ctx = A.Ctx(0)
@@ -323,6 +375,9 @@ def main():
     if args.only_learned:
         print(json.dumps({"learned": learned_bench(A, synth, torch, args)}), flush=True)
         return
+    if args.only_kmeans:
+        print(json.dumps({"kmeans": kmeans_bench(A, synth, torch, timer)}), flush=True)
+        return
     if args.only_program:
         print(json.dumps({"program": program_bench(A, synth, torch, timer, args.program_log2n, args.program_cost)}),
               flush=True)
@@ -416,6 +471,12 @@ def main():
                 line["program"] = program_bench(A, synth, torch, timer, args.program_log2n)
             except Exception as e:  # report, keep the main line
                 line["program"] = {"error": repr(e)}
+            torch.cuda.empty_cache()
+        if not args.skip_kmeans:
+            try:
+                line["kmeans"] = kmeans_bench(A, synth, torch, timer)
+            except Exception as e:
+                line["kmeans"] = {"error": repr(e)}
             torch.cuda.empty_cache()
         if not args.skip_batched:
             try:

@@ -265,6 +265,25 @@ def random_program(seed: int, n_fields: int, k: int = 8, n_gather: int = 4, degr
     return secs
 
 
+# op code of reductions (same numbering as the C-ABI's adha_op)
+OP_REDUCE = 4
+KMEANS_FEATURES, KMEANS_KEY, KMEANS_SCORE, KMEANS_K = 32, 32, 33, 5
+
+
+def kmeans_struct(n: int = 8388608) -> StructSpec:
+    """K-Means-shaped workload: 32 f32 features (ids 0-31), the cluster key
+    (id 32, i32, drawn U[0, 5) from stream 77 by uniform_index) and one f32
+    result field (id 33)."""
+    return StructSpec(n, [F32] * 32 + [I32, F32], [4] * 34)
+
+
+def kmeans_sections():
+    """The two loops: a direct GEN over the features writing field 33, then a
+    reduction of the features per cluster key (read, key, key count)."""
+    return (SectionSpec(OP_GEN, list(range(KMEANS_FEATURES)), [KMEANS_SCORE]),
+            (list(range(KMEANS_FEATURES)), KMEANS_KEY, KMEANS_K))
+
+
 def config4_arrays(seed: int = 4, n_arrays: int = 512, lo_log2: int = 10, hi_log2: int = 22):
     """Batched-remap workload: per array (n, elem_bytes[], target partition, tiles).
 

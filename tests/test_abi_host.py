@@ -8,6 +8,7 @@ import subprocess
 import numpy as np
 import pytest
 
+from oracle import costmodel as OC
 from oracle import planner as OP
 from oracle.layout import Layout as OLayout, aos as oaos, soa as osoa
 from paper_1407_4859_amd import adha as A
@@ -197,3 +198,58 @@ def test_analytic_plan_catalogue_matches_oracle():
     cost, path = OP.pdl_dp(T, R)
     assert pl.choices() == path
     assert abs(pl.cost - cost) <= 1e-9 * cost
+
+
+class _FakeDev:
+    """Stands in for a device tensor at creation time (nothing is read or
+    written through it until a run)."""
+
+    def __init__(self, addr, nbytes):
+        self.addr, self.nbytes = addr, nbytes
+
+    def data_ptr(self):
+        return self.addr
+
+    def numel(self):
+        return self.nbytes
+
+    def element_size(self):
+        return 1
+
+
+def test_reduction_sections_validate_and_plan_like_the_oracle():
+    spec = synth.StructSpec(1 << 12, [synth.F32] * 6 + [synth.I32, synth.F64], [4] * 7 + [8])
+    st = A.Struct.from_spec(spec)
+    out = _FakeDev(1 << 20, 5 * 4 * 8)
+    r = A.Section.reduce(st, [0, 2, 7], 6, 5, out)
+    assert r.bytes == spec.n * (4 + 4 + 8 + 4)
+    bad = [([0], 2, 5, out),                                   # key is F32
+           ([0, 6], 6, 5, out),                                # key also read
+           ([0], -1, 3, out),                                  # no key, several rows
+           ([0], 6, 0, out),                                   # no rows
+           ([0, 1, 2], 6, 5, _FakeDev(1 << 20, 5 * 4 * 8 - 1)),  # table does not fit
+           ([0], 6, 5, _FakeDev((1 << 20) + 8, 4096)),         # misaligned
+           ([0] * 2, 6, 5, out),                               # field twice
+           (list(range(6)), 6, 4096 // 7 + 1, _FakeDev(1 << 20, 1 << 20))]   # too many cells
+    for rd, key, nk, o in bad:
+        with pytest.raises(A.AdhaError) as e:
+            A.Section.reduce(st, rd, key, nk, o)
+        assert e.value.status == A.ERR_INVALID
+    with pytest.raises(A.AdhaError):
+        A.Section(st, A.OP_REDUCE, [0], [1], 0)             # not through adha_section_create
+    # a program with a reduction: affinity, catalogue and analytic tables as
+    # the oracle's with the key taken as one more streamed read
+    g = A.Section(st, A.OP_GEN, [0, 1, 3], [4], 0)
+    prog = A.Program(st, [g, r])
+    osecs = [([0, 1, 3], [4], 0), ([0, 2, 6, 7], [], 0)]
+    assert prog.affinity(0, 1) == OP.affinity(osecs, spec.n_fields)
+    opts = A.plan_opts(cost=A.COST_ANALYTIC, cap_bytes=64)
+    h = ctypes.c_void_p()
+    A.check(A.lib().adha_plan_create(None, prog.h, ctypes.byref(opts), None, 0, None, ctypes.byref(h)))
+    pl = A.Plan(h, 2)
+    cat = OP.catalogue(osecs, spec.n, spec.elem_bytes, 64)
+    assert pl.n_candidates == len(cat)
+    T, _ = pl.tables()
+    for c, O in enumerate(cat):
+        for s, (rd, wr, d) in enumerate(osecs):
+            assert T[s][c] == pytest.approx(OC.section_us(rd, wr, d, O), rel=1e-12)

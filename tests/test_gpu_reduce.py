@@ -1,0 +1,217 @@
+"""GPU parity of reduction sections against the oracle.
+
+F32 and I32 columns and the counts must match exactly: the generator's F32
+values are multiples of 2^-23 below 1 in magnitude, so every partial sum in
+double is exact whatever the order.  F64 columns must lie within
+(m-1) * 2^-53 * sum|x| of the exactly rounded sum of their m values."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import reduce as OR
+from oracle.layout import Layout as OLayout, aos as oaos, soa as osoa, from_partition
+from paper_1407_4859_amd import adha as A
+from paper_1407_4859_amd import synth
+from gpu_util import dev_bytes, host, mirror, say
+
+pytestmark = pytest.mark.gpu
+
+F32, F64, I32 = synth.F32, synth.F64, synth.I32
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return A.Ctx(0)
+
+
+def _struct(n, seed, n_keys, bad=()):
+    """Fields: 0-5 f32, 6 key (i32 in [0, n_keys)), 7 i32, 8-9 f64, 10 f32."""
+    dtypes = [F32] * 6 + [I32, I32, F64, F64, F32]
+    eb = [4] * 8 + [8, 8, 4]
+    cols = synth.record_matrix(seed, n, dtypes, eb)
+    keys = synth.uniform_index(seed, 77, n, n_keys).astype(np.int32)
+    for r, k in bad:
+        keys[r] = k
+    cols[6] = keys.view(np.uint8).reshape(n, 4)
+    return synth.StructSpec(n, dtypes, eb), cols
+
+
+def _check(got_cells, table, dtypes, read, values):
+    """got_cells: uint64 cells from the device; table: the oracle's."""
+    want = OR.table_cells(table, dtypes, read)
+    cols = len(read) + 1
+    for k, row in enumerate(table):
+        for j in range(cols):
+            g, w = got_cells[k * cols + j], want[k * cols + j]
+            if j < len(read) and dtypes[read[j]] == F64:
+                gv = float(np.array([g], np.uint64).view(np.float64)[0])
+                m = row[-1]
+                bound = max(m - 1, 0) * 2.0 ** -53 * values[(k, j)]
+                assert abs(gv - row[j]) <= bound, (k, j, gv, row[j], bound)
+            else:
+                assert g == w, (k, j, int(g), int(w))
+
+
+def _abs_sums(L, dtypes, read, key, n_keys, buf):
+    """sum |x| per (key, column) for the F64 bound."""
+    keys = (OR.field_values(L, buf, I32, key).astype(np.int64) if key >= 0 else np.zeros(L.n, np.int64))
+    out = {}
+    for j, f in enumerate(sorted(read)):
+        v = np.abs(OR.field_values(L, buf, dtypes[f], f).astype(np.float64))
+        for k in range(n_keys):
+            out[(k, j)] = float(v[keys == k].sum()) * (1 + 1e-12)
+    return out
+
+
+def _run(ctx, spec, cols, O, read, key, n_keys):
+    st = A.Struct.from_spec(spec)
+    L = mirror(st, O)
+    buf_h = oracle.pack(O, cols)
+    dev = dev_bytes(buf_h)
+    cells = n_keys * (len(read) + 1)
+    out = torch.full((cells * 8,), 0xEE, dtype=torch.uint8, device="cuda")
+    sec = A.Section.reduce(st, read, key, n_keys, out)
+    A.section_run(ctx, sec, L, dev)
+    return buf_h, sec, out
+
+
+@pytest.mark.parametrize("n", [1, 255, 4096 + 13, 1 << 18])
+def test_reduce_matches_oracle_on_layouts(ctx, n):
+    spec, cols = _struct(n, 5, 5)
+    eb = spec.elem_bytes
+    read = [0, 2, 5, 7, 8, 10]
+    layouts = (oaos(n, eb), osoa(n, eb), OLayout(n, eb, [0] * 11, [64]),
+               from_partition(n, eb, [[0, 2, 5, 6], [7, 8, 9, 10]], 1),
+               from_partition(n, eb, [[0, 6], [2, 5, 8]], 16))
+    for O in layouts:
+        say("reduce", n, O)
+        buf_h, sec, out = _run(ctx, spec, cols, O, read, 6, 5)
+        ctx.check()
+        table, bad = OR.reduce(O, spec.dtypes, read, 6, 5, buf_h)
+        assert bad == 0
+        got = host(out).view(np.uint64)
+        _check(got, table, spec.dtypes, read, _abs_sums(O, spec.dtypes, read, 6, 5, buf_h))
+
+
+@pytest.mark.parametrize("n_keys,read", [(1, [0, 1, 7, 9]), (64, [0, 1, 2, 3]), (128, list(range(6)) + [7] + [8, 9, 10]),
+                                         (409, [0, 1, 2, 3, 4, 5, 7, 8, 10])])
+def test_reduce_key_counts_and_no_key(ctx, n_keys, read):
+    n = 100_000
+    spec, cols = _struct(n, 6, n_keys)
+    O = osoa(n, spec.elem_bytes)
+    key = -1 if n_keys == 1 else 6
+    say("reduce keys", n_keys, "read", read)
+    buf_h, sec, out = _run(ctx, spec, cols, O, read, key, n_keys)
+    ctx.check()
+    table, _ = OR.reduce(O, spec.dtypes, read, key, n_keys, buf_h)
+    _check(host(out).view(np.uint64), table, spec.dtypes, read, _abs_sums(O, spec.dtypes, read, key, n_keys, buf_h))
+
+
+def test_reduce_bad_keys_are_left_out_and_reported(ctx):
+    n = 10_000
+    spec, cols = _struct(n, 7, 8, bad=[(0, -1), (17, 8), (9999, 1 << 30)])
+    O = oaos(n, spec.elem_bytes)
+    buf_h, sec, out = _run(ctx, spec, cols, O, [0, 7], 6, 8)
+    with pytest.raises(A.AdhaError) as e:
+        ctx.check()
+    assert e.value.status == A.ERR_INVALID
+    ctx.check()                                      # the flag is cleared
+    table, bad = OR.reduce(O, spec.dtypes, [0, 7], 6, 8, buf_h)
+    assert bad == 3 and sum(r[-1] for r in table) == n - 3
+    _check(host(out).view(np.uint64), table, spec.dtypes, [0, 7], {})
+
+
+def test_reduce_overlap_is_rejected_and_empty_struct_zeroes(ctx):
+    spec, cols = _struct(1000, 8, 4)
+    st = A.Struct.from_spec(spec)
+    O = oaos(1000, spec.elem_bytes)
+    L = mirror(st, O)
+    dev = dev_bytes(oracle.pack(O, cols), extra=4096)
+    sec = A.Section.reduce(st, [0, 1], 6, 4, dev[O.nbytes - 256:])   # table inside the data
+    with pytest.raises(A.AdhaError):
+        A.section_run(ctx, sec, L, dev)
+    st0 = A.Struct(0, spec.dtypes, spec.elem_bytes)
+    out = torch.full((4 * 3 * 8,), 0xEE, dtype=torch.uint8, device="cuda")
+    s0 = A.Section.reduce(st0, [0, 1], 6, 4, out)
+    A.section_run(ctx, s0, A.Layout.aos(st0), torch.empty(256, dtype=torch.uint8, device="cuda"))
+    ctx.check()
+    assert not host(out).any()
+
+
+def test_program_with_a_reduction_runs_to_the_oracle_result(ctx):
+    # a K-Means-like pair: a direct section writes field 10, then the
+    # reduction reads it together with other fields, per key
+    n = (1 << 16) + 3
+    spec, cols = _struct(n, 9, 5)
+    st = A.Struct.from_spec(spec)
+    cells = 5 * 6
+    out = torch.zeros(cells * 8, dtype=torch.uint8, device="cuda")
+    g = A.Section(st, A.OP_GEN, [0, 1, 2, 3], [10], 0)
+    r = A.Section.reduce(st, [0, 4, 7, 9, 10], 6, 5, out)
+    prog = A.Program(st, [g, r])
+    plan = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_MEASURED, catalogue=A.CAT_FULL, reps=3))
+    say("program with reduction: plan", plan.choices(), "of", plan.n_candidates)
+    assert not host(out).any()                       # planning left the table alone
+    Oa = oaos(n, spec.elem_bytes)
+    want_buf = oracle.pack(Oa, cols)
+    oracle.section(Oa, spec.dtypes, A.OP_GEN, [0, 1, 2, 3], [10], 0, None, want_buf)
+    table, _ = OR.reduce(Oa, spec.dtypes, [0, 4, 7, 9, 10], 6, 5, want_buf)
+    sums = _abs_sums(Oa, spec.dtypes, [0, 4, 7, 9, 10], 6, 5, want_buf)
+    for pl in (plan, A.Plan.uniform(prog, A.Layout.aos(st)), A.Plan.uniform(prog, A.Layout.soa(st))):
+        first = pl.candidate(pl.choices()[0])
+        gof, tiles = first.groups(spec.n_fields)
+        O1 = OLayout(n, spec.elem_bytes, gof, tiles)
+        cap = max(pl.candidate(c).nbytes for c in range(pl.n_candidates)) + 256
+        a = dev_bytes(oracle.pack(O1, cols), extra=cap - O1.nbytes)
+        b = torch.empty(cap, dtype=torch.uint8, device="cuda")
+        out.zero_()
+        A.run(ctx, pl, first, a, b)
+        ctx.check()
+        _check(host(out).view(np.uint64), table, spec.dtypes, [0, 4, 7, 9, 10], sums)
+
+
+@pytest.mark.timeout(900)
+def test_kmeans_workload_full_size(ctx):
+    """The K-Means-shaped program at its full size (2^23 points): the planned,
+    all-AoS and all-SoA runs give the oracle's table."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    from gpu_util import fill_aos_device
+    n = 8388608
+    spec = synth.kmeans_struct(n)
+    st = A.Struct.from_spec(spec)
+    gen_spec, (rd, key, nk) = synth.kmeans_sections()
+    say("kmeans full: generating", n, "points on the device")
+    src = fill_aos_device(spec, 6)
+    S = spec.record_bytes
+    src[: n * S].view(n, S)[:, 4 * key:4 * key + 4] = \
+        synth.uniform_index_torch(6, 77, n, nk, "cuda").view(torch.uint8).view(n, 4)
+    want = src.cpu().numpy()
+    O = oaos(n, spec.elem_bytes)
+    assert O.nbytes == want.size
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    bounds = [n * i // cores for i in range(cores + 1)]
+    say("kmeans full: oracle loop on", cores, "threads")
+    with ThreadPoolExecutor(cores) as ex:
+        list(ex.map(lambda i: oracle.section(O, spec.dtypes, gen_spec.op, gen_spec.read, gen_spec.write, 0, None,
+                                             want, bounds[i], bounds[i + 1]), range(cores)))
+    say("kmeans full: oracle reduction")
+    table, bad = OR.reduce(O, spec.dtypes, rd, key, nk, want)
+    assert bad == 0 and sum(r[-1] for r in table) == n
+    out = torch.zeros(nk * (len(rd) + 1) * 8, dtype=torch.uint8, device="cuda")
+    prog = A.Program(st, [A.Section.from_spec(st, gen_spec), A.Section.reduce(st, rd, key, nk, out)])
+    La = A.Layout.aos(st)
+    cap = max(La.nbytes, A.Layout.soa(st).nbytes) + (1 << 26)
+    buf_a = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    buf_b = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    plans = [("planned", A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_MEASURED, catalogue=A.CAT_FULL,
+                                                             reps=3))),
+             ("all-AoS", A.Plan.uniform(prog, La)), ("all-SoA", A.Plan.uniform(prog, A.Layout.soa(st)))]
+    for name, plan in plans:
+        say("kmeans full: run", name, plan.choices())
+        buf_a[: La.nbytes].copy_(src)
+        out.zero_()
+        A.run(ctx, plan, La, buf_a, buf_b)
+        ctx.check()
+        _check(host(out).view(np.uint64), table, spec.dtypes, rd, {})
