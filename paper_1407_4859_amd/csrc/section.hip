@@ -349,19 +349,24 @@ static void launch_maxr(uint32_t nr, dim3 grid, const SectionArgs &a, hipStream_
 
 // ------------------------------------------------------------ reductions
 // A reduction adds the read fields of every record into row `key` of a small
-// table.  Pass 1: each workgroup accumulates its records into its own copy
-// of the table in LDS and writes that copy out; pass 2 adds the copies in
-// workgroup order.  Floating-point fields are summed in double and integer
-// fields in int64 (two's complement), the last column counts records.
-// Inside a workgroup, lanes of a wave whose records share one key are first
-// summed across the wave (a butterfly over the 64 lanes), so a table with
-// few rows does not serialise on LDS atomics to the same cell.
+// table.  Floating-point fields are summed in double and integer fields in
+// int64 (two's complement); the last column counts records.
+// Pass 1: each workgroup accumulates its records into LDS copies of the
+// table and writes their sum out.  The copies ("replicas") split the
+// workgroup's lanes into groups of 256 / replicas, so lanes whose records
+// share a key rarely add to the same LDS cell in one instruction.  When all
+// the live lanes of a wave share one key, the wave first sums across its 64
+// lanes (a butterfly) and one lane adds the result.
+// Pass 2: one workgroup per cell adds the workgroups' sums in a fixed order
+// (strided per thread, then a tree in LDS), so a given grid always adds in
+// the same order.
 struct ReduceArgs {
   const uint8_t *buf;
   uint32_t *err;
-  uint64_t *partials;  // [gridDim.x][cells]
+  uint64_t *partials;  // [cells][gridDim.x]
   int64_t n;
   uint32_t n_read, n_keys, cells, has_key;
+  uint32_t replicas;   // power of two in [1, 64]
   uint32_t fp_mask;    // bit q: read field q is floating point
   SField rd[ADHA_MAX_READ];
   SField key;
@@ -379,12 +384,20 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
   return v;
 }
 
+__device__ __forceinline__ void cell_add(uint64_t *cell, bool fp, double d, uint64_t u) {
+  if (fp) atomicAdd(reinterpret_cast<double *>(cell), d);
+  else atomicAdd(reinterpret_cast<unsigned long long *>(cell), (unsigned long long)u);
+}
+
+__device__ __forceinline__ uint64_t as_i64(uint64_t t) { return (uint64_t)(int64_t)(int32_t)(uint32_t)t; }
+
 template <int MAXR>
 __global__ __launch_bounds__(256) void reduce_partial_kernel(const ReduceArgs a) {
   extern __shared__ uint64_t tab[];
-  const uint32_t nr = a.n_read, cols = nr + 1;
-  for (uint32_t c = threadIdx.x; c < a.cells; c += 256) tab[c] = 0;
+  const uint32_t nr = a.n_read, cols = nr + 1, cells = a.cells;
+  for (uint32_t c = threadIdx.x; c < cells * a.replicas; c += 256) tab[c] = 0;
   __syncthreads();
+  uint64_t *mine = tab + (threadIdx.x * a.replicas / 256u) * cells;
   const uint32_t lane = threadIdx.x & 63u;
   bool bad = false;
   const uint64_t stride = (uint64_t)gridDim.x * 256u;
@@ -407,56 +420,71 @@ __global__ __launch_bounds__(256) void reduce_partial_kernel(const ReduceArgs a)
     const int32_t k0 = __shfl(k, lead, 64);
     const bool uniform = __ballot(ok && k != k0) == 0;
     if (uniform) {
-      uint64_t *row = tab + (uint32_t)k0 * cols;
+      uint64_t *row = mine + (uint32_t)k0 * cols;
 #pragma unroll
       for (int q = 0; q < MAXR; ++q)
         if (q < (int)nr) {
-          if (a.fp_mask >> q & 1u) {
-            const double v = wave_sum_f64(ok ? to_f64(a.rd[q].dt, t[q]) : 0.0);
-            if ((int)lane == lead) atomicAdd(reinterpret_cast<double *>(row + q), v);
-          } else {
-            const uint64_t v = wave_sum_u64(ok ? (uint64_t)(int64_t)(int32_t)(uint32_t)t[q] : (uint64_t)0);
-            if ((int)lane == lead) atomicAdd(reinterpret_cast<unsigned long long *>(row + q), (unsigned long long)v);
-          }
+          const bool fp = a.fp_mask >> q & 1u;
+          const double d = fp ? wave_sum_f64(ok ? to_f64(a.rd[q].dt, t[q]) : 0.0) : 0.0;
+          const uint64_t u = fp ? 0 : wave_sum_u64(ok ? as_i64(t[q]) : (uint64_t)0);
+          if ((int)lane == lead) cell_add(row + q, fp, d, u);
         }
-      if ((int)lane == lead)
-        atomicAdd(reinterpret_cast<unsigned long long *>(row + nr), (unsigned long long)__popcll(okm));
+      if ((int)lane == lead) cell_add(row + nr, false, 0.0, (uint64_t)__popcll(okm));
     } else if (ok) {
-      uint64_t *row = tab + (uint32_t)k * cols;
+      uint64_t *row = mine + (uint32_t)k * cols;
 #pragma unroll
       for (int q = 0; q < MAXR; ++q)
         if (q < (int)nr) {
-          if (a.fp_mask >> q & 1u)
-            atomicAdd(reinterpret_cast<double *>(row + q), to_f64(a.rd[q].dt, t[q]));
-          else
-            atomicAdd(reinterpret_cast<unsigned long long *>(row + q),
-                      (unsigned long long)(int64_t)(int32_t)(uint32_t)t[q]);
+          const bool fp = a.fp_mask >> q & 1u;
+          cell_add(row + q, fp, fp ? to_f64(a.rd[q].dt, t[q]) : 0.0, fp ? 0 : as_i64(t[q]));
         }
-      atomicAdd(reinterpret_cast<unsigned long long *>(row + nr), 1ull);
+      cell_add(row + nr, false, 0.0, 1);
     }
   }
   __syncthreads();
-  uint64_t *mine = a.partials + (uint64_t)blockIdx.x * a.cells;
-  for (uint32_t c = threadIdx.x; c < a.cells; c += 256) mine[c] = tab[c];
+  for (uint32_t c = threadIdx.x; c < cells; c += 256) {
+    const uint32_t q = c % cols;
+    const bool fp = q < nr && (a.fp_mask >> q & 1u);
+    double d = 0.0;
+    uint64_t u = 0;
+    for (uint32_t r = 0; r < a.replicas; ++r) {
+      const uint64_t v = tab[r * cells + c];
+      if (fp) d += __longlong_as_double((long long)v);
+      else u += v;
+    }
+    a.partials[(uint64_t)c * gridDim.x + blockIdx.x] = fp ? (uint64_t)__double_as_longlong(d) : u;
+  }
   if (bad) atomicOr(a.err, 1u);
 }
 
-// Pass 2: one thread per cell adds the workgroups' copies in order.
-__global__ __launch_bounds__(256) void reduce_final_kernel(const uint64_t *partials, uint32_t groups, uint32_t cells,
-                                                           uint32_t cols, uint32_t fp_mask, uint64_t *out) {
-  const uint32_t c = blockIdx.x * 256u + threadIdx.x;
-  if (c >= cells) return;
-  const uint32_t q = c % cols;
-  if (q + 1 < cols && (fp_mask >> q & 1u)) {
-    double s = 0.0;
-    for (uint32_t g = 0; g < groups; ++g) s += __longlong_as_double((long long)partials[(uint64_t)g * cells + c]);
-    out[c] = (uint64_t)__double_as_longlong(s);
-  } else {
-    uint64_t s = 0;
-    for (uint32_t g = 0; g < groups; ++g) s += partials[(uint64_t)g * cells + c];
-    out[c] = s;
+__global__ __launch_bounds__(256) void reduce_final_kernel(const uint64_t *partials, uint32_t groups, uint32_t cols,
+                                                           uint32_t fp_mask, uint64_t *out) {
+  __shared__ double sd[256];
+  __shared__ uint64_t su[256];
+  const uint32_t c = blockIdx.x, q = c % cols;
+  const bool fp = q + 1 < cols && (fp_mask >> q & 1u);
+  const uint64_t *p = partials + (uint64_t)c * groups;
+  double d = 0.0;
+  uint64_t u = 0;
+  for (uint32_t g = threadIdx.x; g < groups; g += 256) {
+    if (fp) d += __longlong_as_double((long long)p[g]);
+    else u += p[g];
   }
+  sd[threadIdx.x] = d;
+  su[threadIdx.x] = u;
+  __syncthreads();
+  for (uint32_t h = 128; h >= 1; h >>= 1) {
+    if (threadIdx.x < h) {
+      sd[threadIdx.x] += sd[threadIdx.x + h];
+      su[threadIdx.x] += su[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = fp ? (uint64_t)__double_as_longlong(sd[0]) : su[0];
 }
+
+// LDS for the table copies of one workgroup.
+static const size_t kReduceLdsBudget = 24576;
 
 static adha_status reduce_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l, const void *buf,
                                  void *out, hipStream_t stream) {
@@ -474,13 +502,15 @@ static adha_status reduce_launch(Ctx *ctx, const SectionDesc &sec, const LayoutD
     if (l.shape.dtype[sec.rd[q]] != ADHA_I32) a.fp_mask |= 1u << q;
   }
   if (sec.key >= 0) a.key = sfield(l, sec.key);
+  a.replicas = 1;
+  while (a.replicas < 64 && (size_t)a.cells * 8 * a.replicas * 2 <= kReduceLdsBudget) a.replicas *= 2;
   // a fixed grid for a given N, so the order of pass 2 is fixed too
   const uint64_t want = std::max<uint64_t>(1, ((uint64_t)n + 255) / 256);
   const uint32_t groups = (uint32_t)std::min<uint64_t>(want, (uint64_t)std::max(1, ctx->cu_count) * 4);
   uint64_t *partials = nullptr;
   ADHA_HIP(hipMallocAsync((void **)&partials, (size_t)groups * a.cells * 8, stream));
   a.partials = partials;
-  const size_t lds = (size_t)a.cells * 8;
+  const size_t lds = (size_t)a.cells * 8 * a.replicas;
   const uint32_t nr = a.n_read;
   if (nr <= 4) hipLaunchKernelGGL((reduce_partial_kernel<4>), dim3(groups), dim3(256), lds, stream, a);
   else if (nr <= 8) hipLaunchKernelGGL((reduce_partial_kernel<8>), dim3(groups), dim3(256), lds, stream, a);
@@ -488,8 +518,8 @@ static adha_status reduce_launch(Ctx *ctx, const SectionDesc &sec, const LayoutD
   else hipLaunchKernelGGL((reduce_partial_kernel<32>), dim3(groups), dim3(256), lds, stream, a);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess)
-    hipLaunchKernelGGL(reduce_final_kernel, dim3((a.cells + 255) / 256), dim3(256), 0, stream,
-                       (const uint64_t *)partials, groups, a.cells, nr + 1, a.fp_mask, (uint64_t *)out);
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(a.cells), dim3(256), 0, stream, (const uint64_t *)partials, groups,
+                       nr + 1, a.fp_mask, (uint64_t *)out);
   if (e == hipSuccess) e = hipGetLastError();
   (void)hipFreeAsync(partials, stream);
   if (e != hipSuccess) return fail(ADHA_ERR_DEVICE, "reduction launch failed: %s", hipGetErrorString(e));
