@@ -121,7 +121,14 @@ adha_status adha_ctx_cu_count(const adha_ctx *ctx, int32_t *out);
 typedef enum {
   /* 1 (default): a gather whose read fields share one interleaved group
    * fetches each neighbour's span with wide loads; 0: one load per field. */
-  ADHA_OPT_SPAN_GATHER = 1
+  ADHA_OPT_SPAN_GATHER = 1,
+  /* reductions: workgroups per compute unit in the first pass (1..32,
+   * default 8) */
+  ADHA_OPT_REDUCE_WG_PER_CU = 2,
+  /* reductions: LDS bytes a workgroup may spend on copies of the table
+   * (1024..65536, default 12288); more copies mean fewer lanes adding to
+   * one LDS cell at once */
+  ADHA_OPT_REDUCE_LDS_BYTES = 3
 } adha_option;
 adha_status adha_ctx_set_option(adha_ctx *ctx, adha_option opt, int64_t value);
 

@@ -205,6 +205,14 @@ adha_status adha_ctx_set_option(adha_ctx *ctx, adha_option opt, int64_t value) {
       if (value != 0 && value != 1) return fail(ADHA_ERR_INVALID, "span-gather option is 0 or 1");
       ctx->c.no_span = value == 0;
       return ADHA_OK;
+    case ADHA_OPT_REDUCE_WG_PER_CU:
+      if (value < 1 || value > 32) return fail(ADHA_ERR_INVALID, "workgroups per CU %lld not in [1, 32]", (long long)value);
+      ctx->c.reduce_wg_per_cu = (uint32_t)value;
+      return ADHA_OK;
+    case ADHA_OPT_REDUCE_LDS_BYTES:
+      if (value < 1024 || value > 65536) return fail(ADHA_ERR_INVALID, "LDS bytes %lld not in [1024, 65536]", (long long)value);
+      ctx->c.reduce_lds_bytes = (uint32_t)value;
+      return ADHA_OK;
     default:
       return fail(ADHA_ERR_INVALID, "unknown option %d", (int)opt);
   }

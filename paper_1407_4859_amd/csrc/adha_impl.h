@@ -212,6 +212,8 @@ struct Ctx {
   std::vector<float> model;  // trained / loaded cost-model parameters (empty = none)
   bool has_model = false;
   bool no_span = false;      // gathers always take the per-field path
+  uint32_t reduce_wg_per_cu = 8;     // reductions: first-pass workgroups per CU
+  uint32_t reduce_lds_bytes = 12288; // reductions: LDS for table copies
   ~Ctx();
 };
 

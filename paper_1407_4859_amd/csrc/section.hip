@@ -351,13 +351,18 @@ static void launch_maxr(uint32_t nr, dim3 grid, const SectionArgs &a, hipStream_
 // A reduction adds the read fields of every record into row `key` of a small
 // table.  Floating-point fields are summed in double and integer fields in
 // int64 (two's complement); the last column counts records.
-// Pass 1: each workgroup accumulates its records into LDS copies of the
-// table and writes their sum out.  The copies ("replicas") split the
-// workgroup's lanes into groups of 256 / replicas, so lanes whose records
-// share a key rarely add to the same LDS cell in one instruction.  When all
-// the live lanes of a wave share one key, the wave first sums across its 64
-// lanes (a butterfly) and one lane adds the result.
-// Pass 2: one workgroup per cell adds the workgroups' sums in a fixed order
+// Pass 1 has two forms.
+//  * Few keys (at most 8): every thread keeps its own sums for a slice of
+//    the table's columns in registers (all keys x up to 33 / 17 / 9 / 5
+//    columns) over a grid-stride walk of the records; gridDim.y runs over
+//    the column slices.  At the end the 64 lanes of each wave are summed
+//    (a butterfly), then the 4 waves in order.  No LDS atomics at all.
+//  * More keys: each workgroup adds its records into LDS copies of the
+//    table with LDS atomics.  The copies ("replicas") split the lanes into
+//    groups of 256 / replicas, so lanes whose records share a key rarely add
+//    to the same cell in one instruction.
+// Either way pass 1 writes one partial table per workgroup (column slice).
+// Pass 2: one workgroup per cell adds those partials in a fixed order
 // (strided per thread, then a tree in LDS), so a given grid always adds in
 // the same order.
 struct ReduceArgs {
@@ -398,11 +403,8 @@ __global__ __launch_bounds__(256) void reduce_partial_kernel(const ReduceArgs a)
   for (uint32_t c = threadIdx.x; c < cells * a.replicas; c += 256) tab[c] = 0;
   __syncthreads();
   uint64_t *mine = tab + (threadIdx.x * a.replicas / 256u) * cells;
-  const uint32_t lane = threadIdx.x & 63u;
   bool bad = false;
   const uint64_t stride = (uint64_t)gridDim.x * 256u;
-  // the loop bound is the same for every lane of the workgroup, so the
-  // wave-wide steps below run with all 64 lanes
   for (uint64_t i0 = (uint64_t)blockIdx.x * 256u; i0 < (uint64_t)a.n; i0 += stride) {
     const uint64_t i = i0 + threadIdx.x;
     const bool live = i < (uint64_t)a.n;
@@ -414,23 +416,7 @@ __global__ __launch_bounds__(256) void reduce_partial_kernel(const ReduceArgs a)
 #pragma unroll
     for (int q = 0; q < MAXR; ++q)
       if (q < (int)nr) t[q] = ok ? load_term(a.buf, a.rd[q], i) : 0;
-    const uint64_t okm = __ballot(ok);
-    if (okm == 0) continue;
-    const int lead = __ffsll((unsigned long long)okm) - 1;
-    const int32_t k0 = __shfl(k, lead, 64);
-    const bool uniform = __ballot(ok && k != k0) == 0;
-    if (uniform) {
-      uint64_t *row = mine + (uint32_t)k0 * cols;
-#pragma unroll
-      for (int q = 0; q < MAXR; ++q)
-        if (q < (int)nr) {
-          const bool fp = a.fp_mask >> q & 1u;
-          const double d = fp ? wave_sum_f64(ok ? to_f64(a.rd[q].dt, t[q]) : 0.0) : 0.0;
-          const uint64_t u = fp ? 0 : wave_sum_u64(ok ? as_i64(t[q]) : (uint64_t)0);
-          if ((int)lane == lead) cell_add(row + q, fp, d, u);
-        }
-      if ((int)lane == lead) cell_add(row + nr, false, 0.0, (uint64_t)__popcll(okm));
-    } else if (ok) {
+    if (ok) {
       uint64_t *row = mine + (uint32_t)k * cols;
 #pragma unroll
       for (int q = 0; q < MAXR; ++q)
@@ -453,6 +439,83 @@ __global__ __launch_bounds__(256) void reduce_partial_kernel(const ReduceArgs a)
       else u += v;
     }
     a.partials[(uint64_t)c * gridDim.x + blockIdx.x] = fp ? (uint64_t)__double_as_longlong(d) : u;
+  }
+  if (bad) atomicOr(a.err, 1u);
+}
+
+// Few keys: sums in registers.  KR >= n_keys rows, CR columns per slice.
+template <int KR, int CR>
+__global__ __launch_bounds__(256) void reduce_reg_kernel(const ReduceArgs a) {
+  __shared__ uint64_t wsum[4][KR * CR];
+  const uint32_t nr = a.n_read, cols = nr + 1;
+  const uint32_t c0 = blockIdx.y * CR;
+  const uint32_t nc = min((uint32_t)CR, cols - c0);
+  uint64_t acc[KR][CR];
+#pragma unroll
+  for (int kk = 0; kk < KR; ++kk)
+#pragma unroll
+    for (int c = 0; c < CR; ++c) acc[kk][c] = 0;
+  bool bad = false;
+  const uint64_t stride = (uint64_t)gridDim.x * 256u;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < (uint64_t)a.n; i += stride) {
+    int32_t k = 0;
+    if (a.has_key) k = (int32_t)(uint32_t)load_term(a.buf, a.key, i);
+    const bool ok = k >= 0 && (uint32_t)k < a.n_keys;
+    bad |= !ok;
+    uint64_t v[CR];
+#pragma unroll
+    for (int c = 0; c < CR; ++c) {
+      const uint32_t col = c0 + c;
+      v[c] = 0;
+      if ((uint32_t)c < nc) v[c] = col < nr ? load_term(a.buf, a.rd[col], i) : 1;
+    }
+#pragma unroll
+    for (int c = 0; c < CR; ++c) {
+      if ((uint32_t)c >= nc) continue;
+      const uint32_t col = c0 + c;
+      if (col < nr && (a.fp_mask >> col & 1u)) {
+        const double d = to_f64(a.rd[col].dt, v[c]);
+#pragma unroll
+        for (int kk = 0; kk < KR; ++kk) {
+          const double s = __longlong_as_double((long long)acc[kk][c]) + d;
+          acc[kk][c] = (ok && k == kk) ? (uint64_t)__double_as_longlong(s) : acc[kk][c];
+        }
+      } else {
+        const uint64_t u = col < nr ? as_i64(v[c]) : v[c];
+#pragma unroll
+        for (int kk = 0; kk < KR; ++kk) acc[kk][c] = (ok && k == kk) ? acc[kk][c] + u : acc[kk][c];
+      }
+    }
+  }
+  // the 64 lanes of each wave, then the 4 waves in order
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+#pragma unroll
+  for (int c = 0; c < CR; ++c) {
+    const uint32_t col = c0 + c;
+    const bool fp = col < nr && (a.fp_mask >> col & 1u);
+#pragma unroll
+    for (int kk = 0; kk < KR; ++kk) {
+      uint64_t x = acc[kk][c];
+      if (fp) x = (uint64_t)__double_as_longlong(wave_sum_f64(__longlong_as_double((long long)x)));
+      else x = wave_sum_u64(x);
+      if (lane == 0) wsum[wave][kk * CR + c] = x;
+    }
+  }
+  __syncthreads();
+  const uint32_t t = threadIdx.x;
+  if (t < (uint32_t)(KR * CR)) {
+    const uint32_t kk = t / CR, c = t % CR, col = c0 + c;
+    if (kk < a.n_keys && c < nc) {
+      const bool fp = col < nr && (a.fp_mask >> col & 1u);
+      double d = 0.0;
+      uint64_t u = 0;
+      for (int w = 0; w < 4; ++w) {
+        if (fp) d += __longlong_as_double((long long)wsum[w][t]);
+        else u += wsum[w][t];
+      }
+      const uint32_t cell = kk * cols + col;
+      a.partials[(uint64_t)cell * gridDim.x + blockIdx.x] = fp ? (uint64_t)__double_as_longlong(d) : u;
+    }
   }
   if (bad) atomicOr(a.err, 1u);
 }
@@ -483,9 +546,6 @@ __global__ __launch_bounds__(256) void reduce_final_kernel(const uint64_t *parti
   if (threadIdx.x == 0) out[c] = fp ? (uint64_t)__double_as_longlong(sd[0]) : su[0];
 }
 
-// LDS for the table copies of one workgroup.
-static const size_t kReduceLdsBudget = 24576;
-
 static adha_status reduce_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l, const void *buf,
                                  void *out, hipStream_t stream) {
   const int64_t n = l.shape.n;
@@ -503,23 +563,36 @@ static adha_status reduce_launch(Ctx *ctx, const SectionDesc &sec, const LayoutD
   }
   if (sec.key >= 0) a.key = sfield(l, sec.key);
   a.replicas = 1;
-  while (a.replicas < 64 && (size_t)a.cells * 8 * a.replicas * 2 <= kReduceLdsBudget) a.replicas *= 2;
+  while (a.replicas < 64 && (size_t)a.cells * 8 * a.replicas * 2 <= ctx->reduce_lds_bytes) a.replicas *= 2;
+  const uint32_t nr = a.n_read, cols = nr + 1;
+  // few keys: sums in registers, KR rows by CR columns per slice
+  uint32_t KR = 0, CR = 0;
+  if (sec.n_keys <= 1) KR = 1, CR = 33;
+  else if (sec.n_keys <= 2) KR = 2, CR = 17;
+  else if (sec.n_keys <= 4) KR = 4, CR = 9;
+  else if (sec.n_keys <= 8) KR = 8, CR = 5;
+  const uint32_t slices = KR ? (cols + CR - 1) / CR : 1;
   // a fixed grid for a given N, so the order of pass 2 is fixed too
   const uint64_t want = std::max<uint64_t>(1, ((uint64_t)n + 255) / 256);
-  const uint32_t groups = (uint32_t)std::min<uint64_t>(want, (uint64_t)std::max(1, ctx->cu_count) * 4);
+  const uint64_t budget = (uint64_t)std::max(1, ctx->cu_count) * ctx->reduce_wg_per_cu;
+  const uint32_t groups = (uint32_t)std::min<uint64_t>(want, std::max<uint64_t>(1, budget / slices));
   uint64_t *partials = nullptr;
   ADHA_HIP(hipMallocAsync((void **)&partials, (size_t)groups * a.cells * 8, stream));
   a.partials = partials;
   const size_t lds = (size_t)a.cells * 8 * a.replicas;
-  const uint32_t nr = a.n_read;
-  if (nr <= 4) hipLaunchKernelGGL((reduce_partial_kernel<4>), dim3(groups), dim3(256), lds, stream, a);
-  else if (nr <= 8) hipLaunchKernelGGL((reduce_partial_kernel<8>), dim3(groups), dim3(256), lds, stream, a);
-  else if (nr <= 16) hipLaunchKernelGGL((reduce_partial_kernel<16>), dim3(groups), dim3(256), lds, stream, a);
-  else hipLaunchKernelGGL((reduce_partial_kernel<32>), dim3(groups), dim3(256), lds, stream, a);
+  const dim3 grid(groups, slices);
+  if (KR == 1) hipLaunchKernelGGL((reduce_reg_kernel<1, 33>), grid, dim3(256), 0, stream, a);
+  else if (KR == 2) hipLaunchKernelGGL((reduce_reg_kernel<2, 17>), grid, dim3(256), 0, stream, a);
+  else if (KR == 4) hipLaunchKernelGGL((reduce_reg_kernel<4, 9>), grid, dim3(256), 0, stream, a);
+  else if (KR == 8) hipLaunchKernelGGL((reduce_reg_kernel<8, 5>), grid, dim3(256), 0, stream, a);
+  else if (nr <= 4) hipLaunchKernelGGL((reduce_partial_kernel<4>), grid, dim3(256), lds, stream, a);
+  else if (nr <= 8) hipLaunchKernelGGL((reduce_partial_kernel<8>), grid, dim3(256), lds, stream, a);
+  else if (nr <= 16) hipLaunchKernelGGL((reduce_partial_kernel<16>), grid, dim3(256), lds, stream, a);
+  else hipLaunchKernelGGL((reduce_partial_kernel<32>), grid, dim3(256), lds, stream, a);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess)
     hipLaunchKernelGGL(reduce_final_kernel, dim3(a.cells), dim3(256), 0, stream, (const uint64_t *)partials, groups,
-                       nr + 1, a.fp_mask, (uint64_t *)out);
+                       cols, a.fp_mask, (uint64_t *)out);
   if (e == hipSuccess) e = hipGetLastError();
   (void)hipFreeAsync(partials, stream);
   if (e != hipSuccess) return fail(ADHA_ERR_DEVICE, "reduction launch failed: %s", hipGetErrorString(e));
