@@ -44,10 +44,28 @@ __device__ __forceinline__ uint64_t faddr(const SField &F, uint64_t r) {
   return F.base + (r >> F.logT) * F.TS + F.pT + (r & ((1ull << F.logT) - 1)) * F.e;
 }
 
-__device__ __forceinline__ uint64_t load_term(const uint8_t *buf, const SField &F, uint64_t r) {
-  const uint32_t *p = reinterpret_cast<const uint32_t *>(buf + faddr(F, r));
-  if (F.e == 4) return p[0];
-  return (uint64_t)p[0] | ((uint64_t)p[1] << 32);
+// The raw words of up to N terms.  Loads only fill registers; the terms are
+// assembled afterwards (word() below), so no arithmetic sits between one
+// load and the next and all of them are in flight together.  W8: some term
+// is 8 bytes wide, so a second word is loaded per term -- for a 4-byte term
+// that second load reads the same word again and stays inside the field.
+template <int N, bool W8>
+struct Words {
+  uint32_t lo[N];
+  uint32_t hi[W8 ? N : 1];
+  __device__ __forceinline__ void load(int q, const uint8_t *buf, const SField &F, uint64_t r) {
+    const uint32_t *p = reinterpret_cast<const uint32_t *>(buf + faddr(F, r));
+    lo[q] = p[0];
+    if constexpr (W8) hi[q] = p[F.e >> 3];
+  }
+  __device__ __forceinline__ uint64_t term(int q, const SField &F) const {
+    if constexpr (W8) return (uint64_t)lo[q] | ((uint64_t)(F.e == 8 ? hi[q] : 0u) << 32);
+    return lo[q];
+  }
+};
+
+__device__ __forceinline__ uint32_t load_word(const uint8_t *buf, const SField &F, uint64_t r) {
+  return *reinterpret_cast<const uint32_t *>(buf + faddr(F, r));
 }
 
 __device__ __forceinline__ float to_f32(uint32_t dt, uint64_t b) {
@@ -101,7 +119,8 @@ __device__ __forceinline__ void store_acc(uint8_t *buf, const SField &W, uint64_
 
 // DG = 0: direct section; otherwise a gather of at most DG neighbours.
 // MAXR: bound on the number of read fields (loads are unrolled to it).
-template <int OP, int DG, int MAXR>
+// W8: some read field is 8 bytes wide.
+template <int OP, int DG, int MAXR, bool W8>
 __global__ __launch_bounds__(256) void section_kernel(const SectionArgs a) {
   const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
   if (i >= (uint64_t)a.n) return;
@@ -110,10 +129,13 @@ __global__ __launch_bounds__(256) void section_kernel(const SectionArgs a) {
   acc[0] = acc[1] = Acc{0.0f, 0.0, 0u};
 
   if constexpr (DG == 0) {
-    uint64_t tv[MAXR];
+    Words<MAXR, W8> w;
 #pragma unroll
     for (int q = 0; q < MAXR; ++q)
-      if (q < (int)nr) tv[q] = load_term(a.buf, a.rd[q], i);
+      if (q < (int)nr) w.load(q, a.buf, a.rd[q], i);
+    uint64_t tv[MAXR];
+#pragma unroll
+    for (int q = 0; q < MAXR; ++q) tv[q] = q < (int)nr ? w.term(q, a.rd[q]) : 0;
     if constexpr (OP == ADHA_OP_GEN || OP == ADHA_OP_SUM) {
 #pragma unroll
       for (int q = 0; q < MAXR; ++q)
@@ -152,16 +174,17 @@ __global__ __launch_bounds__(256) void section_kernel(const SectionArgs a) {
     for (int j0 = 0; j0 < deg; j0 += NB) {
 #pragma unroll
       for (int b = 0; b < NB; ++b) nxt[b] = j0 + NB + b < deg ? row[j0 + NB + b] : 0;
-      uint64_t t[NB][MAXR];
+      Words<MAXR, W8> w[NB];
       bool ok[NB];
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const bool live = j0 + b < deg;
         ok[b] = live && cur[b] >= 0 && (int64_t)cur[b] < a.n;
         bad |= live && !ok[b];
+        const uint64_t rr = ok[b] ? (uint64_t)cur[b] : 0;   // a bad neighbour loads record 0, unused
 #pragma unroll
         for (int q = 0; q < MAXR; ++q)
-          if (q < (int)nr) t[b][q] = ok[b] ? load_term(a.buf, a.rd[q], (uint64_t)cur[b]) : 0;
+          if (q < (int)nr) w[b].load(q, a.buf, a.rd[q], rr);
       }
 #pragma unroll
       for (int b = 0; b < NB; ++b)
@@ -169,8 +192,9 @@ __global__ __launch_bounds__(256) void section_kernel(const SectionArgs a) {
 #pragma unroll
           for (int q = 0; q < MAXR; ++q)
             if (q < (int)nr) {
-              fold(acc[0], 0, a.wr[0].dt, a.rd[q].dt, t[b][q]);
-              if (nw > 1) fold(acc[1], 1, a.wr[1].dt, a.rd[q].dt, t[b][q]);
+              const uint64_t t = w[b].term(q, a.rd[q]);
+              fold(acc[0], 0, a.wr[0].dt, a.rd[q].dt, t);
+              if (nw > 1) fold(acc[1], 1, a.wr[1].dt, a.rd[q].dt, t);
             }
         }
 #pragma unroll
@@ -339,12 +363,20 @@ static SField sfield(const LayoutDesc &l, int f) {
   return s;
 }
 
+template <int OP, int DG, bool W8>
+static void launch_maxr_w(uint32_t nr, dim3 grid, const SectionArgs &a, hipStream_t st) {
+  if (nr <= 4) hipLaunchKernelGGL((section_kernel<OP, DG, 4, W8>), grid, dim3(256), 0, st, a);
+  else if (nr <= 8) hipLaunchKernelGGL((section_kernel<OP, DG, 8, W8>), grid, dim3(256), 0, st, a);
+  else if (nr <= 16) hipLaunchKernelGGL((section_kernel<OP, DG, 16, W8>), grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((section_kernel<OP, DG, 32, W8>), grid, dim3(256), 0, st, a);
+}
+
 template <int OP, int DG>
 static void launch_maxr(uint32_t nr, dim3 grid, const SectionArgs &a, hipStream_t st) {
-  if (nr <= 4) hipLaunchKernelGGL((section_kernel<OP, DG, 4>), grid, dim3(256), 0, st, a);
-  else if (nr <= 8) hipLaunchKernelGGL((section_kernel<OP, DG, 8>), grid, dim3(256), 0, st, a);
-  else if (nr <= 16) hipLaunchKernelGGL((section_kernel<OP, DG, 16>), grid, dim3(256), 0, st, a);
-  else hipLaunchKernelGGL((section_kernel<OP, DG, 32>), grid, dim3(256), 0, st, a);
+  bool w8 = false;
+  for (uint32_t q = 0; q < nr; ++q) w8 |= a.rd[q].e == 8;
+  if (w8) launch_maxr_w<OP, DG, true>(nr, grid, a, st);
+  else launch_maxr_w<OP, DG, false>(nr, grid, a, st);
 }
 
 // ------------------------------------------------------------ reductions
@@ -396,7 +428,7 @@ __device__ __forceinline__ void cell_add(uint64_t *cell, bool fp, double d, uint
 
 __device__ __forceinline__ uint64_t as_i64(uint64_t t) { return (uint64_t)(int64_t)(int32_t)(uint32_t)t; }
 
-template <int MAXR>
+template <int MAXR, bool W8>
 __global__ __launch_bounds__(256) void reduce_partial_kernel(const ReduceArgs a) {
   extern __shared__ uint64_t tab[];
   const uint32_t nr = a.n_read, cols = nr + 1, cells = a.cells;
@@ -409,20 +441,23 @@ __global__ __launch_bounds__(256) void reduce_partial_kernel(const ReduceArgs a)
     const uint64_t i = i0 + threadIdx.x;
     const bool live = i < (uint64_t)a.n;
     int32_t k = 0;
-    if (a.has_key && live) k = (int32_t)(uint32_t)load_term(a.buf, a.key, i);
+    if (a.has_key && live) k = (int32_t)load_word(a.buf, a.key, i);
     const bool ok = live && k >= 0 && (uint32_t)k < a.n_keys;
     bad |= live && !ok;
-    uint64_t t[MAXR];
+    Words<MAXR, W8> w;
+    const uint64_t rr = live ? i : 0;     // lanes past N load record 0, unused
 #pragma unroll
     for (int q = 0; q < MAXR; ++q)
-      if (q < (int)nr) t[q] = ok ? load_term(a.buf, a.rd[q], i) : 0;
+      if (q < (int)nr) w.load(q, a.buf, a.rd[q], rr);
+
     if (ok) {
       uint64_t *row = mine + (uint32_t)k * cols;
 #pragma unroll
       for (int q = 0; q < MAXR; ++q)
         if (q < (int)nr) {
           const bool fp = a.fp_mask >> q & 1u;
-          cell_add(row + q, fp, fp ? to_f64(a.rd[q].dt, t[q]) : 0.0, fp ? 0 : as_i64(t[q]));
+          const uint64_t t = w.term(q, a.rd[q]);
+          cell_add(row + q, fp, fp ? to_f64(a.rd[q].dt, t) : 0.0, fp ? 0 : as_i64(t));
         }
       cell_add(row + nr, false, 0.0, 1);
     }
@@ -444,7 +479,7 @@ __global__ __launch_bounds__(256) void reduce_partial_kernel(const ReduceArgs a)
 }
 
 // Few keys: sums in registers.  KR >= n_keys rows, CR columns per slice.
-template <int KR, int CR>
+template <int KR, int CR, bool W8>
 __global__ __launch_bounds__(256) void reduce_reg_kernel(const ReduceArgs a) {
   __shared__ uint64_t wsum[4][KR * CR];
   const uint32_t nr = a.n_read, cols = nr + 1;
@@ -459,16 +494,16 @@ __global__ __launch_bounds__(256) void reduce_reg_kernel(const ReduceArgs a) {
   const uint64_t stride = (uint64_t)gridDim.x * 256u;
   for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < (uint64_t)a.n; i += stride) {
     int32_t k = 0;
-    if (a.has_key) k = (int32_t)(uint32_t)load_term(a.buf, a.key, i);
+    if (a.has_key) k = (int32_t)load_word(a.buf, a.key, i);
     const bool ok = k >= 0 && (uint32_t)k < a.n_keys;
     bad |= !ok;
+    Words<CR, W8> w;
+#pragma unroll
+    for (int c = 0; c < CR; ++c)
+      if (c0 + c < nr) w.load(c, a.buf, a.rd[c0 + c], i);
     uint64_t v[CR];
 #pragma unroll
-    for (int c = 0; c < CR; ++c) {
-      const uint32_t col = c0 + c;
-      v[c] = 0;
-      if ((uint32_t)c < nc) v[c] = col < nr ? load_term(a.buf, a.rd[col], i) : 1;
-    }
+    for (int c = 0; c < CR; ++c) v[c] = c0 + c < nr ? w.term(c, a.rd[c0 + c]) : 1;
 #pragma unroll
     for (int c = 0; c < CR; ++c) {
       if ((uint32_t)c >= nc) continue;
@@ -546,6 +581,18 @@ __global__ __launch_bounds__(256) void reduce_final_kernel(const uint64_t *parti
   if (threadIdx.x == 0) out[c] = fp ? (uint64_t)__double_as_longlong(sd[0]) : su[0];
 }
 
+template <bool W8>
+static void reduce_dispatch(uint32_t KR, uint32_t nr, dim3 grid, size_t lds, hipStream_t stream, const ReduceArgs &a) {
+  if (KR == 1) hipLaunchKernelGGL((reduce_reg_kernel<1, 33, W8>), grid, dim3(256), 0, stream, a);
+  else if (KR == 2) hipLaunchKernelGGL((reduce_reg_kernel<2, 17, W8>), grid, dim3(256), 0, stream, a);
+  else if (KR == 4) hipLaunchKernelGGL((reduce_reg_kernel<4, 9, W8>), grid, dim3(256), 0, stream, a);
+  else if (KR == 8) hipLaunchKernelGGL((reduce_reg_kernel<8, 5, W8>), grid, dim3(256), 0, stream, a);
+  else if (nr <= 4) hipLaunchKernelGGL((reduce_partial_kernel<4, W8>), grid, dim3(256), lds, stream, a);
+  else if (nr <= 8) hipLaunchKernelGGL((reduce_partial_kernel<8, W8>), grid, dim3(256), lds, stream, a);
+  else if (nr <= 16) hipLaunchKernelGGL((reduce_partial_kernel<16, W8>), grid, dim3(256), lds, stream, a);
+  else hipLaunchKernelGGL((reduce_partial_kernel<32, W8>), grid, dim3(256), lds, stream, a);
+}
+
 static adha_status reduce_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l, const void *buf,
                                  void *out, hipStream_t stream) {
   const int64_t n = l.shape.n;
@@ -581,14 +628,10 @@ static adha_status reduce_launch(Ctx *ctx, const SectionDesc &sec, const LayoutD
   a.partials = partials;
   const size_t lds = (size_t)a.cells * 8 * a.replicas;
   const dim3 grid(groups, slices);
-  if (KR == 1) hipLaunchKernelGGL((reduce_reg_kernel<1, 33>), grid, dim3(256), 0, stream, a);
-  else if (KR == 2) hipLaunchKernelGGL((reduce_reg_kernel<2, 17>), grid, dim3(256), 0, stream, a);
-  else if (KR == 4) hipLaunchKernelGGL((reduce_reg_kernel<4, 9>), grid, dim3(256), 0, stream, a);
-  else if (KR == 8) hipLaunchKernelGGL((reduce_reg_kernel<8, 5>), grid, dim3(256), 0, stream, a);
-  else if (nr <= 4) hipLaunchKernelGGL((reduce_partial_kernel<4>), grid, dim3(256), lds, stream, a);
-  else if (nr <= 8) hipLaunchKernelGGL((reduce_partial_kernel<8>), grid, dim3(256), lds, stream, a);
-  else if (nr <= 16) hipLaunchKernelGGL((reduce_partial_kernel<16>), grid, dim3(256), lds, stream, a);
-  else hipLaunchKernelGGL((reduce_partial_kernel<32>), grid, dim3(256), lds, stream, a);
+  bool w8 = false;
+  for (int f : sec.rd) w8 |= l.shape.ebytes[f] == 8;
+  if (w8) reduce_dispatch<true>(KR, nr, grid, lds, stream, a);
+  else reduce_dispatch<false>(KR, nr, grid, lds, stream, a);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess)
     hipLaunchKernelGGL(reduce_final_kernel, dim3(a.cells), dim3(256), 0, stream, (const uint64_t *)partials, groups,
@@ -652,10 +695,10 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
       launch_maxr<ADHA_OP_SUM, 0>(nr, grid, a, stream);
       break;
     case ADHA_OP_MULADD3:
-      hipLaunchKernelGGL((section_kernel<ADHA_OP_MULADD3, 0, 4>), grid, dim3(256), 0, stream, a);
+      hipLaunchKernelGGL((section_kernel<ADHA_OP_MULADD3, 0, 4, true>), grid, dim3(256), 0, stream, a);
       break;
     case ADHA_OP_SUB2:
-      hipLaunchKernelGGL((section_kernel<ADHA_OP_SUB2, 0, 4>), grid, dim3(256), 0, stream, a);
+      hipLaunchKernelGGL((section_kernel<ADHA_OP_SUB2, 0, 4, true>), grid, dim3(256), 0, stream, a);
       break;
     default:
       return fail(ADHA_ERR_UNSUPPORTED, "unknown op %d", sec.op);
