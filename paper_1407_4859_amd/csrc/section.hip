@@ -395,9 +395,9 @@ static void launch_maxr(uint32_t nr, dim3 grid, const SectionArgs &a, hipStream_
 // int64 (two's complement); the last column counts records.
 // Pass 1 has two forms.
 //  * Few keys (at most 8): every thread keeps its own sums for a slice of
-//    the table's columns in registers (all keys x up to 33 / 17 / 9 / 5
-//    columns) over a grid-stride walk of the records; gridDim.y runs over
-//    the column slices.  At the end the 64 lanes of each wave are summed
+//    the table's columns in registers (all keys x about 40 / keys columns)
+//    over a grid-stride walk of the records; gridDim.y runs over the
+//    column slices.  At the end the 64 lanes of each wave are summed
 //    (a butterfly), then the 4 waves in order.  No LDS atomics at all.
 //  * More keys: each workgroup adds its records into LDS copies of the
 //    table with LDS atomics.  The copies ("replicas") split the lanes into
@@ -597,7 +597,11 @@ template <bool W8>
 static void reduce_dispatch(uint32_t KR, uint32_t nr, dim3 grid, size_t lds, hipStream_t stream, const ReduceArgs &a) {
   if (KR == 1) hipLaunchKernelGGL((reduce_reg_kernel<1, 33, W8>), grid, dim3(256), 0, stream, a);
   else if (KR == 2) hipLaunchKernelGGL((reduce_reg_kernel<2, 17, W8>), grid, dim3(256), 0, stream, a);
+  else if (KR == 3) hipLaunchKernelGGL((reduce_reg_kernel<3, 11, W8>), grid, dim3(256), 0, stream, a);
   else if (KR == 4) hipLaunchKernelGGL((reduce_reg_kernel<4, 9, W8>), grid, dim3(256), 0, stream, a);
+  else if (KR == 5) hipLaunchKernelGGL((reduce_reg_kernel<5, 7, W8>), grid, dim3(256), 0, stream, a);
+  else if (KR == 6) hipLaunchKernelGGL((reduce_reg_kernel<6, 6, W8>), grid, dim3(256), 0, stream, a);
+  else if (KR == 7) hipLaunchKernelGGL((reduce_reg_kernel<7, 5, W8>), grid, dim3(256), 0, stream, a);
   else if (KR == 8) hipLaunchKernelGGL((reduce_reg_kernel<8, 5, W8>), grid, dim3(256), 0, stream, a);
   else if (nr <= 4) hipLaunchKernelGGL((reduce_partial_kernel<4, W8>), grid, dim3(256), lds, stream, a);
   else if (nr <= 8) hipLaunchKernelGGL((reduce_partial_kernel<8, W8>), grid, dim3(256), lds, stream, a);
@@ -624,12 +628,10 @@ static adha_status reduce_launch(Ctx *ctx, const SectionDesc &sec, const LayoutD
   a.replicas = 1;
   while (a.replicas < 64 && (size_t)a.cells * 8 * a.replicas * 2 <= ctx->reduce_lds_bytes) a.replicas *= 2;
   const uint32_t nr = a.n_read, cols = nr + 1;
-  // few keys: sums in registers, KR rows by CR columns per slice
-  uint32_t KR = 0, CR = 0;
-  if (sec.n_keys <= 1) KR = 1, CR = 33;
-  else if (sec.n_keys <= 2) KR = 2, CR = 17;
-  else if (sec.n_keys <= 4) KR = 4, CR = 9;
-  else if (sec.n_keys <= 8) KR = 8, CR = 5;
+  // few keys: sums in registers, KR = n_keys rows by CR columns per slice
+  // (about 40 accumulators per thread)
+  static const uint32_t kCols[9] = {0, 33, 17, 11, 9, 7, 6, 5, 5};
+  const uint32_t KR = sec.n_keys <= 8 ? sec.n_keys : 0, CR = kCols[KR];
   const uint32_t slices = KR ? (cols + CR - 1) / CR : 1;
   // a fixed grid for a given N, so the order of pass 2 is fixed too
   const uint64_t want = std::max<uint64_t>(1, ((uint64_t)n + 255) / 256);

@@ -94,7 +94,10 @@ def test_reduce_matches_oracle_on_layouts(ctx, n):
         _check(got, table, spec.dtypes, read, _abs_sums(O, spec.dtypes, read, 6, 5, buf_h))
 
 
-@pytest.mark.parametrize("n_keys,read", [(1, [0, 1, 7, 9]), (64, [0, 1, 2, 3]), (128, list(range(6)) + [7] + [8, 9, 10]),
+@pytest.mark.parametrize("n_keys,read", [(1, [0, 1, 7, 9]), (1, [0, 1, 2]), (2, [0, 7, 8, 10]), (3, [1, 2, 3, 4, 5]),
+                                         (6, [0, 2, 7, 9, 10]), (7, [0, 1, 2, 3, 4, 5, 7, 10]),
+                                         (8, [0, 1, 7, 8, 9, 10]), (9, [0, 1, 7]), (64, [0, 1, 2, 3]),
+                                         (128, list(range(6)) + [7] + [8, 9, 10]),
                                          (409, [0, 1, 2, 3, 4, 5, 7, 8, 10])])
 def test_reduce_key_counts_and_no_key(ctx, n_keys, read):
     n = 100_000
