@@ -297,6 +297,22 @@ adha_status adha_section_bytes(const adha_section *sec, uint64_t *out);
  * byte count (the unit of the gathers' transaction roofline). */
 adha_status adha_section_effective_bytes(const adha_section *sec, const adha_layout *l, double *out);
 
+/* ------------------------------------------------------------ host backend */
+/* The same section on host memory with `threads` host threads (0: one per
+ * core, at most 64), for plans that map sections to the CPU (section 2:
+ * each section runs on the CPU or the GPU).  Results are identical to the
+ * device kernels' (the same operations in the same order and rounding; a
+ * reduction's double sums may differ in rounding order only).  idx is a
+ * host array for gathers; a reduction writes its table to the host array
+ * `table` (the device array given at creation is not touched).  *bad (may
+ * be NULL) receives the number of out-of-range indices or keys. */
+adha_status adha_host_section_run(const adha_section *sec, const adha_layout *l, void *buf, uint64_t buf_cap,
+                                  const int32_t *idx, uint64_t idx_count, void *table, uint64_t table_cap,
+                                  uint32_t threads, uint64_t *bad);
+/* A remap between host buffers (padding zero-filled; out of place). */
+adha_status adha_host_remap(const adha_layout *src_l, const void *src, uint64_t src_cap,
+                            const adha_layout *dst_l, void *dst, uint64_t dst_cap, uint32_t threads);
+
 /* ------------------------------------------------------------ programs */
 adha_status adha_program_create(const adha_struct *s, uint32_t k, const adha_section *const *secs,
                                 adha_program **out);

@@ -113,6 +113,8 @@ _SIGS = {
     "adha_section_run": ([P, P, P, P, U64, P, U64, P], I32T),
     "adha_section_bytes": ([P, ctypes.POINTER(U64)], I32T),
     "adha_section_effective_bytes": ([P, P, ctypes.POINTER(ctypes.c_double)], I32T),
+    "adha_host_section_run": ([P, P, P, U64, P, U64, P, U64, U32, ctypes.POINTER(U64)], I32T),
+    "adha_host_remap": ([P, P, U64, P, P, U64, U32], I32T),
     "adha_program_create": ([P, U32, P, PP], I32T),
     "adha_program_destroy": ([P], I32T),
     "adha_affinity": ([P, U32, U32, P], I32T),
@@ -532,6 +534,32 @@ def describe(src_l: Layout, dst_l: Layout, cu_count: int = 256) -> dict:
     out.update(tile_records=r.shape.tile_records, slots=r.shape.slots, pad_shift=r.shape.pad_shift,
                wg_per_cu=r.shape.wg_per_cu, order=r.shape.order, nontemporal=r.shape.nontemporal)
     return out
+
+
+def _host(a):
+    """(pointer, capacity in bytes) of a host numpy array or CPU tensor (or (None, 0))."""
+    if a is None:
+        return None, 0
+    if hasattr(a, "ctypes"):
+        return ctypes.c_void_p(a.ctypes.data), a.nbytes
+    return ctypes.c_void_p(a.data_ptr()), a.numel() * a.element_size()
+
+
+def host_section_run(sec: Section, layout: Layout, buf, idx=None, table=None, threads: int = 0) -> int:
+    """Runs a section on host memory; returns the number of out-of-range
+    indices or keys met."""
+    bp, bc = _host(buf)
+    ip, ic = _host(idx)
+    tp, tc = _host(table)
+    bad = ctypes.c_uint64()
+    check(lib().adha_host_section_run(sec.h, layout.h, bp, bc, ip, ic // 4, tp, tc, threads, ctypes.byref(bad)))
+    return bad.value
+
+
+def host_remap(src_l: Layout, src, dst_l: Layout, dst, threads: int = 0):
+    sp, sc = _host(src)
+    dp, dc = _host(dst)
+    check(lib().adha_host_remap(src_l.h, sp, sc, dst_l.h, dp, dc, threads))
 
 
 def section_run(ctx: Ctx, sec: Section, layout: Layout, buf, idx=None, stream=None):

@@ -178,6 +178,15 @@ adha_status prepared_for(Ctx *ctx, const adha_layout *a, const adha_layout *b, c
 adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l, void *buf,
                            const int32_t *idx, hipStream_t stream, void *out_override = nullptr);
 
+// ------------------------------------------------------------------ host backend
+uint32_t host_threads(const Ctx *ctx);
+// A section on host memory; a reduction writes its table (host) to `table`.
+// *bad_out counts out-of-range gather indices or reduction keys.
+adha_status host_section_run(uint32_t threads, const SectionDesc &sec, const LayoutDesc &l, uint8_t *buf,
+                             const int32_t *idx, void *table, uint64_t *bad_out);
+adha_status host_remap(uint32_t threads, const LayoutDesc &a, const uint8_t *src, const LayoutDesc &b,
+                       uint8_t *dst);
+
 // ------------------------------------------------------------------ MLP
 adha_status mlp_forward(Ctx *ctx, const float *params, const float *x, uint32_t batch, float *y,
                         hipStream_t stream);
@@ -214,6 +223,7 @@ struct Ctx {
   bool no_span = false;      // gathers always take the per-field path
   uint32_t reduce_wg_per_cu = 8;     // reductions: first-pass workgroups per CU
   uint32_t reduce_lds_bytes = 12288; // reductions: LDS for table copies
+  uint32_t host_threads = 0;         // host backend threads (0: one per core, at most 64)
   ~Ctx();
 };
 

@@ -1,0 +1,277 @@
+// Host backend: sections, reductions and remaps on host memory.
+//
+// The paper maps each section to the CPU or the GPU of its platform and
+// weighs that choice in the shortest path (section 2, third paragraph;
+// Table 4 maps the Medical sections to both).  These are the host versions
+// of the device kernels, with the same semantics and the same rounding:
+// terms are read before any write, folded in the order the section fixes,
+// and every floating-point step is a single IEEE operation in the write
+// field's type (this file is compiled without contraction into fused
+// multiply-adds, and x86-64 evaluates float and double in their own
+// precision).  Records are split into contiguous ranges over host threads;
+// a reduction adds the threads' tables in thread order.
+#include <algorithm>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "adha_impl.h"
+
+namespace adha {
+
+namespace {
+
+template <class Fn>
+void parallel_ranges(int64_t n, uint32_t threads, Fn fn) {
+  const uint32_t t = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(threads, (n + 4095) / 4096));
+  if (t <= 1) {
+    fn(0u, (int64_t)0, n);
+    return;
+  }
+  std::vector<std::thread> pool;
+  pool.reserve(t);
+  for (uint32_t k = 0; k < t; ++k) {
+    const int64_t b = n * k / t, e = n * (k + 1) / t;
+    pool.emplace_back([=] { fn(k, b, e); });
+  }
+  for (auto &th : pool) th.join();
+}
+
+inline uint64_t read_term(const uint8_t *buf, const LayoutDesc &l, int64_t r, int f) {
+  uint64_t v = 0;
+  std::memcpy(&v, buf + l.addr(r, f), l.shape.ebytes[f]);
+  return v;
+}
+
+inline float as_f32(int32_t dt, uint64_t b) {
+  if (dt == ADHA_F32) {
+    float x;
+    const uint32_t u = (uint32_t)b;
+    std::memcpy(&x, &u, 4);
+    return x;
+  }
+  if (dt == ADHA_I32) return (float)(int32_t)(uint32_t)b;
+  double d;
+  std::memcpy(&d, &b, 8);
+  return (float)d;
+}
+
+inline double as_f64(int32_t dt, uint64_t b) {
+  if (dt == ADHA_F32) return (double)as_f32(ADHA_F32, b);
+  if (dt == ADHA_I32) return (double)(int32_t)(uint32_t)b;
+  double d;
+  std::memcpy(&d, &b, 8);
+  return d;
+}
+
+inline uint32_t word32(int32_t dt, uint64_t b) {
+  return dt == ADHA_F64 ? (uint32_t)b ^ (uint32_t)(b >> 32) : (uint32_t)b;
+}
+
+struct HAcc {
+  float f = 0.0f;
+  double d = 0.0;
+  uint32_t u = 0;
+};
+
+// Write k's accumulator after one more term (GEN and SUM).
+inline void fold_term(HAcc &a, int k, int32_t wdt, int32_t tdt, uint64_t t) {
+  if (wdt == ADHA_F32) {
+    const float v = as_f32(tdt, t);
+    if (k == 0) a.f = a.f + v;
+    else {
+      const float h = a.f * 0.5f;
+      a.f = h + v;
+    }
+  } else if (wdt == ADHA_F64) {
+    const double v = as_f64(tdt, t);
+    if (k == 0) a.d = a.d + v;
+    else {
+      const double h = a.d * 0.5;
+      a.d = h + v;
+    }
+  } else {
+    const uint32_t u = word32(tdt, t);
+    a.u = k == 0 ? a.u + u : (a.u ^ u) * 16777619u;
+  }
+}
+
+inline void write_acc(uint8_t *buf, const LayoutDesc &l, int64_t r, int f, const HAcc &a) {
+  uint8_t *p = buf + l.addr(r, f);
+  const int32_t dt = l.shape.dtype[f];
+  if (dt == ADHA_F32) std::memcpy(p, &a.f, 4);
+  else if (dt == ADHA_F64) std::memcpy(p, &a.d, 8);
+  else std::memcpy(p, &a.u, 4);
+}
+
+}  // namespace
+
+uint32_t host_threads(const Ctx *ctx) {
+  if (ctx && ctx->host_threads) return ctx->host_threads;
+  const uint32_t hw = std::thread::hardware_concurrency();
+  return std::max(1u, std::min(hw ? hw : 1u, 64u));
+}
+
+adha_status host_section_run(uint32_t threads, const SectionDesc &sec, const LayoutDesc &l, uint8_t *buf,
+                             const int32_t *idx, void *table, uint64_t *bad_out) {
+  const int64_t n = l.shape.n;
+  const size_t nr = sec.rd.size(), nw = sec.wr.size();
+  std::vector<uint64_t> bad(std::max<uint32_t>(1, threads), 0);
+  if (sec.op == ADHA_OP_REDUCE) {
+    const uint32_t cols = (uint32_t)nr + 1, cells = sec.reduce_cells();
+    const uint32_t t = std::max<uint32_t>(1, threads);
+    // per thread: double sums for floating-point columns, uint64 for the rest
+    std::vector<std::vector<double>> fs(t, std::vector<double>(cells, 0.0));
+    std::vector<std::vector<uint64_t>> us(t, std::vector<uint64_t>(cells, 0));
+    parallel_ranges(n, t, [&](uint32_t k, int64_t b, int64_t e) {
+      for (int64_t r = b; r < e; ++r) {
+        int64_t key = 0;
+        if (sec.key >= 0) key = (int32_t)(uint32_t)read_term(buf, l, r, sec.key);
+        if (key < 0 || key >= (int64_t)sec.n_keys) {
+          ++bad[k];
+          continue;
+        }
+        const size_t row = (size_t)key * cols;
+        for (size_t q = 0; q < nr; ++q) {
+          const int f = sec.rd[q];
+          const uint64_t v = read_term(buf, l, r, f);
+          if (l.shape.dtype[f] == ADHA_I32) us[k][row + q] += (uint64_t)(int64_t)(int32_t)(uint32_t)v;
+          else fs[k][row + q] += as_f64(l.shape.dtype[f], v);
+        }
+        us[k][row + nr] += 1;
+      }
+    });
+    uint64_t *out = (uint64_t *)table;
+    for (uint32_t c = 0; c < cells; ++c) {
+      const uint32_t q = c % cols;
+      const bool fp = q < nr && l.shape.dtype[sec.rd[q]] != ADHA_I32;
+      if (fp) {
+        double s = 0.0;
+        for (uint32_t k = 0; k < t; ++k) s += fs[k][c];
+        std::memcpy(&out[c], &s, 8);
+      } else {
+        uint64_t s = 0;
+        for (uint32_t k = 0; k < t; ++k) s += us[k][c];
+        out[c] = s;
+      }
+    }
+  } else {
+    const int32_t w0 = nw > 0 ? l.shape.dtype[sec.wr[0]] : ADHA_F32;
+    const int32_t w1 = nw > 1 ? l.shape.dtype[sec.wr[1]] : ADHA_F32;
+    parallel_ranges(n, threads, [&](uint32_t k, int64_t b, int64_t e) {
+      std::vector<uint64_t> tv(nr);
+      for (int64_t r = b; r < e; ++r) {
+        HAcc acc[2];
+        if (sec.degree == 0) {
+          for (size_t q = 0; q < nr; ++q) tv[q] = read_term(buf, l, r, sec.rd[q]);
+          if (sec.op == ADHA_OP_GEN || sec.op == ADHA_OP_SUM) {
+            for (size_t q = 0; q < nr; ++q) {
+              const int32_t dt = l.shape.dtype[sec.rd[q]];
+              fold_term(acc[0], 0, w0, dt, tv[q]);
+              if (nw > 1) fold_term(acc[1], 1, w1, dt, tv[q]);
+            }
+          } else {
+            const int32_t d0 = l.shape.dtype[sec.rd[0]], d1 = l.shape.dtype[sec.rd[1]];
+            if (w0 == ADHA_F32) {
+              const float x = as_f32(d0, tv[0]), y = as_f32(d1, tv[1]);
+              if (sec.op == ADHA_OP_MULADD3) {
+                const float m = x * y;
+                acc[0].f = m + as_f32(l.shape.dtype[sec.rd[2]], tv[2]);
+              } else {
+                acc[0].f = x - y;
+              }
+            } else {
+              const double x = as_f64(d0, tv[0]), y = as_f64(d1, tv[1]);
+              if (sec.op == ADHA_OP_MULADD3) {
+                const double m = x * y;
+                acc[0].d = m + as_f64(l.shape.dtype[sec.rd[2]], tv[2]);
+              } else {
+                acc[0].d = x - y;
+              }
+            }
+          }
+        } else {
+          const int32_t *row = idx + (uint64_t)r * sec.degree;
+          for (uint32_t j = 0; j < sec.degree; ++j) {
+            const int64_t nb = row[j];
+            if (nb < 0 || nb >= n) {
+              ++bad[k];
+              continue;
+            }
+            for (size_t q = 0; q < nr; ++q) {
+              const int f = sec.rd[q];
+              const uint64_t t = read_term(buf, l, nb, f);
+              fold_term(acc[0], 0, w0, l.shape.dtype[f], t);
+              if (nw > 1) fold_term(acc[1], 1, w1, l.shape.dtype[f], t);
+            }
+          }
+        }
+        write_acc(buf, l, r, sec.wr[0], acc[0]);
+        if (nw > 1) write_acc(buf, l, r, sec.wr[1], acc[1]);
+      }
+    });
+  }
+  if (bad_out) {
+    uint64_t s = 0;
+    for (uint64_t b : bad) s += b;
+    *bad_out = s;
+  }
+  return ADHA_OK;
+}
+
+adha_status host_remap(uint32_t threads, const LayoutDesc &a, const uint8_t *src, const LayoutDesc &b,
+                       uint8_t *dst) {
+  const int64_t n = a.shape.n;
+  const int F = a.shape.nfields();
+  // padding is zero: clear the destination, then place every element
+  parallel_ranges((int64_t)b.nbytes, threads, [&](uint32_t, int64_t s, int64_t e) {
+    std::memset(dst + s, 0, (size_t)(e - s));
+  });
+  parallel_ranges(n, threads, [&](uint32_t, int64_t s, int64_t e) {
+    for (int64_t r = s; r < e; ++r)
+      for (int f = 0; f < F; ++f) std::memcpy(dst + b.addr(r, f), src + a.addr(r, f), a.shape.ebytes[f]);
+  });
+  return ADHA_OK;
+}
+
+}  // namespace adha
+
+using namespace adha;
+
+extern "C" {
+
+adha_status adha_host_section_run(const adha_section *sec, const adha_layout *l, void *buf, uint64_t buf_cap,
+                                  const int32_t *idx, uint64_t idx_count, void *table, uint64_t table_cap,
+                                  uint32_t threads, uint64_t *bad) {
+  if (!sec || !l) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (!sec->d.shape.same(l->d.shape)) return fail(ADHA_ERR_INVALID, "section and layout describe different structs");
+  const int64_t n = l->d.shape.n;
+  if (n > 0 && (!buf || buf_cap < l->d.nbytes))
+    return fail(ADHA_ERR_INVALID, "host buffer is NULL or holds %llu bytes, the layout needs %llu",
+                (unsigned long long)buf_cap, (unsigned long long)l->d.nbytes);
+  if (sec->d.degree > 0 && n > 0 && (!idx || idx_count < (uint64_t)n * sec->d.degree))
+    return fail(ADHA_ERR_INVALID, "gather section needs a host index array of N*d entries");
+  if (sec->d.op == ADHA_OP_REDUCE && (!table || table_cap < (uint64_t)sec->d.reduce_cells() * 8))
+    return fail(ADHA_ERR_INVALID, "reduction needs a host table of %u cells", sec->d.reduce_cells());
+  if (threads == 0) threads = host_threads(nullptr);
+  uint64_t nbad = 0;
+  ADHA_TRY(host_section_run(threads, sec->d, l->d, (uint8_t *)buf, idx, table, &nbad));
+  if (bad) *bad = nbad;
+  return ADHA_OK;
+}
+
+adha_status adha_host_remap(const adha_layout *src_l, const void *src, uint64_t src_cap, const adha_layout *dst_l,
+                            void *dst, uint64_t dst_cap, uint32_t threads) {
+  if (!src_l || !dst_l) return fail(ADHA_ERR_INVALID, "layout is NULL");
+  if (!src_l->d.shape.same(dst_l->d.shape))
+    return fail(ADHA_ERR_INVALID, "source and destination layouts describe different structs");
+  if (src_l->d.nbytes && (!src || src_cap < src_l->d.nbytes)) return fail(ADHA_ERR_INVALID, "src too small");
+  if (dst_l->d.nbytes && (!dst || dst_cap < dst_l->d.nbytes)) return fail(ADHA_ERR_INVALID, "dst too small");
+  const uintptr_t x = (uintptr_t)src, y = (uintptr_t)dst;
+  if (src_l->d.nbytes && dst_l->d.nbytes && x < y + dst_l->d.nbytes && y < x + src_l->d.nbytes)
+    return fail(ADHA_ERR_INVALID, "src and dst overlap (remaps are out of place)");
+  if (threads == 0) threads = host_threads(nullptr);
+  return host_remap(threads, src_l->d, (const uint8_t *)src, dst_l->d, (uint8_t *)dst);
+}
+
+}  // extern "C"

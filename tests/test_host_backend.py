@@ -1,0 +1,148 @@
+"""The library's host backend against the oracle (CPU only): sections, gathers,
+reductions and remaps on host memory, bit for bit (F64 reduction sums within
+their bound), for several layouts and thread counts."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import reduce as OR
+from oracle.layout import Layout as OLayout, aos as oaos, soa as osoa, from_partition
+from paper_1407_4859_amd import adha as A
+from paper_1407_4859_amd import synth
+
+
+def _mirror(st, O):
+    gof = [O.group_of[f] for f in range(len(O.elem_bytes))]
+    return A.Layout.create(st, gof, [t for _, t in O.groups])
+
+
+def _layouts(n, eb):
+    F = len(eb)
+    return (oaos(n, eb), osoa(n, eb), OLayout(n, eb, [0] * F, [64]),
+            from_partition(n, eb, [list(range(0, F, 3)), list(range(1, F, 3))], 1),
+            from_partition(n, eb, [list(range(0, F, 2))], 8))
+
+
+@pytest.mark.parametrize("n", [1, 257, 5000])
+def test_config3_sections_on_the_host(n):
+    spec = synth.config3_struct(n)
+    cols = synth.record_matrix(3, n, spec.dtypes, spec.elem_bytes)
+    idx = synth.uniform_index(3, 999, n * 16, n)
+    st = A.Struct.from_spec(spec)
+    secs = synth.random_program(3, spec.n_fields)
+    for O in _layouts(n, spec.elem_bytes):
+        L = _mirror(st, O)
+        want = oracle.pack(O, cols)
+        got = want.copy()
+        for s in secs:
+            bad_o = oracle.section(O, spec.dtypes, s.op, s.read, s.write, s.degree, idx if s.degree else None, want)
+            bad = A.host_section_run(A.Section.from_spec(st, s), L, got, idx if s.degree else None, threads=3)
+            assert bad == bad_o == 0
+        assert np.array_equal(got, want), O
+
+
+def test_config1_ops_and_bad_indices():
+    n = 4099
+    spec = synth.config1_struct(n)
+    cols = synth.record_matrix(1, n, spec.dtypes, spec.elem_bytes)
+    st = A.Struct.from_spec(spec)
+    for O in (oaos(n, spec.elem_bytes), osoa(n, spec.elem_bytes)):
+        L = _mirror(st, O)
+        want = oracle.pack(O, cols)
+        got = want.copy()
+        for s in synth.config1_sections():
+            oracle.section(O, spec.dtypes, s.op, s.read, s.write, 0, None, want)
+            A.host_section_run(A.Section.from_spec(st, s), L, got)
+        assert np.array_equal(got, want)
+    # gather indices outside [0, N) are skipped and counted, as in the oracle
+    idx = synth.uniform_index(1, 5, n * 4, n)
+    idx[[0, 7, 4000]] = [-1, n, 1 << 30]
+    O = osoa(n, spec.elem_bytes)
+    want = oracle.pack(O, cols)
+    got = want.copy()
+    bo = oracle.section(O, spec.dtypes, synth.OP_GEN, [0, 1], [5], 4, idx, want)
+    bh = A.host_section_run(A.Section(st, A.OP_GEN, [0, 1], [5], 4), _mirror(st, O), got, idx)
+    assert bo == bh == 3 and np.array_equal(got, want)
+
+
+def test_threads_do_not_change_results():
+    n = 20000
+    spec = synth.config3_struct(n)
+    cols = synth.record_matrix(4, n, spec.dtypes, spec.elem_bytes)
+    idx = synth.uniform_index(4, 999, n * 16, n)
+    st = A.Struct.from_spec(spec)
+    O = oaos(n, spec.elem_bytes)
+    L = _mirror(st, O)
+    outs = []
+    for t in (1, 2, 7, 16):
+        b = oracle.pack(O, cols)
+        for s in synth.random_program(4, spec.n_fields):
+            A.host_section_run(A.Section.from_spec(st, s), L, b, idx if s.degree else None, threads=t)
+        outs.append(b)
+    assert all(np.array_equal(o, outs[0]) for o in outs)
+
+
+def test_reductions_on_the_host():
+    n = 30000
+    dtypes = [synth.F32] * 4 + [synth.I32, synth.I32, synth.F64]
+    eb = [4] * 6 + [8]
+    cols = synth.record_matrix(6, n, dtypes, eb)
+    keys = synth.uniform_index(6, 77, n, 7).astype(np.int32)
+    keys[[5, 17]] = [-3, 7]
+    cols[4] = keys.view(np.uint8).reshape(n, 4)
+    spec = synth.StructSpec(n, dtypes, eb)
+    st = A.Struct.from_spec(spec)
+    read = [0, 2, 3, 5, 6]
+    for O in _layouts(n, eb):
+        buf = oracle.pack(O, cols)
+        table, bad = OR.reduce(O, dtypes, read, 4, 7, buf)
+        fake_dev = _FakeDev(1 << 20, 7 * 6 * 8)
+        sec = A.Section.reduce(st, read, 4, 7, fake_dev)
+        got = np.zeros(7 * 6, np.uint64)
+        hb = A.host_section_run(sec, _mirror(st, O), buf, table=got, threads=5)
+        assert hb == bad == 2
+        want = OR.table_cells(table, dtypes, read)
+        for k in range(7):
+            for j in range(6):
+                c = k * 6 + j
+                if j == 4:             # the F64 column: within (m-1) 2^-53 sum|x|
+                    g = float(got[c:c + 1].view(np.float64)[0])
+                    v = np.abs(OR.field_values(O, buf, synth.F64, 6)[
+                        OR.field_values(O, buf, synth.I32, 4) == k])
+                    assert abs(g - table[k][j]) <= max(len(v) - 1, 0) * 2.0 ** -53 * float(v.sum()) * (1 + 1e-12)
+                else:
+                    assert got[c] == want[c], (k, j)
+
+
+def test_host_remaps_match_oracle():
+    n = 3001
+    spec = synth.config3_struct(n)
+    cols = synth.record_matrix(8, n, spec.dtypes, spec.elem_bytes)
+    st = A.Struct.from_spec(spec)
+    lays = _layouts(n, spec.elem_bytes)
+    for Oa in lays:
+        src = oracle.pack(Oa, cols)
+        for Ob in lays:
+            want = oracle.remap(Oa, src, Ob)
+            got = np.full(Ob.nbytes, 0xA5, np.uint8)
+            A.host_remap(_mirror(st, Oa), src, _mirror(st, Ob), got, threads=4)
+            assert np.array_equal(got, want)
+    with pytest.raises(A.AdhaError):
+        b = np.zeros(lays[0].nbytes, np.uint8)
+        A.host_remap(_mirror(st, lays[0]), b, _mirror(st, lays[0]), b)      # in place
+
+
+class _FakeDev:
+    """A device address stand-in at creation time (nothing reads it here)."""
+
+    def __init__(self, addr, nbytes):
+        self.addr, self.nbytes = addr, nbytes
+
+    def data_ptr(self):
+        return self.addr
+
+    def numel(self):
+        return self.nbytes
+
+    def element_size(self):
+        return 1
