@@ -128,7 +128,9 @@ typedef enum {
   /* reductions: LDS bytes a workgroup may spend on copies of the table
    * (1024..65536, default 12288); more copies mean fewer lanes adding to
    * one LDS cell at once */
-  ADHA_OPT_REDUCE_LDS_BYTES = 3
+  ADHA_OPT_REDUCE_LDS_BYTES = 3,
+  /* host backend threads (0: one per core, at most 64; up to 256) */
+  ADHA_OPT_HOST_THREADS = 4
 } adha_option;
 adha_status adha_ctx_set_option(adha_ctx *ctx, adha_option opt, int64_t value);
 
@@ -344,7 +346,13 @@ typedef enum {
   ADHA_COST_LEARNED = 2   /* the trained cost model; falls back to MEASURED */
 } adha_cost_source;
 typedef enum { ADHA_CAT_AOS_SOA = 0, ADHA_CAT_FULL = 1 } adha_catalogue;
-typedef enum { ADHA_INIT_FREE = 0, ADHA_INIT_AOS = 1 } adha_init;
+/* FREE: data starts in the first chosen layout (and device) at no cost;
+ * AOS: in AoS on the GPU; HOST_AOS: in AoS on the host (plans over both
+ * devices only). */
+typedef enum { ADHA_INIT_FREE = 0, ADHA_INIT_AOS = 1, ADHA_INIT_HOST_AOS = 2 } adha_init;
+/* Where sections may run (section 2: the tuning profile holds CPU and GPU
+ * times and the path picks a device per section). */
+typedef enum { ADHA_DEVICES_GPU = 0, ADHA_DEVICES_GPU_HOST = 1 } adha_devices;
 
 typedef struct {
   adha_cost_source cost;
@@ -352,6 +360,7 @@ typedef struct {
   uint32_t cap_bytes; /* ODS structure capacity in bytes */
   adha_init init;     /* FREE: data starts in the first chosen layout at no cost */
   uint32_t reps;      /* measured costs: median of this many timed runs */
+  adha_devices devices; /* GPU only, or GPU and host */
 } adha_plan_opts;
 
 adha_status adha_plan_opts_default(adha_plan_opts *o);
@@ -369,6 +378,22 @@ adha_status adha_plan_create(adha_ctx *ctx, const adha_program *p, const adha_pl
 /* A plan that keeps one layout for every section (the all-AoS / all-SoA
  * baselines). */
 adha_status adha_plan_uniform(const adha_program *p, const adha_layout *l, adha_plan **out);
+/* A plan given section by section: layouts[k] and devices[k] (0 the GPU,
+ * 1 the host; NULL = all on the GPU).  Its cost tables are zero. */
+adha_status adha_plan_explicit(const adha_program *p, const adha_layout *const *layouts, const int32_t *devices,
+                               adha_plan **out);
+/* Device of section s's choice: 0 the GPU, 1 the host. */
+adha_status adha_plan_device(const adha_plan *pl, uint32_t s, int32_t *device);
+/* The shortest-path graph: M nodes (C for GPU plans; 2C over both devices,
+ * node m = (device m / C, candidate m % C)); T[k*M] section costs and
+ * R[M*M] move costs in microseconds.  Over both devices a move between
+ * devices costs one transfer of the struct each way (measured with pinned
+ * host memory, or analytic at 50 GB/s) plus, when the layout changes, the
+ * GPU remap (done on the GPU side); a host remap costs the measured host
+ * remap.  Host section costs are measured with the context's host threads
+ * (median of reps) or analytic (bytes at 40 GB/s plus 30 us). */
+adha_status adha_plan_nodes(const adha_plan *pl, uint32_t *M);
+adha_status adha_plan_node_tables(const adha_plan *pl, double *T, double *R);
 adha_status adha_plan_destroy(adha_plan *pl);
 adha_status adha_plan_n_candidates(const adha_plan *pl, uint32_t *out);
 /* Candidate c's layout; the plan owns it. */
@@ -390,6 +415,23 @@ adha_status adha_run(adha_ctx *ctx, const adha_plan *pl, const adha_layout *in_l
                      void *buf_a, void *buf_b, uint64_t buf_cap, const int32_t *idx,
                      uint64_t idx_count, void *stream, const adha_layout **out_layout,
                      int32_t *out_in_b);
+/* Runs a plan whose sections may be mapped to the host (the same as
+ * adha_run for GPU plans, which reject host sections).  The data starts in
+ * dev_a (in_device 0) or host_a (in_device 1), laid out by in_layout.  A
+ * GPU section runs on `stream` in the device buffers, a host section with
+ * the context's host threads in the host buffers (after the stream has
+ * drained).  A move between devices copies the struct over; when it also
+ * changes the layout the remap happens on the GPU side.  Host buffers
+ * should be pinned for full copy speed.  Gathers need idx_dev (device,
+ * 256-byte aligned) and/or idx_host (host) as their sections' devices
+ * require, each holding idx_count >= N*d entries.  A reduction on the host
+ * copies its table to the device array given at creation.  The call
+ * returns once host work is done; GPU work may still be in flight.
+ * *out_device (0/1) and *out_in_b tell where the data ends. */
+adha_status adha_run_hetero(adha_ctx *ctx, const adha_plan *pl, const adha_layout *in_layout, int32_t in_device,
+                            void *dev_a, void *dev_b, void *host_a, void *host_b, uint64_t buf_cap,
+                            const int32_t *idx_dev, const int32_t *idx_host, uint64_t idx_count, void *stream,
+                            const adha_layout **out_layout, int32_t *out_device, int32_t *out_in_b);
 
 /* ------------------------------------------------------------ cost model */
 #define ADHA_N_FEATURES 16

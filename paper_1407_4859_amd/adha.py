@@ -25,9 +25,10 @@ OP_GEN, OP_MULADD3, OP_SUB2, OP_SUM, OP_REDUCE = 0, 1, 2, 3, 4
 MAX_REDUCE_CELLS = 4096
 COST_MEASURED, COST_ANALYTIC, COST_LEARNED = 0, 1, 2
 CAT_AOS_SOA, CAT_FULL = 0, 1
-INIT_FREE, INIT_AOS = 0, 1
+INIT_FREE, INIT_AOS, INIT_HOST_AOS = 0, 1, 2
 BATCH_GRAPH, BATCH_SEPARATE = 1, 2
-OPT_SPAN_GATHER, OPT_REDUCE_WG_PER_CU, OPT_REDUCE_LDS_BYTES = 1, 2, 3
+OPT_SPAN_GATHER, OPT_REDUCE_WG_PER_CU, OPT_REDUCE_LDS_BYTES, OPT_HOST_THREADS = 1, 2, 3, 4
+DEVICES_GPU, DEVICES_GPU_HOST = 0, 1
 N_FEATURES = 16
 MLP_PARAMS = 64 * 16 + 64 + 64 * 64 + 64 + 64 * 64 + 64 + 64 + 1
 
@@ -56,7 +57,7 @@ class RemapInfo(ctypes.Structure):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("cost", ctypes.c_int), ("catalogue", ctypes.c_int), ("cap_bytes", ctypes.c_uint32),
-                ("init", ctypes.c_int), ("reps", ctypes.c_uint32)]
+                ("init", ctypes.c_int), ("reps", ctypes.c_uint32), ("devices", ctypes.c_int)]
 
 
 class TrainOpts(ctypes.Structure):
@@ -131,6 +132,12 @@ _SIGS = {
     "adha_plan_tables": ([P, P, P], I32T),
     "adha_plan_time": ([P, ctypes.POINTER(DBL)], I32T),
     "adha_run": ([P, P, P, P, P, U64, P, U64, P, PP, ctypes.POINTER(I32T)], I32T),
+    "adha_run_hetero": ([P, P, P, I32T, P, P, P, P, U64, P, P, U64, P, PP, ctypes.POINTER(I32T),
+                         ctypes.POINTER(I32T)], I32T),
+    "adha_plan_explicit": ([P, P, P, PP], I32T),
+    "adha_plan_device": ([P, U32, ctypes.POINTER(I32T)], I32T),
+    "adha_plan_nodes": ([P, ctypes.POINTER(U32)], I32T),
+    "adha_plan_node_tables": ([P, P, P], I32T),
     "adha_features": ([P, P, P], I32T),
     "adha_mlp_forward": ([P, P, P, U32, P, P], I32T),
     "adha_mlp_backward": ([P, P, P, P, U32, P, P, P], I32T),
@@ -414,6 +421,33 @@ class Plan:
         check(lib().adha_plan_uniform(prog.h, layout.h, ctypes.byref(h)))
         return cls(h, len(prog.sections))
 
+    @classmethod
+    def explicit(cls, prog: Program, layouts, devices=None):
+        """A plan given section by section (devices: 0 the GPU, 1 the host)."""
+        h = ctypes.c_void_p()
+        arr = (ctypes.c_void_p * len(layouts))(*[l.h.value for l in layouts])
+        dv = _i32(devices) if devices is not None else None
+        check(lib().adha_plan_explicit(prog.h, arr, dv, ctypes.byref(h)))
+        return cls(h, len(prog.sections))
+
+    def devices(self):
+        out = []
+        for s in range(self.k):
+            v = ctypes.c_int32()
+            check(lib().adha_plan_device(self.h, s, ctypes.byref(v)))
+            out.append(v.value)
+        return out
+
+    def node_tables(self):
+        M = ctypes.c_uint32()
+        check(lib().adha_plan_nodes(self.h, ctypes.byref(M)))
+        m = M.value
+        T = (ctypes.c_double * (self.k * m))()
+        R = (ctypes.c_double * (m * m))()
+        check(lib().adha_plan_node_tables(self.h, T, R))
+        return ([[T[s * m + c] for c in range(m)] for s in range(self.k)],
+                [[R[a * m + b] for b in range(m)] for a in range(m)])
+
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
             _lib.adha_plan_destroy(self.h)
@@ -579,6 +613,29 @@ def run(ctx: Ctx, plan: Plan, in_layout: Layout, buf_a, buf_b, idx=None, stream=
     check(lib().adha_run(ctx.h, plan.h, in_layout.h, ap, bp, cap, ip, icap // 4, stream_ptr(stream),
                          ctypes.byref(out_l), ctypes.byref(in_b)))
     return out_l.value, bool(in_b.value)
+
+
+def run_hetero(ctx: Ctx, plan: Plan, in_layout: Layout, in_device: int, dev_a, dev_b, host_a, host_b,
+               idx_dev=None, idx_host=None, stream=None):
+    """Runs a plan over both devices; returns (final layout handle value,
+    final device 0/1, True if the data ends in buffer b)."""
+    da, dac = _dev(dev_a)
+    db, dbc = _dev(dev_b)
+    ha, hac = _host(host_a)
+    hb, hbc = _host(host_b)
+    caps = [c for p, c in ((da, dac), (db, dbc), (ha, hac), (hb, hbc)) if p is not None]
+    cap = min(caps) if caps else 0
+    ip, ic = _dev(idx_dev)
+    hp, hc = _host(idx_host)
+    count = max(ic, hc) // 4
+    if ip is not None and hp is not None:
+        count = min(ic, hc) // 4
+    out_l = ctypes.c_void_p()
+    out_d = ctypes.c_int32()
+    in_b = ctypes.c_int32()
+    check(lib().adha_run_hetero(ctx.h, plan.h, in_layout.h, in_device, da, db, ha, hb, cap, ip, hp, count,
+                                stream_ptr(stream), ctypes.byref(out_l), ctypes.byref(out_d), ctypes.byref(in_b)))
+    return out_l.value, out_d.value, bool(in_b.value)
 
 
 def mlp_forward(ctx: Ctx, params, x, y, stream=None):

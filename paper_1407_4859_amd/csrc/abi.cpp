@@ -183,6 +183,10 @@ adha_status adha_ctx_check(adha_ctx *ctx, void *stream) {
   ADHA_HIP(hipStreamSynchronize((hipStream_t)stream));
   uint32_t flag = 0;
   ADHA_HIP(hipMemcpy(&flag, ctx->c.err_flag, 4, hipMemcpyDeviceToHost));
+  if (ctx->c.host_bad) {
+    flag = 1;
+    ctx->c.host_bad = 0;
+  }
   if (flag) {
     ADHA_HIP(hipMemset(ctx->c.err_flag, 0, 4));
     return fail(ADHA_ERR_INVALID,
@@ -208,6 +212,10 @@ adha_status adha_ctx_set_option(adha_ctx *ctx, adha_option opt, int64_t value) {
     case ADHA_OPT_REDUCE_WG_PER_CU:
       if (value < 1 || value > 32) return fail(ADHA_ERR_INVALID, "workgroups per CU %lld not in [1, 32]", (long long)value);
       ctx->c.reduce_wg_per_cu = (uint32_t)value;
+      return ADHA_OK;
+    case ADHA_OPT_HOST_THREADS:
+      if (value < 0 || value > 256) return fail(ADHA_ERR_INVALID, "host threads %lld not in [0, 256]", (long long)value);
+      ctx->c.host_threads = (uint32_t)value;
       return ADHA_OK;
     case ADHA_OPT_REDUCE_LDS_BYTES:
       if (value < 1024 || value > 65536) return fail(ADHA_ERR_INVALID, "LDS bytes %lld not in [1024, 65536]", (long long)value);

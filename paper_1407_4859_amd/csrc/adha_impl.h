@@ -224,6 +224,7 @@ struct Ctx {
   uint32_t reduce_wg_per_cu = 8;     // reductions: first-pass workgroups per CU
   uint32_t reduce_lds_bytes = 12288; // reductions: LDS for table copies
   uint32_t host_threads = 0;         // host backend threads (0: one per core, at most 64)
+  uint64_t host_bad = 0;             // out-of-range indices / keys met by host sections
   ~Ctx();
 };
 

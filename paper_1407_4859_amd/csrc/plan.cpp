@@ -22,8 +22,15 @@ struct adha_plan {
   adha::Shape shape;
   std::vector<adha::SectionDesc> secs;
   std::vector<adha_layout *> cands;
-  std::vector<uint32_t> choice;
-  std::vector<double> T, R;  // k*C and C*C, microseconds
+  std::vector<uint32_t> choice;  // per section: candidate layout
+  std::vector<int32_t> dev;      // per section: 0 the GPU, 1 the host
+  std::vector<double> T, R;  // k*C and C*C, microseconds (the GPU)
+  // plans over both devices: host section costs (k*C), the host remap, the
+  // transfers each way; a move between devices that changes the layout
+  // remaps on the GPU side
+  bool hetero = false;
+  std::vector<double> TH;
+  double rem_h = 0.0, xfer_dh = 0.0, xfer_hd = 0.0;
   double cost = 0.0, seconds = 0.0;
   ~adha_plan() {
     for (auto *l : cands) delete l;
@@ -313,6 +320,125 @@ static adha_status measured_costs(Ctx *ctx, const Shape &sh, const std::vector<S
   return ADHA_OK;
 }
 
+// The GPU's whole-struct remap figure of a plan: every pair of different
+// layouts costs the same (zero when the plan has one candidate).
+static double device_remap_figure(const adha_plan *pl) {
+  const size_t C = pl->cands.size();
+  return C > 1 ? pl->R[0 * C + 1] : 0.0;
+}
+
+// The node graph of a plan over both devices: node m is (device m / C,
+// layout m % C).  T is k*M, R is M*M.
+static void node_tables(const adha_plan *pl, std::vector<double> *T, std::vector<double> *R) {
+  const size_t k = pl->secs.size(), C = pl->cands.size(), M = pl->hetero ? 2 * C : C;
+  T->assign(k * M, 0.0);
+  R->assign(M * M, 0.0);
+  for (size_t s = 0; s < k; ++s)
+    for (size_t m = 0; m < M; ++m) (*T)[s * M + m] = m < C ? pl->T[s * C + m] : pl->TH[s * C + m - C];
+  const double rd = device_remap_figure(pl);
+  for (size_t x = 0; x < M; ++x)
+    for (size_t y = 0; y < M; ++y) {
+      const size_t a = x % C, b = y % C;
+      const bool gx = x < C, gy = y < C;
+      double r;
+      if (gx && gy) r = pl->R[a * C + b];
+      else if (!gx && !gy) r = a == b ? 0.0 : pl->rem_h;
+      else r = (gx ? pl->xfer_dh : pl->xfer_hd) + (a == b ? 0.0 : rd);
+      (*R)[x * M + y] = x == y ? 0.0 : r;
+    }
+}
+
+// Host costs analytic: the bytes model over a host bandwidth, plus thread
+// start-up; transfers over PCIe.
+static const double kHostBytesPerUs = 4.0e4;  // 40 GB/s over the host cores
+static const double kHostStartUs = 30.0;
+static const double kPcieBytesPerUs = 5.0e4;  // 50 GB/s each way
+static const double kCopyStartUs = 10.0;
+
+static void analytic_host_costs(adha_plan *pl) {
+  const size_t k = pl->secs.size(), C = pl->cands.size();
+  pl->TH.assign(k * C, 0.0);
+  for (size_t s = 0; s < k; ++s)
+    for (size_t c = 0; c < C; ++c)
+      pl->TH[s * C + c] = kHostStartUs + (double)pl->shape.n * analytic_bytes_per_record(pl->secs[s], pl->cands[c]->d) /
+                                             kHostBytesPerUs;
+  const double bytes = (double)pl->shape.n * pl->shape.record_bytes();
+  pl->rem_h = kHostStartUs + 2.0 * bytes / kHostBytesPerUs;
+  pl->xfer_dh = pl->xfer_hd = kCopyStartUs + bytes / kPcieBytesPerUs;
+}
+
+// Host costs measured: each (section, candidate) on host scratch with the
+// context's host threads (median of reps after one warm-up), one host
+// remap, and a pinned transfer each way of the whole struct.
+static adha_status measured_host_costs(Ctx *ctx, adha_plan *pl, uint32_t reps, const int32_t *idx_dev,
+                                       uint64_t idx_count, hipStream_t stream) {
+  const size_t k = pl->secs.size(), C = pl->cands.size();
+  const Shape &sh = pl->shape;
+  const uint32_t threads = host_threads(ctx);
+  uint64_t maxb = 256;
+  uint32_t maxd = 0;
+  for (auto *l : pl->cands) maxb = std::max(maxb, l->d.nbytes);
+  for (auto &s : pl->secs) maxd = std::max(maxd, s.degree);
+  std::vector<uint8_t> a(maxb, 0), b(maxb, 0);
+  std::vector<int32_t> idx;
+  if (maxd > 0 && sh.n > 0) {
+    idx.resize((size_t)sh.n * maxd);
+    if (idx_dev && idx_count >= (uint64_t)sh.n * maxd) {
+      ADHA_HIP(hipMemcpy(idx.data(), idx_dev, idx.size() * 4, hipMemcpyDeviceToHost));
+    } else {
+      for (size_t i = 0; i < idx.size(); ++i) {  // uniform neighbours (SplitMix64, multiply-shift)
+        uint64_t z = ((0x5eedULL << 32) + i + 1) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        idx[i] = (int32_t)(((z >> 32) * (uint64_t)sh.n) >> 32);
+      }
+    }
+  }
+  std::vector<uint64_t> table(ADHA_MAX_REDUCE_CELLS, 0);
+  auto median_us = [&](auto fn) {
+    fn();
+    std::vector<double> ts;
+    for (uint32_t r = 0; r < std::max<uint32_t>(1, reps); ++r) {
+      auto t0 = std::chrono::steady_clock::now();
+      fn();
+      ts.push_back(std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count());
+    }
+    std::sort(ts.begin(), ts.end());
+    return ts[ts.size() / 2];
+  };
+  pl->TH.assign(k * C, 0.0);
+  for (size_t c = 0; c < C; ++c)
+    for (size_t s = 0; s < k; ++s)
+      pl->TH[s * C + c] = median_us([&] {
+        uint64_t bad = 0;
+        (void)host_section_run(threads, pl->secs[s], pl->cands[c]->d, a.data(), idx.data(), table.data(), &bad);
+      });
+  pl->rem_h = C > 1 ? median_us([&] { (void)host_remap(threads, pl->cands[0]->d, a.data(), pl->cands[1]->d, b.data()); })
+                    : 0.0;
+  // transfers: pinned host staging and device scratch of the struct's size
+  const uint64_t bytes = pl->cands[0]->d.nbytes;
+  void *hp = nullptr, *dp = nullptr;
+  if (bytes) {
+    ADHA_HIP(hipHostMalloc(&hp, bytes, hipHostMallocDefault));
+    if (hipMalloc(&dp, bytes) != hipSuccess) {
+      (void)hipHostFree(hp);
+      return fail(ADHA_ERR_OOM, "device scratch of %llu bytes failed", (unsigned long long)bytes);
+    }
+    pl->xfer_dh = median_us([&] {
+      (void)hipMemcpyAsync(hp, dp, bytes, hipMemcpyDeviceToHost, stream);
+      (void)hipStreamSynchronize(stream);
+    });
+    pl->xfer_hd = median_us([&] {
+      (void)hipMemcpyAsync(dp, hp, bytes, hipMemcpyHostToDevice, stream);
+      (void)hipStreamSynchronize(stream);
+    });
+    (void)hipFree(dp);
+    (void)hipHostFree(hp);
+  }
+  return ADHA_OK;
+}
+
 }  // namespace adha
 
 using namespace adha;
@@ -381,6 +507,7 @@ adha_status adha_plan_opts_default(adha_plan_opts *o) {
   o->cap_bytes = 64;
   o->init = ADHA_INIT_FREE;
   o->reps = 5;
+  o->devices = ADHA_DEVICES_GPU;
   return ADHA_OK;
 }
 
@@ -391,6 +518,11 @@ adha_status adha_plan_create(adha_ctx *ctx, const adha_program *p, const adha_pl
   if (o->cap_bytes == 0) return fail(ADHA_ERR_INVALID, "cap_bytes must be positive");
   if (o->cost < ADHA_COST_MEASURED || o->cost > ADHA_COST_LEARNED) return fail(ADHA_ERR_INVALID, "unknown cost source");
   if (idx && ((uintptr_t)idx & 255u)) return fail(ADHA_ERR_INVALID, "idx is not 256-byte aligned");
+  if (o->devices != ADHA_DEVICES_GPU && o->devices != ADHA_DEVICES_GPU_HOST)
+    return fail(ADHA_ERR_INVALID, "unknown devices option %d", (int)o->devices);
+  if (o->init < ADHA_INIT_FREE || o->init > ADHA_INIT_HOST_AOS) return fail(ADHA_ERR_INVALID, "unknown init option");
+  if (o->init == ADHA_INIT_HOST_AOS && o->devices != ADHA_DEVICES_GPU_HOST)
+    return fail(ADHA_ERR_INVALID, "data starting on the host needs a plan over both devices");
   auto t0 = std::chrono::steady_clock::now();
   std::unique_ptr<adha_plan> pl(new (std::nothrow) adha_plan);
   if (!pl) return fail(ADHA_ERR_OOM, "plan allocation failed");
@@ -447,13 +579,84 @@ adha_status adha_plan_create(adha_ctx *ctx, const adha_program *p, const adha_pl
     ADHA_TRY(measured_costs(&ctx->c, p->shape, p->secs, pl->cands, std::max<uint32_t>(1, o->reps), idx,
                             idx_count, st, &pl->T, &pl->R));
   }
-  std::vector<double> R0(C, 0.0);
+  if (o->devices == ADHA_DEVICES_GPU_HOST) {
+    pl->hetero = true;
+    if (o->cost == ADHA_COST_ANALYTIC) analytic_host_costs(pl.get());
+    else ADHA_TRY(measured_host_costs(&ctx->c, pl.get(), std::max<uint32_t>(1, o->reps), idx, idx_count, st));
+  }
+  std::vector<double> NT, NR;
+  node_tables(pl.get(), &NT, &NR);
+  const size_t M = pl->hetero ? 2 * C : C;
+  std::vector<double> R0(M, 0.0);
   if (o->init == ADHA_INIT_AOS)
-    for (size_t c = 0; c < C; ++c) R0[c] = pl->R[0 * C + c];
-  ADHA_TRY(pdl_solve((uint32_t)k, (uint32_t)C, pl->T.data(), pl->R.data(), R0.data(), &pl->choice, &pl->cost));
+    for (size_t m = 0; m < M; ++m) R0[m] = NR[0 * M + m];
+  if (o->init == ADHA_INIT_HOST_AOS)
+    for (size_t m = 0; m < M; ++m) R0[m] = m == C ? 0.0 : NR[C * M + m];
+  std::vector<uint32_t> nodes;
+  ADHA_TRY(pdl_solve((uint32_t)k, (uint32_t)M, NT.data(), NR.data(), R0.data(), &nodes, &pl->cost));
+  pl->choice.resize(k);
+  pl->dev.resize(k);
+  for (size_t s2 = 0; s2 < k; ++s2) {
+    pl->choice[s2] = nodes[s2] % (uint32_t)C;
+    pl->dev[s2] = nodes[s2] >= C ? 1 : 0;
+  }
   pl->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   *out = pl.release();
   return result;
+}
+
+adha_status adha_plan_explicit(const adha_program *p, const adha_layout *const *layouts, const int32_t *devices,
+                               adha_plan **out) {
+  if (!p || !layouts || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
+  const size_t k = p->secs.size();
+  std::unique_ptr<adha_plan> pl(new (std::nothrow) adha_plan);
+  if (!pl) return fail(ADHA_ERR_OOM, "plan allocation failed");
+  pl->shape = p->shape;
+  pl->secs = p->secs;
+  for (size_t s = 0; s < k; ++s) {
+    if (!layouts[s] || !layouts[s]->d.shape.same(p->shape))
+      return fail(ADHA_ERR_INVALID, "layout %zu is NULL or describes another struct", s);
+    const int32_t d = devices ? devices[s] : 0;
+    if (d != 0 && d != 1) return fail(ADHA_ERR_INVALID, "device %d of section %zu is not 0 (GPU) or 1 (host)", d, s);
+    uint32_t c = 0;
+    while (c < pl->cands.size() && !pl->cands[c]->d.same_map(layouts[s]->d)) ++c;
+    if (c == pl->cands.size()) {
+      adha_layout *l = new_layout(layouts[s]->d);
+      if (!l) return fail(ADHA_ERR_OOM, "layout allocation failed");
+      pl->cands.push_back(l);
+    }
+    pl->choice.push_back(c);
+    pl->dev.push_back(d);
+    pl->hetero |= d == 1;
+  }
+  const size_t C = pl->cands.size();
+  pl->T.assign(k * C, 0.0);
+  pl->R.assign(C * C, 0.0);
+  if (pl->hetero) pl->TH.assign(k * C, 0.0);
+  *out = pl.release();
+  return ADHA_OK;
+}
+
+adha_status adha_plan_device(const adha_plan *pl, uint32_t s, int32_t *device) {
+  if (!pl || !device) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (s >= pl->choice.size()) return fail(ADHA_ERR_INVALID, "section %u out of range", s);
+  *device = pl->dev.empty() ? 0 : pl->dev[s];
+  return ADHA_OK;
+}
+
+adha_status adha_plan_nodes(const adha_plan *pl, uint32_t *M) {
+  if (!pl || !M) return fail(ADHA_ERR_INVALID, "NULL argument");
+  *M = (uint32_t)(pl->hetero ? 2 * pl->cands.size() : pl->cands.size());
+  return ADHA_OK;
+}
+
+adha_status adha_plan_node_tables(const adha_plan *pl, double *T, double *R) {
+  if (!pl) return fail(ADHA_ERR_INVALID, "NULL argument");
+  std::vector<double> NT, NR;
+  node_tables(pl, &NT, &NR);
+  if (T) memcpy(T, NT.data(), NT.size() * sizeof(double));
+  if (R) memcpy(R, NR.data(), NR.size() * sizeof(double));
+  return ADHA_OK;
 }
 
 adha_status adha_plan_uniform(const adha_program *p, const adha_layout *l, adha_plan **out) {
@@ -470,6 +673,7 @@ adha_status adha_plan_uniform(const adha_program *p, const adha_layout *l, adha_
   }
   pl->cands.push_back(c);
   pl->choice.assign(p->secs.size(), 0);
+  pl->dev.assign(p->secs.size(), 0);
   pl->T.assign(p->secs.size(), 0.0);
   pl->R.assign(1, 0.0);
   *out = pl;
@@ -525,6 +729,8 @@ adha_status adha_run(adha_ctx *ctx, const adha_plan *pl, const adha_layout *in_l
                      const adha_layout **out_layout, int32_t *out_in_b) {
   if (!ctx || !pl || !in_layout || !out_layout || !out_in_b) return fail(ADHA_ERR_INVALID, "NULL argument");
   if (!in_layout->d.shape.same(pl->shape)) return fail(ADHA_ERR_INVALID, "input layout describes another struct");
+  for (int32_t d : pl->dev)
+    if (d != 0) return fail(ADHA_ERR_INVALID, "the plan maps sections to the host: run it with adha_run_hetero");
   // validate everything before the first launch
   const adha_layout *cur = in_layout;
   bool in_b = false, needs_b = false;
@@ -569,6 +775,110 @@ adha_status adha_run(adha_ctx *ctx, const adha_plan *pl, const adha_layout *in_l
   }
   *out_layout = cur;
   *out_in_b = in_b ? 1 : 0;
+  return ADHA_OK;
+}
+
+adha_status adha_run_hetero(adha_ctx *ctx, const adha_plan *pl, const adha_layout *in_layout, int32_t in_device,
+                            void *dev_a, void *dev_b, void *host_a, void *host_b, uint64_t buf_cap,
+                            const int32_t *idx_dev, const int32_t *idx_host, uint64_t idx_count, void *stream,
+                            const adha_layout **out_layout, int32_t *out_device, int32_t *out_in_b) {
+  if (!ctx || !pl || !in_layout || !out_layout || !out_device || !out_in_b)
+    return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (!in_layout->d.shape.same(pl->shape)) return fail(ADHA_ERR_INVALID, "input layout describes another struct");
+  if (in_device != 0 && in_device != 1) return fail(ADHA_ERR_INVALID, "in_device must be 0 (GPU) or 1 (host)");
+  // validate everything before the first launch or copy
+  const size_t k = pl->secs.size();
+  uint64_t need = in_layout->d.nbytes;
+  bool uses_host = in_device == 1, uses_dev = in_device == 0, host_gather = false, dev_gather = false;
+  int at = in_device;
+  for (size_t s = 0; s < k; ++s) {
+    const adha_layout *L = pl->cands[pl->choice[s]];
+    need = std::max(need, L->d.nbytes);
+    const int d = pl->dev.empty() ? 0 : pl->dev[s];
+    uses_host |= d == 1;
+    uses_dev |= d == 0 || d != at;  // a move between devices goes through the GPU's buffers
+    at = d;
+    if (pl->secs[s].degree) (d == 1 ? host_gather : dev_gather) = true;
+  }
+  const int64_t n = pl->shape.n;
+  if (need) {
+    if (buf_cap < need)
+      return fail(ADHA_ERR_INVALID, "buffers hold %llu bytes, the plan needs %llu", (unsigned long long)buf_cap,
+                  (unsigned long long)need);
+    if (uses_dev && (!dev_a || !dev_b || ((uintptr_t)dev_a & 255u) || ((uintptr_t)dev_b & 255u)))
+      return fail(ADHA_ERR_INVALID, "device buffers are NULL or misaligned");
+    if (uses_host && (!host_a || !host_b)) return fail(ADHA_ERR_INVALID, "host buffers are NULL");
+    const void *bufs[4] = {dev_a, dev_b, host_a, host_b};
+    for (int x = 0; x < 4; ++x)
+      for (int y = x + 1; y < 4; ++y)
+        if (bufs[x] && bufs[y] && (uintptr_t)bufs[x] < (uintptr_t)bufs[y] + need &&
+            (uintptr_t)bufs[y] < (uintptr_t)bufs[x] + need)
+          return fail(ADHA_ERR_INVALID, "buffers overlap");
+  }
+  if (n > 0) {
+    uint32_t maxd = 0;
+    for (auto &d : pl->secs) maxd = std::max(maxd, d.degree);
+    if (host_gather && (!idx_host || idx_count < (uint64_t)n * maxd))
+      return fail(ADHA_ERR_INVALID, "a gather on the host needs a host index array of N*d entries");
+    if (dev_gather && (!idx_dev || ((uintptr_t)idx_dev & 255u) || idx_count < (uint64_t)n * maxd))
+      return fail(ADHA_ERR_INVALID, "a gather on the GPU needs a device index array of N*d entries");
+    for (const SectionDesc &d : pl->secs)
+      if (d.op == ADHA_OP_REDUCE && need) {
+        const uintptr_t o = (uintptr_t)d.out, no = (uintptr_t)d.reduce_cells() * 8;
+        for (const void *b : {(const void *)dev_a, (const void *)dev_b})
+          if (b && o < (uintptr_t)b + need && (uintptr_t)b < o + no)
+            return fail(ADHA_ERR_INVALID, "a reduction's result table overlaps the data buffers");
+      }
+  }
+  DeviceGuard g(ctx->c.device);
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t threads = host_threads(&ctx->c);
+  void *bufs[2][2] = {{dev_a, dev_b}, {host_a, host_b}};
+  int where = in_device, which = 0;
+  const adha_layout *cur = in_layout;
+  for (size_t s = 0; s < k; ++s) {
+    const adha_layout *L = pl->cands[pl->choice[s]];
+    const int dev = pl->dev.empty() ? 0 : pl->dev[s];
+    const bool remap = !cur->d.same_map(L->d);
+    if (dev == where) {
+      if (remap) {
+        if (where == 0) ADHA_TRY(remap_one(&ctx->c, cur, bufs[0][which], L, bufs[0][!which], st));
+        else ADHA_TRY(host_remap(threads, cur->d, (const uint8_t *)bufs[1][which], L->d, (uint8_t *)bufs[1][!which]));
+        which = !which;
+      }
+    } else if (where == 0) {  // GPU -> host: remap on the GPU first
+      if (remap) {
+        ADHA_TRY(remap_one(&ctx->c, cur, bufs[0][which], L, bufs[0][!which], st));
+        which = !which;
+      }
+      ADHA_HIP(hipMemcpyAsync(bufs[1][which], bufs[0][which], L->d.nbytes, hipMemcpyDeviceToHost, st));
+      ADHA_HIP(hipStreamSynchronize(st));
+    } else {  // host -> GPU: copy, then remap on the GPU
+      ADHA_HIP(hipMemcpyAsync(bufs[0][which], bufs[1][which], cur->d.nbytes, hipMemcpyHostToDevice, st));
+      if (remap) {
+        ADHA_TRY(remap_one(&ctx->c, cur, bufs[0][which], L, bufs[0][!which], st));
+        which = !which;
+      }
+    }
+    where = dev;
+    cur = L;
+    const SectionDesc &sec = pl->secs[s];
+    if (dev == 0) {
+      ADHA_TRY(section_launch(&ctx->c, sec, L->d, bufs[0][which], idx_dev, st));
+    } else {
+      ADHA_HIP(hipStreamSynchronize(st));
+      std::vector<uint64_t> table(sec.op == ADHA_OP_REDUCE ? sec.reduce_cells() : 0);
+      uint64_t bad = 0;
+      ADHA_TRY(host_section_run(threads, sec, L->d, (uint8_t *)bufs[1][which], idx_host, table.data(), &bad));
+      ctx->c.host_bad += bad;
+      if (sec.op == ADHA_OP_REDUCE)
+        ADHA_HIP(hipMemcpy(sec.out, table.data(), table.size() * 8, hipMemcpyHostToDevice));
+    }
+  }
+  if (where == 1) ADHA_HIP(hipStreamSynchronize(st));
+  *out_layout = cur;
+  *out_device = where;
+  *out_in_b = which;
   return ADHA_OK;
 }
 

@@ -253,3 +253,57 @@ def test_reduction_sections_validate_and_plan_like_the_oracle():
     for c, O in enumerate(cat):
         for s, (rd, wr, d) in enumerate(osecs):
             assert T[s][c] == pytest.approx(OC.section_us(rd, wr, d, O), rel=1e-12)
+
+
+def test_analytic_plans_over_both_devices():
+    """Node graph of a plan over the GPU and the host: section costs per
+    device, moves between devices cost a transfer (plus the GPU remap when
+    the layout changes); the chosen path is the shortest over those nodes."""
+    for n in (1 << 8, 1 << 20):
+        spec = synth.config3_struct(n)
+        secs = synth.random_program(5, spec.n_fields)
+        st, ss, prog = _prog(spec, secs)
+        for init in (A.INIT_FREE, A.INIT_HOST_AOS):
+            opts = A.plan_opts(cost=A.COST_ANALYTIC, cap_bytes=64, devices=A.DEVICES_GPU_HOST, init=init)
+            h = ctypes.c_void_p()
+            A.check(A.lib().adha_plan_create(None, prog.h, ctypes.byref(opts), None, 0, None, ctypes.byref(h)))
+            pl = A.Plan(h, len(secs))
+            C = pl.n_candidates
+            T, R = pl.node_tables()
+            assert len(T[0]) == 2 * C and len(R) == 2 * C
+            Tg, Rg = pl.tables()
+            S = spec.record_bytes * n
+            xfer = 10.0 + S / 5.0e4
+            rem_h = 30.0 + 2.0 * S / 4.0e4
+            for s in range(len(secs)):
+                assert T[s][:C] == Tg[s]
+                for c in range(0, C, 7):
+                    want = 30.0 + OC.bytes_per_record(secs[s].read, secs[s].write, secs[s].degree,
+                                                      OP.catalogue([(x.read, x.write, x.degree) for x in secs],
+                                                                   n, spec.elem_bytes, 64)[c]) * n / 4.0e4
+                    assert T[s][C + c] == pytest.approx(want, rel=1e-12)
+            for a in range(0, 2 * C, 5):
+                for b in range(0, 2 * C, 3):
+                    if a == b:
+                        continue
+                    la, lb, ga, gb = a % C, b % C, a < C, b < C
+                    if ga and gb:
+                        want = Rg[la][lb]
+                    elif not ga and not gb:
+                        want = 0.0 if la == lb else rem_h
+                    else:
+                        want = xfer + (0.0 if la == lb else Rg[0][1])
+                    assert R[a][b] == pytest.approx(want, rel=1e-12)
+            R0 = None
+            if init == A.INIT_HOST_AOS:
+                R0 = [0.0 if m == C else R[C][m] for m in range(2 * C)]
+            cost, path = OP.pdl_dp(T, R, R0)
+            assert [m % C for m in path] == pl.choices()
+            assert [int(m >= C) for m in path] == pl.devices()
+            assert pl.cost == pytest.approx(cost, rel=1e-12)
+        if n == 1 << 20:
+            assert pl.devices() == [0] * len(secs)       # a large struct stays on the GPU
+    with pytest.raises(A.AdhaError):
+        opts = A.plan_opts(cost=A.COST_ANALYTIC, init=A.INIT_HOST_AOS)   # host start needs both devices
+        h = ctypes.c_void_p()
+        A.check(A.lib().adha_plan_create(None, prog.h, ctypes.byref(opts), None, 0, None, ctypes.byref(h)))
