@@ -16,6 +16,9 @@ Besides the timed steps the run reports (outside the timed region):
   kmeans        the K-Means-shaped program (2^23 points, a direct loop and a
                 per-cluster reduction of 32 features): planned vs all-AoS and
                 all-SoA, per-section GB/s;
+  hetero        plans over the GPU and the host (plain small program, data
+                starting on the host, N = 2^10 .. 2^20): planned devices and
+                run time vs all-GPU and all-host;
   batched       the 512-array batched remap: one graph launch vs one launch
                 per array;
   learned       (with --learned) the cost model: planned program time with
@@ -72,6 +75,8 @@ def parse():
     ap.add_argument("--skip-program", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-kmeans", action="store_true")
+    ap.add_argument("--skip-hetero", action="store_true")
+    ap.add_argument("--only-hetero", action="store_true", help="the GPU + host planning leg only")
     ap.add_argument("--only-kmeans", action="store_true", help="the K-Means-shaped leg only (for profiling)")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--learned", action="store_true")
@@ -284,6 +289,56 @@ def kmeans_bench(A, synth, torch, timer, log2n=23):
     return res
 
 
+def hetero_bench(A, synth, torch):
+    """Plans over the GPU and the host for the plain small program (8 f32
+    fields, MULADD3, SUB2, SUM) with its data starting in AoS on the host,
+    for N = 2^10 .. 2^20: the planned devices, and the wall time of the
+    planned run against all-GPU (which first copies the data over) and
+    all-host runs."""
+    ctx = A.Ctx(0)
+    rows = []
+    for log2n in (10, 12, 14, 16, 18, 20):
+        n = 1 << log2n
+        spec = synth.config1_struct(n)
+        st = A.Struct.from_spec(spec)
+        prog = A.Program(st, [A.Section.from_spec(st, s) for s in synth.config1_sections()])
+        aos = A.Layout.aos(st)
+        img = synth.pack_aos(synth.record_matrix(1, n, spec.dtypes, spec.elem_bytes), n).reshape(-1)
+        cap = max(aos.nbytes, A.Layout.soa(st).nbytes) + 4096
+        dev = [torch.empty(cap, dtype=torch.uint8, device="cuda") for _ in range(2)]
+        hst = [torch.empty(cap, dtype=torch.uint8).pin_memory() for _ in range(2)]
+        src = torch.from_numpy(img)
+        t0 = time.perf_counter()
+        plan = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_MEASURED, catalogue=A.CAT_FULL, reps=5,
+                                                    devices=A.DEVICES_GPU_HOST, init=A.INIT_HOST_AOS))
+        plan_s = time.perf_counter() - t0
+        gpu = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_MEASURED, catalogue=A.CAT_FULL, reps=5))
+        host_only = A.Plan.explicit(prog, [aos] * 3, [1] * 3)
+
+        def timed(pl):
+            ts = []
+            for r in range(6):
+                hst[0][: img.size].copy_(src)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                A.run_hetero(ctx, pl, aos, 1, dev[0], dev[1], hst[0], hst[1])
+                torch.cuda.synchronize()
+                if r:
+                    ts.append((time.perf_counter() - t) * 1e6)
+            return sorted(ts)[len(ts) // 2]
+
+        row = {"log2n": log2n, "devices": plan.devices(), "choices": plan.choices(),
+               "predicted_us": round(plan.cost, 1), "plan_s": round(plan_s, 2),
+               "planned_us": round(timed(plan), 1), "all_gpu_us": round(timed(gpu), 1),
+               "all_host_us": round(timed(host_only), 1)}
+        row["planned_not_worse"] = row["planned_us"] <= 1.1 * min(row["all_gpu_us"], row["all_host_us"])
+        ctx.check()
+        rows.append(row)
+        log("hetero:", row)
+    return {"workload": "plain small program (8 f32, MULADD3, SUB2, SUM), data starting in AoS on the host, "
+                        "N = 2^10 .. 2^20; host threads: %s" % (os.cpu_count(),), "rows": rows}
+
+
 def batched_bench(A, synth, torch, timer):
     arrs = synth.config4_arrays()
     ctx = A.Ctx(0)
@@ -385,6 +440,9 @@ def main():
     timer = Timer(torch)
     if args.only_learned:
         print(json.dumps({"learned": learned_bench(A, synth, torch, args)}), flush=True)
+        return
+    if args.only_hetero:
+        print(json.dumps({"hetero": hetero_bench(A, synth, torch)}), flush=True)
         return
     if args.only_kmeans:
         print(json.dumps({"kmeans": kmeans_bench(A, synth, torch, timer)}), flush=True)
@@ -488,6 +546,12 @@ def main():
                 line["kmeans"] = kmeans_bench(A, synth, torch, timer)
             except Exception as e:
                 line["kmeans"] = {"error": repr(e)}
+            torch.cuda.empty_cache()
+        if not args.skip_hetero:
+            try:
+                line["hetero"] = hetero_bench(A, synth, torch)
+            except Exception as e:
+                line["hetero"] = {"error": repr(e)}
             torch.cuda.empty_cache()
         if not args.skip_batched:
             try:
