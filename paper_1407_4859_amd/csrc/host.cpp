@@ -11,7 +11,11 @@
 // precision).  Records are split into contiguous ranges over host threads;
 // a reduction adds the threads' tables in thread order.
 #include <algorithm>
+#include <atomic>
+#include <condition_variable>
 #include <cstring>
+#include <functional>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -21,6 +25,84 @@ namespace adha {
 
 namespace {
 
+// A process-wide pool of host threads, started on first use and kept until
+// exit (starting threads per call costs far more than the small sections it
+// would run).  One job at a time: its parts are taken from a counter by the
+// workers and by the calling thread.
+class HostPool {
+ public:
+  static HostPool &get() {
+    static HostPool pool;
+    return pool;
+  }
+  uint32_t size() const { return (uint32_t)workers_.size() + 1; }
+  void run(uint32_t parts, const std::function<void(uint32_t)> &fn) {
+    std::lock_guard<std::mutex> one(run_m_);
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      job_ = &fn;
+      parts_ = parts;
+      next_.store(0);
+      done_.store(0);
+      ++gen_;
+    }
+    cv_.notify_all();
+    work();
+    std::unique_lock<std::mutex> lk(m_);
+    done_cv_.wait(lk, [&] { return done_.load() == parts_; });
+    job_ = nullptr;
+  }
+  ~HostPool() {
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto &t : workers_) t.join();
+  }
+
+ private:
+  HostPool() {
+    const uint32_t hw = std::thread::hardware_concurrency();
+    const uint32_t n = std::max(1u, std::min(hw ? hw : 1u, 256u)) - 1;
+    for (uint32_t k = 0; k < n; ++k) workers_.emplace_back([this] { loop(); });
+  }
+  void work() {
+    for (;;) {
+      const uint32_t p = next_.fetch_add(1);
+      if (p >= parts_) return;
+      (*job_)(p);
+      if (done_.fetch_add(1) + 1 == parts_) {
+        std::lock_guard<std::mutex> lk(m_);
+        done_cv_.notify_all();
+      }
+    }
+  }
+  void loop() {
+    uint64_t seen = 0;
+    for (;;) {
+      {
+        std::unique_lock<std::mutex> lk(m_);
+        cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+        if (stop_) return;
+        seen = gen_;
+        if (!job_) continue;
+      }
+      work();
+    }
+  }
+  std::vector<std::thread> workers_;
+  std::mutex m_, run_m_;
+  std::condition_variable cv_, done_cv_;
+  const std::function<void(uint32_t)> *job_ = nullptr;
+  uint32_t parts_ = 0;
+  std::atomic<uint32_t> next_{0}, done_{0};
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+};
+
+// fn(part, begin, end) over `threads` contiguous ranges of [0, n) (fewer for
+// small n).
 template <class Fn>
 void parallel_ranges(int64_t n, uint32_t threads, Fn fn) {
   const uint32_t t = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(threads, (n + 4095) / 4096));
@@ -28,13 +110,8 @@ void parallel_ranges(int64_t n, uint32_t threads, Fn fn) {
     fn(0u, (int64_t)0, n);
     return;
   }
-  std::vector<std::thread> pool;
-  pool.reserve(t);
-  for (uint32_t k = 0; k < t; ++k) {
-    const int64_t b = n * k / t, e = n * (k + 1) / t;
-    pool.emplace_back([=] { fn(k, b, e); });
-  }
-  for (auto &th : pool) th.join();
+  const std::function<void(uint32_t)> part = [&](uint32_t k) { fn(k, n * k / t, n * (k + 1) / t); };
+  HostPool::get().run(t, part);
 }
 
 inline uint64_t read_term(const uint8_t *buf, const LayoutDesc &l, int64_t r, int f) {
