@@ -320,6 +320,21 @@ adha_status adha_program_create(const adha_struct *s, uint32_t k, const adha_sec
                                 adha_program **out);
 adha_status adha_program_destroy(adha_program *p);
 
+/* Structured control flow (section 2: the sections form a structured
+ * control-flow graph): the program's sections in a sequence with two-way
+ * branches, as a token list -- a section index s >= 0 runs section s;
+ * ADHA_TOK_IF opens a branch whose first part runs with probability
+ * probs[i] (i counts IFs in order); ADHA_TOK_ELSE starts its second part
+ * (optional); ADHA_TOK_END closes it.  Every section appears exactly once.
+ * Plans of such a program minimise the expected cost over the branch
+ * outcomes; the layout at each join is chosen too (a branch part that
+ * ends in another layout is remapped there).  n_tokens = 0 restores the
+ * plain sequence. */
+#define ADHA_TOK_IF (-1)
+#define ADHA_TOK_ELSE (-2)
+#define ADHA_TOK_END (-3)
+adha_status adha_program_set_flow(adha_program *p, uint32_t n_tokens, const int32_t *tokens, const double *probs);
+
 /* Affinity weights (section 2, the ODS pass) of sections first..last:
  * w[a*F + b] for a != b.  Per loop iteration, fields touched at the same
  * record co-occur once: a direct section adds 1 to every pair of R u W; a
@@ -338,6 +353,14 @@ adha_status adha_ods(const adha_program *p, uint32_t first, uint32_t last, uint3
  * Ties go to the smaller candidate index.  path[k] receives the choice. */
 adha_status adha_pdl_solve(uint32_t k, uint32_t C, const double *T, const double *R,
                            const double *R0, uint32_t *path, double *cost);
+
+/* The expected-cost shortest path of a structured program (tokens and
+ * probs as for adha_program_set_flow) over k sections by C candidates with
+ * the tables of adha_pdl_solve: node[k] per section, join[b] per branch,
+ * *start the node the data starts in. */
+adha_status adha_flow_solve(uint32_t k, uint32_t C, const double *T, const double *R, const double *R0,
+                            uint32_t n_tokens, const int32_t *tokens, const double *probs, uint32_t *node,
+                            uint32_t *join, uint32_t *start, double *cost);
 
 /* ------------------------------------------------------------ planning */
 typedef enum {
@@ -382,6 +405,15 @@ adha_status adha_plan_uniform(const adha_program *p, const adha_layout *l, adha_
  * 1 the host; NULL = all on the GPU).  Its cost tables are zero. */
 adha_status adha_plan_explicit(const adha_program *p, const adha_layout *const *layouts, const int32_t *devices,
                                adha_plan **out);
+/* Candidate layout at the join of branch i (structured programs). */
+adha_status adha_plan_join(const adha_plan *pl, uint32_t i, uint32_t *candidate);
+/* Runs a structured program (any plan of it, GPU sections only) along the
+ * branch outcomes taken[i] (1: the first part of branch i, 0: the second),
+ * n_taken >= the number of branches; otherwise as adha_run. */
+adha_status adha_run_flow(adha_ctx *ctx, const adha_plan *pl, const adha_layout *in_layout, void *buf_a,
+                          void *buf_b, uint64_t buf_cap, const int32_t *idx, uint64_t idx_count,
+                          const uint8_t *taken, uint32_t n_taken, void *stream, const adha_layout **out_layout,
+                          int32_t *out_in_b);
 /* Device of section s's choice: 0 the GPU, 1 the host. */
 adha_status adha_plan_device(const adha_plan *pl, uint32_t s, int32_t *device);
 /* The shortest-path graph: M nodes (C for GPU plans; 2C over both devices,

@@ -195,3 +195,86 @@ def pdl_bruteforce(T, R, R0=None):
         if best is None or v < best:
             best, arg = v, list(combo)
     return best, arg
+
+
+# --------------------------------------------------------------- branches
+TOK_IF, TOK_ELSE, TOK_END = -1, -2, -3
+
+
+def flow_paths(tokens, probs):
+    """Every execution path of a structured program, with its probability.
+
+    A path is a list of steps: ("s", section) runs a section, ("j", branch)
+    is the join after branch `branch`.  A branch's first part runs with
+    probability probs[branch], its second part (after ELSE, possibly empty)
+    otherwise."""
+    def parse(pos, counter):
+        # a sequence up to ELSE / END / the end: list of items
+        items = []
+        while pos < len(tokens) and tokens[pos] not in (TOK_ELSE, TOK_END):
+            t = tokens[pos]
+            if t >= 0:
+                items.append(("s", t))
+                pos += 1
+            else:
+                b = counter[0]
+                counter[0] += 1
+                first, pos = parse(pos + 1, counter)
+                second = []
+                if tokens[pos] == TOK_ELSE:
+                    second, pos = parse(pos + 1, counter)
+                pos += 1                                   # END
+                items.append(("b", b, first, second))
+        return items, pos
+
+    root, _ = parse(0, [0])
+
+    def expand(items):
+        # list of (probability, steps)
+        out = [(1.0, [])]
+        for it in items:
+            if it[0] == "s":
+                out = [(p, st + [it]) for p, st in out]
+            else:
+                _, b, first, second = it
+                pa = probs[b]
+                # each part with its own inner branches' probabilities
+                alts = [(pa * q, s1 + [("j", b)]) for q, s1 in expand(first)] + \
+                       [((1 - pa) * q, s2 + [("j", b)]) for q, s2 in expand(second)]
+                out = [(p * q, st + s) for p, st in out for q, s in alts if q > 0.0]
+        return out
+
+    return expand(root)
+
+
+def flow_expected_cost(tokens, probs, T, R, R0, start, nodes, joins):
+    """Expected cost of an assignment: start node, a node per section and a
+    node per join.  Along a path the data moves from node to node (R, zero
+    when it stays) and every section costs T at its node."""
+    total = 0.0
+    for p, steps in flow_paths(tokens, probs):
+        cur = start
+        cost = R0[start] if R0 is not None else 0.0
+        for st in steps:
+            nxt = nodes[st[1]] if st[0] == "s" else joins[st[1]]
+            if nxt != cur:
+                cost += R[cur][nxt]
+            cur = nxt
+            if st[0] == "s":
+                cost += T[st[1]][nxt]
+        total += p * cost
+    return total
+
+
+def flow_bruteforce(tokens, probs, T, R, R0=None):
+    """Least expected cost over every assignment (tiny cases only)."""
+    k, C = len(T), len(T[0])
+    nb = len(probs)
+    best = None
+    for start in range(C):
+        for nodes in itertools.product(range(C), repeat=k):
+            for joins in itertools.product(range(C), repeat=nb):
+                c = flow_expected_cost(tokens, probs, T, R, R0, start, list(nodes), list(joins))
+                if best is None or c < best[0]:
+                    best = (c, start, list(nodes), list(joins))
+    return best

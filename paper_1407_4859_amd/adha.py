@@ -135,6 +135,10 @@ _SIGS = {
     "adha_run_hetero": ([P, P, P, I32T, P, P, P, P, U64, P, P, U64, P, PP, ctypes.POINTER(I32T),
                          ctypes.POINTER(I32T)], I32T),
     "adha_plan_explicit": ([P, P, P, PP], I32T),
+    "adha_program_set_flow": ([P, U32, P, P], I32T),
+    "adha_flow_solve": ([U32, U32, P, P, P, U32, P, P, P, P, P, ctypes.POINTER(ctypes.c_double)], I32T),
+    "adha_plan_join": ([P, U32, ctypes.POINTER(U32)], I32T),
+    "adha_run_flow": ([P, P, P, P, P, U64, P, U64, P, U32, P, PP, ctypes.POINTER(I32T)], I32T),
     "adha_plan_device": ([P, U32, ctypes.POINTER(I32T)], I32T),
     "adha_plan_nodes": ([P, ctypes.POINTER(U32)], I32T),
     "adha_plan_node_tables": ([P, P, P], I32T),
@@ -375,10 +379,37 @@ class Program:
         check(lib().adha_affinity(self.h, first, last, w))
         return [[w[a * F + b] for b in range(F)] for a in range(F)]
 
+    def set_flow(self, tokens, probs=()):
+        """Branches: tokens are section indices and TOK_IF / TOK_ELSE /
+        TOK_END; probs holds one probability per TOK_IF."""
+        self.flow = (list(tokens), list(probs))
+        pr = (ctypes.c_double * len(probs))(*probs) if probs else None
+        check(lib().adha_program_set_flow(self.h, len(tokens), _i32(tokens) if tokens else None, pr))
+
     def ods(self, first: int, last: int, cap_bytes: int, tile: int = 1) -> Layout:
         h = ctypes.c_void_p()
         check(lib().adha_ods(self.h, first, last, cap_bytes, tile, ctypes.byref(h)))
         return Layout(h)
+
+
+TOK_IF, TOK_ELSE, TOK_END = -1, -2, -3
+
+
+def flow_solve(T, R, tokens, probs=(), R0=None):
+    """(cost, start node, node per section, join node per branch)."""
+    k, C = len(T), len(T[0])
+    Tf = (ctypes.c_double * (k * C))(*[v for row in T for v in row])
+    Rf = (ctypes.c_double * (C * C))(*[v for row in R for v in row])
+    R0f = (ctypes.c_double * C)(*R0) if R0 is not None else None
+    nb = sum(1 for t in tokens if t == TOK_IF)
+    node = (ctypes.c_uint32 * k)()
+    join = (ctypes.c_uint32 * max(1, nb))()
+    start = ctypes.c_uint32()
+    cost = ctypes.c_double()
+    pr = (ctypes.c_double * len(probs))(*probs) if probs else None
+    check(lib().adha_flow_solve(k, C, Tf, Rf, R0f, len(tokens), _i32(tokens), pr, node, join,
+                                ctypes.byref(start), ctypes.byref(cost)))
+    return cost.value, start.value, list(node), list(join)[:nb]
 
 
 def pdl_solve(T, R, R0=None):
@@ -429,6 +460,14 @@ class Plan:
         dv = _i32(devices) if devices is not None else None
         check(lib().adha_plan_explicit(prog.h, arr, dv, ctypes.byref(h)))
         return cls(h, len(prog.sections))
+
+    def joins(self, n_branches: int):
+        out = []
+        for b in range(n_branches):
+            v = ctypes.c_uint32()
+            check(lib().adha_plan_join(self.h, b, ctypes.byref(v)))
+            out.append(v.value)
+        return out
 
     def devices(self):
         out = []
@@ -612,6 +651,20 @@ def run(ctx: Ctx, plan: Plan, in_layout: Layout, buf_a, buf_b, idx=None, stream=
     in_b = ctypes.c_int32()
     check(lib().adha_run(ctx.h, plan.h, in_layout.h, ap, bp, cap, ip, icap // 4, stream_ptr(stream),
                          ctypes.byref(out_l), ctypes.byref(in_b)))
+    return out_l.value, bool(in_b.value)
+
+
+def run_flow(ctx: Ctx, plan: Plan, in_layout: Layout, buf_a, buf_b, taken, idx=None, stream=None):
+    """Runs a structured program along the branch outcomes `taken` (one
+    bool per branch); returns (final layout handle value, True if in b)."""
+    ap, ac = _dev(buf_a)
+    bp, bc = _dev(buf_b)
+    ip, icap = _dev(idx)
+    tk = (ctypes.c_uint8 * max(1, len(taken)))(*[1 if t else 0 for t in taken])
+    out_l = ctypes.c_void_p()
+    in_b = ctypes.c_int32()
+    check(lib().adha_run_flow(ctx.h, plan.h, in_layout.h, ap, bp, min(ac, bc), ip, icap // 4, tk, len(taken),
+                              stream_ptr(stream), ctypes.byref(out_l), ctypes.byref(in_b)))
     return out_l.value, bool(in_b.value)
 
 

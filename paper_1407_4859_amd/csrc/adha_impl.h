@@ -120,6 +120,10 @@ struct adha_section {
 struct adha_program {
   adha::Shape shape;
   std::vector<adha::SectionDesc> secs;
+  // control flow: empty = the sections in order; otherwise section indices
+  // and IF / ELSE / END markers, with one probability per IF
+  std::vector<int32_t> tokens;
+  std::vector<double> probs;
 };
 
 namespace adha {

@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <new>
 
 #include "adha_impl.h"
@@ -31,6 +32,11 @@ struct adha_plan {
   bool hetero = false;
   std::vector<double> TH;
   double rem_h = 0.0, xfer_dh = 0.0, xfer_hd = 0.0;
+  // structured programs: the control flow and the candidate at each join
+  // (kNoJoin: keep whatever layout the branch ends in)
+  std::vector<int32_t> tokens;
+  std::vector<double> probs;
+  std::vector<uint32_t> join;
   double cost = 0.0, seconds = 0.0;
   ~adha_plan() {
     for (auto *l : cands) delete l;
@@ -320,6 +326,200 @@ static adha_status measured_costs(Ctx *ctx, const Shape &sh, const std::vector<S
   return ADHA_OK;
 }
 
+// ------------------------------------------------------------------ structured flow
+static const uint32_t kNoJoin = 0xFFFFFFFFu;
+
+// A block of a structured program: a section, a sequence of blocks, or a
+// two-way branch over two sequences.
+struct FlowBlock {
+  int kind = 0;            // 0 section, 1 sequence, 2 branch
+  int sec = -1;            // section
+  std::vector<int> items;  // sequence
+  int first = -1, second = -1, branch = -1;  // branch: its two sequences and its index
+  double p = 0.0;
+};
+
+// Parses a token list into blocks (block 0 is the root sequence).
+static adha_status parse_flow(const std::vector<int32_t> &tok, const std::vector<double> &probs, size_t k,
+                              std::vector<FlowBlock> *blocks) {
+  blocks->clear();
+  blocks->push_back(FlowBlock{1});
+  std::vector<int> stack{0};          // open sequences
+  std::vector<int> open_branch;       // open branches
+  std::vector<char> seen(k, 0);
+  int n_if = 0;
+  for (size_t t = 0; t < tok.size(); ++t) {
+    const int32_t x = tok[t];
+    if (x >= 0) {
+      if ((size_t)x >= k) return fail(ADHA_ERR_INVALID, "token %zu names section %d of %zu", t, x, k);
+      if (seen[x]) return fail(ADHA_ERR_INVALID, "section %d appears twice in the flow", x);
+      seen[x] = 1;
+      FlowBlock b;
+      b.kind = 0;
+      b.sec = x;
+      blocks->push_back(b);
+      (*blocks)[stack.back()].items.push_back((int)blocks->size() - 1);
+    } else if (x == ADHA_TOK_IF) {
+      if (n_if >= (int)probs.size()) return fail(ADHA_ERR_INVALID, "more branches than probabilities");
+      const double p = probs[n_if];
+      if (!(p >= 0.0 && p <= 1.0)) return fail(ADHA_ERR_INVALID, "branch %d probability %g not in [0, 1]", n_if, p);
+      FlowBlock br;
+      br.kind = 2;
+      br.p = p;
+      br.branch = n_if++;
+      blocks->push_back(br);
+      const int bid = (int)blocks->size() - 1;
+      (*blocks)[stack.back()].items.push_back(bid);
+      blocks->push_back(FlowBlock{1});
+      (*blocks)[bid].first = (int)blocks->size() - 1;
+      blocks->push_back(FlowBlock{1});
+      (*blocks)[bid].second = (int)blocks->size() - 1;
+      open_branch.push_back(bid);
+      stack.push_back((*blocks)[bid].first);
+    } else if (x == ADHA_TOK_ELSE) {
+      if (open_branch.empty()) return fail(ADHA_ERR_INVALID, "ELSE outside a branch at token %zu", t);
+      const FlowBlock &br = (*blocks)[open_branch.back()];
+      if (stack.back() != br.first) return fail(ADHA_ERR_INVALID, "second ELSE in one branch at token %zu", t);
+      stack.back() = br.second;
+    } else if (x == ADHA_TOK_END) {
+      if (open_branch.empty()) return fail(ADHA_ERR_INVALID, "END outside a branch at token %zu", t);
+      open_branch.pop_back();
+      stack.pop_back();
+    } else {
+      return fail(ADHA_ERR_INVALID, "unknown token %d", x);
+    }
+  }
+  if (!open_branch.empty()) return fail(ADHA_ERR_INVALID, "a branch is not closed");
+  if (n_if != (int)probs.size()) return fail(ADHA_ERR_INVALID, "%d branches but %zu probabilities", n_if, probs.size());
+  for (size_t x = 0; x < k; ++x)
+    if (!seen[x]) return fail(ADHA_ERR_INVALID, "section %zu is not in the flow", x);
+  return ADHA_OK;
+}
+
+// Expected-cost shortest path over a structured program: every block gets
+// an M x M matrix B[a][b], the least expected cost of running it entered in
+// node a and left in node b.  A section s: R[a][b] + T[s][b].  A sequence:
+// the min-plus product of its blocks' matrices (empty: 0 on the diagonal).
+// A branch taken with probability p: p * min_x (B1[a][x] + R[x][b]) +
+// (1 - p) * min_y (B2[a][y] + R[y][b]) -- each part may end in its own
+// node and moves to the join node b.  The program: min over a, b of
+// R0[a] + B_root[a][b].  Ties go to the smaller node index.
+struct FlowSolver {
+  size_t M;
+  const double *T, *R;
+  const std::vector<FlowBlock> &blocks;
+  std::vector<std::vector<double>> mat;
+  std::vector<std::vector<std::vector<uint32_t>>> seq_arg;  // per sequence: per step a..c -> middle
+  std::vector<std::vector<uint32_t>> arg1, arg2;            // per branch block
+  double r(size_t a, size_t b) const { return a == b ? 0.0 : R[a * M + b]; }
+
+  FlowSolver(size_t m, const double *t, const double *rr, const std::vector<FlowBlock> &b)
+      : M(m), T(t), R(rr), blocks(b), mat(b.size()), seq_arg(b.size()), arg1(b.size()), arg2(b.size()) {}
+
+  void solve(int id) {
+    const FlowBlock &b = blocks[id];
+    const double inf = std::numeric_limits<double>::infinity();
+    std::vector<double> &B = mat[id];
+    B.assign(M * M, inf);
+    if (b.kind == 0) {
+      for (size_t a = 0; a < M; ++a)
+        for (size_t c = 0; c < M; ++c) B[a * M + c] = r(a, c) + T[(size_t)b.sec * M + c];
+    } else if (b.kind == 1) {
+      if (b.items.empty()) {
+        for (size_t a = 0; a < M; ++a) B[a * M + a] = 0.0;
+        return;
+      }
+      for (int c : b.items) solve(c);
+      B = mat[b.items[0]];
+      for (size_t i = 1; i < b.items.size(); ++i) {
+        const std::vector<double> &N = mat[b.items[i]];
+        std::vector<double> P(M * M, inf);
+        std::vector<uint32_t> arg(M * M, 0);
+        for (size_t a = 0; a < M; ++a)
+          for (size_t c = 0; c < M; ++c) {
+            double best = inf;
+            uint32_t bm = 0;
+            for (size_t m = 0; m < M; ++m) {
+              const double v = B[a * M + m] + N[m * M + c];
+              if (v < best) {
+                best = v;
+                bm = (uint32_t)m;
+              }
+            }
+            P[a * M + c] = best;
+            arg[a * M + c] = bm;
+          }
+        B.swap(P);
+        seq_arg[id].push_back(std::move(arg));
+      }
+    } else {
+      solve(b.first);
+      solve(b.second);
+      const std::vector<double> &B1 = mat[b.first], &B2 = mat[b.second];
+      arg1[id].assign(M * M, 0);
+      arg2[id].assign(M * M, 0);
+      for (size_t a = 0; a < M; ++a)
+        for (size_t c = 0; c < M; ++c) {
+          double b1 = inf, b2 = inf;
+          uint32_t x1 = 0, x2 = 0;
+          for (size_t x = 0; x < M; ++x) {
+            const double v1 = B1[a * M + x] + r(x, c), v2 = B2[a * M + x] + r(x, c);
+            if (v1 < b1) b1 = v1, x1 = (uint32_t)x;
+            if (v2 < b2) b2 = v2, x2 = (uint32_t)x;
+          }
+          // a part that never runs (p = 0 or 1) adds nothing
+          const double e = (b.p > 0.0 ? b.p * b1 : 0.0) + (b.p < 1.0 ? (1.0 - b.p) * b2 : 0.0);
+          B[a * M + c] = e;
+          arg1[id][a * M + c] = x1;
+          arg2[id][a * M + c] = x2;
+        }
+    }
+  }
+
+  // Node of every section and the join node of every branch, for block id
+  // entered in a and left in c.
+  void rebuild(int id, uint32_t a, uint32_t c, std::vector<uint32_t> *node, std::vector<uint32_t> *join) const {
+    const FlowBlock &b = blocks[id];
+    if (b.kind == 0) {
+      (*node)[b.sec] = c;
+    } else if (b.kind == 1) {
+      if (b.items.empty()) return;
+      uint32_t exit = c;
+      for (size_t i = b.items.size() - 1; i >= 1; --i) {
+        const uint32_t mid = seq_arg[id][i - 1][(size_t)a * M + exit];
+        rebuild(b.items[i], mid, exit, node, join);
+        exit = mid;
+      }
+      rebuild(b.items[0], a, exit, node, join);
+    } else {
+      (*join)[b.branch] = c;
+      rebuild(b.first, a, arg1[id][(size_t)a * M + c], node, join);
+      rebuild(b.second, a, arg2[id][(size_t)a * M + c], node, join);
+    }
+  }
+};
+
+static adha_status flow_solve(size_t k, size_t M, const double *T, const double *R, const double *R0,
+                              const std::vector<FlowBlock> &blocks, size_t n_branch, std::vector<uint32_t> *node,
+                              std::vector<uint32_t> *join, double *cost, uint32_t *start = nullptr) {
+  FlowSolver f(M, T, R, blocks);
+  f.solve(0);
+  const std::vector<double> &B = f.mat[0];
+  double best = std::numeric_limits<double>::infinity();
+  uint32_t ba = 0, bc = 0;
+  for (size_t a = 0; a < M; ++a)
+    for (size_t c = 0; c < M; ++c) {
+      const double v = (R0 ? R0[a] : 0.0) + B[a * M + c];
+      if (v < best) best = v, ba = (uint32_t)a, bc = (uint32_t)c;
+    }
+  node->assign(k, 0);
+  join->assign(n_branch, 0);
+  f.rebuild(0, ba, bc, node, join);
+  *cost = best;
+  if (start) *start = ba;
+  return ADHA_OK;
+}
+
 // The GPU's whole-struct remap figure of a plan: every pair of different
 // layouts costs the same (zero when the plan has one candidate).
 static double device_remap_figure(const adha_plan *pl) {
@@ -468,6 +668,26 @@ adha_status adha_program_destroy(adha_program *p) {
   return ADHA_OK;
 }
 
+adha_status adha_program_set_flow(adha_program *p, uint32_t n_tokens, const int32_t *tokens, const double *probs) {
+  if (!p) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (n_tokens == 0) {
+    p->tokens.clear();
+    p->probs.clear();
+    return ADHA_OK;
+  }
+  if (!tokens) return fail(ADHA_ERR_INVALID, "tokens is NULL");
+  std::vector<int32_t> tok(tokens, tokens + n_tokens);
+  size_t n_if = 0;
+  for (int32_t x : tok) n_if += x == ADHA_TOK_IF;
+  if (n_if && !probs) return fail(ADHA_ERR_INVALID, "probs is NULL");
+  std::vector<double> pr(probs, probs + n_if);
+  std::vector<FlowBlock> blocks;
+  ADHA_TRY(parse_flow(tok, pr, p->secs.size(), &blocks));
+  p->tokens = std::move(tok);
+  p->probs = std::move(pr);
+  return ADHA_OK;
+}
+
 adha_status adha_affinity(const adha_program *p, uint32_t first, uint32_t last, uint64_t *w) {
   if (!p || !w) return fail(ADHA_ERR_INVALID, "NULL argument");
   if (first > last || last >= p->secs.size()) return fail(ADHA_ERR_INVALID, "bad section range");
@@ -500,6 +720,29 @@ adha_status adha_pdl_solve(uint32_t k, uint32_t C, const double *T, const double
   return ADHA_OK;
 }
 
+adha_status adha_flow_solve(uint32_t k, uint32_t C, const double *T, const double *R, const double *R0,
+                            uint32_t n_tokens, const int32_t *tokens, const double *probs, uint32_t *node,
+                            uint32_t *join, uint32_t *start, double *cost) {
+  if (!T || !R || !tokens || !node || !cost) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (k == 0 || C == 0) return fail(ADHA_ERR_INVALID, "k and C must be positive");
+  std::vector<int32_t> tok(tokens, tokens + n_tokens);
+  size_t n_if = 0;
+  for (int32_t x : tok) n_if += x == ADHA_TOK_IF;
+  if (n_if && (!probs || !join)) return fail(ADHA_ERR_INVALID, "branches need probs and join");
+  std::vector<double> pr(probs ? probs : nullptr, probs ? probs + n_if : nullptr);
+  std::vector<FlowBlock> blocks;
+  ADHA_TRY(parse_flow(tok, pr, k, &blocks));
+  std::vector<uint32_t> nv, jv;
+  double c = 0;
+  uint32_t a = 0;
+  ADHA_TRY(flow_solve(k, C, T, R, R0, blocks, n_if, &nv, &jv, &c, &a));
+  memcpy(node, nv.data(), k * sizeof(uint32_t));
+  if (n_if) memcpy(join, jv.data(), n_if * sizeof(uint32_t));
+  if (start) *start = a;
+  *cost = c;
+  return ADHA_OK;
+}
+
 adha_status adha_plan_opts_default(adha_plan_opts *o) {
   if (!o) return fail(ADHA_ERR_INVALID, "NULL argument");
   o->cost = ADHA_COST_MEASURED;
@@ -523,6 +766,8 @@ adha_status adha_plan_create(adha_ctx *ctx, const adha_program *p, const adha_pl
   if (o->init < ADHA_INIT_FREE || o->init > ADHA_INIT_HOST_AOS) return fail(ADHA_ERR_INVALID, "unknown init option");
   if (o->init == ADHA_INIT_HOST_AOS && o->devices != ADHA_DEVICES_GPU_HOST)
     return fail(ADHA_ERR_INVALID, "data starting on the host needs a plan over both devices");
+  if (!p->tokens.empty() && o->devices != ADHA_DEVICES_GPU)
+    return fail(ADHA_ERR_UNSUPPORTED, "programs with branches are planned for the GPU only");
   auto t0 = std::chrono::steady_clock::now();
   std::unique_ptr<adha_plan> pl(new (std::nothrow) adha_plan);
   if (!pl) return fail(ADHA_ERR_OOM, "plan allocation failed");
@@ -593,7 +838,16 @@ adha_status adha_plan_create(adha_ctx *ctx, const adha_program *p, const adha_pl
   if (o->init == ADHA_INIT_HOST_AOS)
     for (size_t m = 0; m < M; ++m) R0[m] = m == C ? 0.0 : NR[C * M + m];
   std::vector<uint32_t> nodes;
-  ADHA_TRY(pdl_solve((uint32_t)k, (uint32_t)M, NT.data(), NR.data(), R0.data(), &nodes, &pl->cost));
+  if (p->tokens.empty()) {
+    ADHA_TRY(pdl_solve((uint32_t)k, (uint32_t)M, NT.data(), NR.data(), R0.data(), &nodes, &pl->cost));
+  } else {
+    std::vector<FlowBlock> blocks;
+    ADHA_TRY(parse_flow(p->tokens, p->probs, k, &blocks));
+    pl->tokens = p->tokens;
+    pl->probs = p->probs;
+    ADHA_TRY(flow_solve(k, M, NT.data(), NR.data(), R0.data(), blocks, p->probs.size(), &nodes, &pl->join,
+                        &pl->cost));
+  }
   pl->choice.resize(k);
   pl->dev.resize(k);
   for (size_t s2 = 0; s2 < k; ++s2) {
@@ -633,7 +887,18 @@ adha_status adha_plan_explicit(const adha_program *p, const adha_layout *const *
   pl->T.assign(k * C, 0.0);
   pl->R.assign(C * C, 0.0);
   if (pl->hetero) pl->TH.assign(k * C, 0.0);
+  pl->tokens = p->tokens;
+  pl->probs = p->probs;
+  pl->join.assign(p->probs.size(), kNoJoin);
   *out = pl.release();
+  return ADHA_OK;
+}
+
+adha_status adha_plan_join(const adha_plan *pl, uint32_t i, uint32_t *candidate) {
+  if (!pl || !candidate) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (i >= pl->join.size()) return fail(ADHA_ERR_INVALID, "branch %u out of range", i);
+  if (pl->join[i] == kNoJoin) return fail(ADHA_ERR_STATE, "branch %u of an explicit plan has no join layout", i);
+  *candidate = pl->join[i] % (uint32_t)pl->cands.size();
   return ADHA_OK;
 }
 
@@ -674,6 +939,9 @@ adha_status adha_plan_uniform(const adha_program *p, const adha_layout *l, adha_
   pl->cands.push_back(c);
   pl->choice.assign(p->secs.size(), 0);
   pl->dev.assign(p->secs.size(), 0);
+  pl->tokens = p->tokens;
+  pl->probs = p->probs;
+  pl->join.assign(p->probs.size(), 0);
   pl->T.assign(p->secs.size(), 0.0);
   pl->R.assign(1, 0.0);
   *out = pl;
@@ -731,6 +999,7 @@ adha_status adha_run(adha_ctx *ctx, const adha_plan *pl, const adha_layout *in_l
   if (!in_layout->d.shape.same(pl->shape)) return fail(ADHA_ERR_INVALID, "input layout describes another struct");
   for (int32_t d : pl->dev)
     if (d != 0) return fail(ADHA_ERR_INVALID, "the plan maps sections to the host: run it with adha_run_hetero");
+  if (!pl->tokens.empty()) return fail(ADHA_ERR_INVALID, "the program has branches: run it with adha_run_flow");
   // validate everything before the first launch
   const adha_layout *cur = in_layout;
   bool in_b = false, needs_b = false;
@@ -786,6 +1055,7 @@ adha_status adha_run_hetero(adha_ctx *ctx, const adha_plan *pl, const adha_layou
     return fail(ADHA_ERR_INVALID, "NULL argument");
   if (!in_layout->d.shape.same(pl->shape)) return fail(ADHA_ERR_INVALID, "input layout describes another struct");
   if (in_device != 0 && in_device != 1) return fail(ADHA_ERR_INVALID, "in_device must be 0 (GPU) or 1 (host)");
+  if (!pl->tokens.empty()) return fail(ADHA_ERR_UNSUPPORTED, "programs with branches run on the GPU (adha_run_flow)");
   // validate everything before the first launch or copy
   const size_t k = pl->secs.size();
   uint64_t need = in_layout->d.nbytes;
@@ -879,6 +1149,95 @@ adha_status adha_run_hetero(adha_ctx *ctx, const adha_plan *pl, const adha_layou
   *out_layout = cur;
   *out_device = where;
   *out_in_b = which;
+  return ADHA_OK;
+}
+
+adha_status adha_run_flow(adha_ctx *ctx, const adha_plan *pl, const adha_layout *in_layout, void *buf_a,
+                          void *buf_b, uint64_t buf_cap, const int32_t *idx, uint64_t idx_count,
+                          const uint8_t *taken, uint32_t n_taken, void *stream, const adha_layout **out_layout,
+                          int32_t *out_in_b) {
+  if (!ctx || !pl || !in_layout || !out_layout || !out_in_b) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (!in_layout->d.shape.same(pl->shape)) return fail(ADHA_ERR_INVALID, "input layout describes another struct");
+  for (int32_t d : pl->dev)
+    if (d != 0) return fail(ADHA_ERR_UNSUPPORTED, "branches run GPU sections only");
+  const size_t k = pl->secs.size();
+  // the walk: the sequence of (section or join) steps along the outcomes
+  std::vector<int32_t> tok = pl->tokens;
+  if (tok.empty())
+    for (size_t s2 = 0; s2 < k; ++s2) tok.push_back((int32_t)s2);
+  size_t n_if = 0;
+  for (int32_t x : tok) n_if += x == ADHA_TOK_IF;
+  if (n_if && (!taken || n_taken < n_if)) return fail(ADHA_ERR_INVALID, "%zu branch outcomes are needed", n_if);
+  struct Step {
+    int sec;          // >= 0: run this section
+    uint32_t join;    // else: move to this join candidate (kNoJoin: stay)
+  };
+  std::vector<FlowBlock> blocks;
+  ADHA_TRY(parse_flow(tok, pl->probs, k, &blocks));
+  std::vector<Step> steps;
+  // the blocks along the outcomes: a branch runs the part taken, then moves
+  // to its join layout
+  std::vector<std::pair<int, int>> stack{{0, 0}};  // (block, next item)
+  while (!stack.empty()) {
+    auto &[id, pos] = stack.back();
+    const FlowBlock &b = blocks[id];
+    if (b.kind == 0) {
+      steps.push_back({b.sec, 0});
+      stack.pop_back();
+    } else if (b.kind == 1) {
+      if (pos < (int)b.items.size()) {
+        const int c = b.items[pos++];
+        stack.push_back({c, 0});
+      } else {
+        stack.pop_back();
+      }
+    } else {
+      if (pos == 0) {
+        pos = 1;
+        stack.push_back({taken[b.branch] ? b.first : b.second, 0});
+      } else {
+        steps.push_back({-1, pl->join.empty() ? kNoJoin : pl->join[b.branch]});
+        stack.pop_back();
+      }
+    }
+  }
+  uint64_t need = in_layout->d.nbytes;
+  for (const Step &st2 : steps) {
+    const adha_layout *L = st2.sec >= 0 ? pl->cands[pl->choice[st2.sec]]
+                                        : (st2.join == kNoJoin ? nullptr : pl->cands[st2.join % pl->cands.size()]);
+    if (!L) continue;
+    need = std::max(need, L->d.nbytes);
+    if (st2.sec >= 0) {
+      adha_section tmp;
+      tmp.d = pl->secs[st2.sec];
+      ADHA_TRY(validate_section_run(&tmp, L, buf_a, buf_cap, idx, idx_count));
+    }
+  }
+  if (buf_cap < need) return fail(ADHA_ERR_INVALID, "buffers hold %llu bytes, the plan needs %llu",
+                                  (unsigned long long)buf_cap, (unsigned long long)need);
+  if (need && (!buf_a || !buf_b || ((uintptr_t)buf_a & 255u) || ((uintptr_t)buf_b & 255u)))
+    return fail(ADHA_ERR_INVALID, "buffers are NULL or misaligned");
+  {
+    const uintptr_t x = (uintptr_t)buf_a, y = (uintptr_t)buf_b;
+    if (need && x < y + need && y < x + need) return fail(ADHA_ERR_INVALID, "buf_a and buf_b overlap");
+  }
+  DeviceGuard g(ctx->c.device);
+  hipStream_t st = (hipStream_t)stream;
+  const adha_layout *cur = in_layout;
+  bool in_b = false;
+  for (const Step &st2 : steps) {
+    const adha_layout *L = st2.sec >= 0 ? pl->cands[pl->choice[st2.sec]]
+                                        : (st2.join == kNoJoin ? nullptr : pl->cands[st2.join % pl->cands.size()]);
+    if (!L) continue;
+    if (!cur->d.same_map(L->d)) {
+      ADHA_TRY(remap_one(&ctx->c, cur, in_b ? buf_b : buf_a, L, in_b ? buf_a : buf_b, st));
+      in_b = !in_b;
+    }
+    cur = L;
+    if (st2.sec >= 0) ADHA_TRY(section_launch(&ctx->c, pl->secs[st2.sec], L->d, in_b ? buf_b : buf_a, idx, st));
+  }
+  *out_layout = cur;
+  *out_in_b = in_b ? 1 : 0;
   return ADHA_OK;
 }
 
