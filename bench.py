@@ -16,6 +16,9 @@ Besides the timed steps the run reports (outside the timed region):
   kmeans        the K-Means-shaped program (2^23 points, a direct loop and a
                 per-cluster reduction of 32 features): planned vs all-AoS and
                 all-SoA, per-section GB/s;
+  flow          the multi-section workload with branches: expected time of
+                the branch-aware plan vs a plan ignoring branches, all-AoS and
+                all-SoA;
   hetero        plans over the GPU and the host (plain small program, data
                 starting on the host, N = 2^10 .. 2^20): planned devices and
                 run time vs all-GPU and all-host;
@@ -76,6 +79,8 @@ def parse():
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-kmeans", action="store_true")
     ap.add_argument("--skip-hetero", action="store_true")
+    ap.add_argument("--skip-flow", action="store_true")
+    ap.add_argument("--only-flow", action="store_true", help="the branching-program leg only")
     ap.add_argument("--only-hetero", action="store_true", help="the GPU + host planning leg only")
     ap.add_argument("--only-kmeans", action="store_true", help="the K-Means-shaped leg only (for profiling)")
     ap.add_argument("--skip-cpu", action="store_true")
@@ -289,6 +294,63 @@ def kmeans_bench(A, synth, torch, timer, log2n=23):
     return res
 
 
+FLOW_TOKENS = [0, 1, -1, 2, 3, -2, 4, -3, 5, -1, 6, -3, 7]   # IF = -1, ELSE = -2, END = -3
+FLOW_PROBS = [0.6, 0.3]
+
+
+def flow_bench(A, synth, torch, timer, log2n=24):
+    """The multi-section workload with branches: sections 2-3 run with
+    probability 0.6, else section 4; section 6 with probability 0.3.  The
+    expected time over the four outcomes for the branch-aware plan, the plan
+    made as if every section ran in sequence, all-AoS and all-SoA."""
+    import itertools
+    n = 1 << log2n
+    spec = synth.config3_struct(n)
+    st = A.Struct.from_spec(spec)
+    secs = synth.random_program(3, spec.n_fields)
+    ss = [A.Section.from_spec(st, s) for s in secs]
+    linear = A.Program(st, ss)
+    prog = A.Program(st, ss)
+    prog.set_flow(FLOW_TOKENS, FLOW_PROBS)
+    aos_l, soa_l = A.Layout.aos(st), A.Layout.soa(st)
+    cap = max(aos_l.nbytes, soa_l.nbytes) + (1 << 26)
+    buf_a = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    buf_b = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    fill_fields(buf_a, spec, 3, torch, synth)
+    idx = synth.uniform_index_torch(3, 999, n * 16, n, "cuda")
+    ctx = A.Ctx(0)
+    t0 = time.perf_counter()
+    plan = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_MEASURED, catalogue=A.CAT_FULL, cap_bytes=64, reps=3),
+                         idx=idx)
+    plan_s = time.perf_counter() - t0
+    lin = A.Plan.create(ctx, linear, A.plan_opts(cost=A.COST_MEASURED, catalogue=A.CAT_FULL, cap_bytes=64, reps=3),
+                        idx=idx)
+    blind = A.Plan.explicit(prog, [lin.candidate(c) for c in lin.choices()])
+    plans = {"adha_flow": plan, "adha_ignoring_branches": blind, "all_aos": A.Plan.uniform(prog, aos_l),
+             "all_soa": A.Plan.uniform(prog, soa_l)}
+    res = {"workload": f"N=2^{log2n} records, the 8-section program (seed 3) with branches: "
+                       f"0 1 IF(0.6) 2 3 ELSE 4 END 5 IF(0.3) 6 END 7",
+           "plan_seconds": round(plan_s, 2), "adha_flow_choices": plan.choices(), "adha_flow_joins": plan.joins(2),
+           "predicted_expected_ms": round(plan.cost / 1e3, 3), "outcomes": {}}
+    for name, pl in plans.items():
+        first = pl.candidate(pl.choices()[0])
+        exp_ms = 0.0
+        for taken in itertools.product([1, 0], repeat=2):
+            prob = 1.0
+            for p, t in zip(FLOW_PROBS, taken):
+                prob *= p if t else 1.0 - p
+            ms, _ = timer.time(lambda: A.run_flow(ctx, pl, first, buf_a, buf_b, taken, idx), reps=3, warm=1)
+            res["outcomes"].setdefault(name, {})["".join(map(str, taken))] = round(ms, 3)
+            exp_ms += prob * ms
+        res[name + "_expected_ms"] = round(exp_ms, 3)
+    ctx.check()
+    best_uniform = min(res["all_aos_expected_ms"], res["all_soa_expected_ms"])
+    res["speedup_vs_best_uniform"] = round(best_uniform / res["adha_flow_expected_ms"], 3)
+    res["gain_vs_ignoring_branches"] = round(res["adha_ignoring_branches_expected_ms"] /
+                                             res["adha_flow_expected_ms"], 3)
+    return res
+
+
 def hetero_bench(A, synth, torch):
     """Plans over the GPU and the host for the plain small program (8 f32
     fields, MULADD3, SUB2, SUM) with its data starting in AoS on the host,
@@ -441,6 +503,9 @@ def main():
     if args.only_learned:
         print(json.dumps({"learned": learned_bench(A, synth, torch, args)}), flush=True)
         return
+    if args.only_flow:
+        print(json.dumps({"flow": flow_bench(A, synth, torch, timer, args.program_log2n)}), flush=True)
+        return
     if args.only_hetero:
         print(json.dumps({"hetero": hetero_bench(A, synth, torch)}), flush=True)
         return
@@ -546,6 +611,12 @@ def main():
                 line["kmeans"] = kmeans_bench(A, synth, torch, timer)
             except Exception as e:
                 line["kmeans"] = {"error": repr(e)}
+            torch.cuda.empty_cache()
+        if not args.skip_flow:
+            try:
+                line["flow"] = flow_bench(A, synth, torch, timer, args.program_log2n)
+            except Exception as e:
+                line["flow"] = {"error": repr(e)}
             torch.cuda.empty_cache()
         if not args.skip_hetero:
             try:
