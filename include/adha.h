@@ -260,6 +260,18 @@ adha_status adha_tune_load(adha_ctx *ctx, const char *path);
 adha_status adha_section_create(const adha_struct *s, adha_op op, uint32_t n_read,
                                 const int32_t *read, uint32_t n_write, const int32_t *write,
                                 uint32_t degree, adha_section **out);
+/* A stencil section (section 3: the Medical sections are loops over a
+ * 256^3 image): a GEN gather whose d neighbours are fixed offsets on a 3-D
+ * grid of nx * ny * nz records (N must equal that product; record r sits at
+ * x = r % nx, y = (r / nx) % ny, z = r / (nx * ny)).  Neighbour j of r is
+ * the record at (x + off[3j], y + off[3j+1], z + off[3j+2]); one outside
+ * the grid is left out (not an error).  Terms are taken as for gathers:
+ * neighbours in order j = 0..d-1, each with its read fields in ascending
+ * id.  No index array is read.  Stencils must not write a field they read;
+ * 1 <= d <= 32, |offsets| < the grid's extent. */
+adha_status adha_section_create_stencil(const adha_struct *s, uint32_t n_read, const int32_t *read,
+                                        uint32_t n_write, const int32_t *write, uint32_t nx, uint32_t ny,
+                                        uint32_t nz, uint32_t d, const int32_t *offsets, adha_section **out);
 /* A reduction section (section 3: the second K-Means section reduces all
  * the features over the points).  It reads n_read fields (F32, F64 or I32)
  * of every record and, when key_field >= 0, the I32 key field, and adds

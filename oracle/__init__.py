@@ -14,6 +14,8 @@ Parity status per function (what pins each one is listed in its tests):
   planner.ods_greedy     pinned (Table 3 split, brute-force partitions)
   planner.pdl_dp         pinned (brute-force enumeration, networkx)
   mlp                    pinned (finite differences, least squares)
+  stencil_index          pinned (hand-listed neighbours of a small grid)
+  reduce.reduce          pinned (exact rounding by hand, closed form, brute force)
 """
 from __future__ import annotations
 
@@ -97,6 +99,22 @@ def section(layout: Layout, dtypes, op: int, read, write, degree: int, idx, buf:
     if bad < 0:
         raise ValueError("too many terms per record")
     return int(bad)
+
+
+def stencil_index(nx: int, ny: int, nz: int, offsets) -> np.ndarray:
+    """The index array a stencil stands for (section 3: the Medical loops run
+    over a 3-D image): record r = x + nx*(y + ny*z), neighbour j at
+    (x+dx, y+dy, z+dz), written as -1 (left out) when outside the grid.
+    Feed it to section() and ignore the count of left-out neighbours."""
+    n = nx * ny * nz
+    r = np.arange(n, dtype=np.int64)
+    x, y, z = r % nx, (r // nx) % ny, r // (nx * ny)
+    out = np.empty((n, len(offsets)), np.int32)
+    for j, (dx, dy, dz) in enumerate(offsets):
+        xx, yy, zz = x + dx, y + dy, z + dz
+        inside = (xx >= 0) & (xx < nx) & (yy >= 0) & (yy < ny) & (zz >= 0) & (zz < nz)
+        out[:, j] = np.where(inside, xx + nx * (yy + ny * zz), -1)
+    return out.reshape(-1)
 
 
 def pack(layout: Layout, cols) -> np.ndarray:

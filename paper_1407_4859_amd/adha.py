@@ -110,6 +110,7 @@ _SIGS = {
     "adha_tune_load": ([P, ctypes.c_char_p], I32T),
     "adha_section_create": ([P, ctypes.c_int, U32, P, U32, P, U32, PP], I32T),
     "adha_section_create_reduce": ([P, U32, P, ctypes.c_int32, U32, P, U64, PP], I32T),
+    "adha_section_create_stencil": ([P, U32, P, U32, P, U32, U32, U32, U32, P, PP], I32T),
     "adha_section_destroy": ([P], I32T),
     "adha_section_run": ([P, P, P, P, U64, P, U64, P], I32T),
     "adha_section_bytes": ([P, ctypes.POINTER(U64)], I32T),
@@ -321,6 +322,21 @@ class Section:
         if spec.op == OP_REDUCE:
             raise ValueError("reduction specs need a result table: use Section.reduce")
         return cls(st, spec.op, spec.read, spec.write, spec.degree)
+
+    @classmethod
+    def stencil(cls, st: Struct, read, write, grid, offsets):
+        """A GEN gather over grid neighbours: grid = (nx, ny, nz), offsets a
+        list of (dx, dy, dz)."""
+        flat = [int(v) for o in offsets for v in o]
+        h = ctypes.c_void_p()
+        check(lib().adha_section_create_stencil(st.h, len(read), _i32(read), len(write), _i32(write),
+                                                grid[0], grid[1], grid[2], len(offsets), _i32(flat),
+                                                ctypes.byref(h)))
+        self = cls.__new__(cls)
+        self.h = h
+        self.op, self.read, self.write, self.degree = OP_GEN, sorted(read), sorted(write), len(offsets)
+        self.grid, self.offsets = tuple(grid), [tuple(o) for o in offsets]
+        return self
 
     @classmethod
     def reduce(cls, st: Struct, read, key: int, n_keys: int, out):

@@ -1,5 +1,6 @@
 // The exported C-ABI: argument validation on the host, then dispatch.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -570,6 +571,30 @@ adha_status adha_section_create(const adha_struct *s, adha_op op, uint32_t n_rea
   return ADHA_OK;
 }
 
+adha_status adha_section_create_stencil(const adha_struct *s, uint32_t n_read, const int32_t *read,
+                                        uint32_t n_write, const int32_t *write, uint32_t nx, uint32_t ny,
+                                        uint32_t nz, uint32_t d, const int32_t *offsets, adha_section **out) {
+  if (!s || !out || !offsets) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (d == 0 || d > ADHA_MAX_DEGREE) return fail(ADHA_ERR_INVALID, "stencil degree %u not in [1, %d]", d, ADHA_MAX_DEGREE);
+  if (s->shape.n >= (int64_t(1) << 31)) return fail(ADHA_ERR_UNSUPPORTED, "stencil grids hold fewer than 2^31 records");
+  if ((uint64_t)nx * ny * nz != (uint64_t)s->shape.n || nx == 0 || ny == 0 || nz == 0)
+    return fail(ADHA_ERR_INVALID, "grid %u x %u x %u does not hold the struct's %lld records", nx, ny, nz,
+                (long long)s->shape.n);
+  const uint32_t ext[3] = {nx, ny, nz};
+  for (uint32_t j = 0; j < 3 * d; ++j)
+    if ((uint64_t)std::abs((int64_t)offsets[j]) >= ext[j % 3])
+      return fail(ADHA_ERR_INVALID, "offset %d of neighbour %u reaches past the grid", offsets[j], j / 3);
+  adha_section *sec = nullptr;
+  ADHA_TRY(adha_section_create(s, ADHA_OP_GEN, n_read, read, n_write, write, d, &sec));
+  sec->d.stencil = true;
+  sec->d.nx = nx;
+  sec->d.ny = ny;
+  sec->d.nz = nz;
+  sec->d.offsets.assign(offsets, offsets + 3 * d);
+  *out = sec;
+  return ADHA_OK;
+}
+
 adha_status adha_section_create_reduce(const adha_struct *s, uint32_t n_read, const int32_t *read,
                                        int32_t key_field, uint32_t n_keys, void *out, uint64_t out_cap,
                                        adha_section **out_sec) {
@@ -635,7 +660,7 @@ adha_status validate_section_run(const adha_section *sec, const adha_layout *l, 
   if (!sec || !l) return fail(ADHA_ERR_INVALID, "NULL argument");
   if (!sec->d.shape.same(l->d.shape)) return fail(ADHA_ERR_INVALID, "section and layout describe different structs");
   ADHA_TRY(check_dev_buf("buf", buf, buf_cap, l->d.nbytes));
-  if (sec->d.degree > 0 && l->d.shape.n > 0) {
+  if (sec->d.degree > 0 && !sec->d.stencil && l->d.shape.n > 0) {
     if (!idx) return fail(ADHA_ERR_INVALID, "gather section needs an index array");
     if (!aligned(idx)) return fail(ADHA_ERR_INVALID, "idx is not 256-byte aligned");
     if (idx_count < (uint64_t)l->d.shape.n * sec->d.degree)

@@ -85,6 +85,10 @@ struct SectionDesc {
   int32_t op = 0;
   std::vector<int32_t> rd, wr;
   uint32_t degree = 0;
+  // stencils: neighbours at grid offsets instead of an index array
+  bool stencil = false;
+  uint32_t nx = 0, ny = 0, nz = 0;
+  std::vector<int32_t> offsets;  // 3 per neighbour
   // reductions: key field (-1: none), key count, result table (device)
   int32_t key = -1;
   uint32_t n_keys = 1;

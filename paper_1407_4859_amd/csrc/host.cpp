@@ -268,9 +268,23 @@ adha_status host_section_run(uint32_t threads, const SectionDesc &sec, const Lay
             }
           }
         } else {
-          const int32_t *row = idx + (uint64_t)r * sec.degree;
+          const int32_t *row = sec.stencil ? nullptr : idx + (uint64_t)r * sec.degree;
+          int64_t x = 0, y = 0, z = 0;
+          if (sec.stencil) {
+            x = r % sec.nx;
+            y = (r / sec.nx) % sec.ny;
+            z = r / ((int64_t)sec.nx * sec.ny);
+          }
           for (uint32_t j = 0; j < sec.degree; ++j) {
-            const int64_t nb = row[j];
+            int64_t nb;
+            if (sec.stencil) {
+              const int64_t xx = x + sec.offsets[3 * j], yy = y + sec.offsets[3 * j + 1],
+                            zz = z + sec.offsets[3 * j + 2];
+              if (xx < 0 || xx >= sec.nx || yy < 0 || yy >= sec.ny || zz < 0 || zz >= sec.nz) continue;  // off the grid
+              nb = xx + (int64_t)sec.nx * (yy + (int64_t)sec.ny * zz);
+            } else {
+              nb = row[j];
+            }
             if (nb < 0 || nb >= n) {
               ++bad[k];
               continue;
@@ -326,7 +340,7 @@ adha_status adha_host_section_run(const adha_section *sec, const adha_layout *l,
   if (n > 0 && (!buf || buf_cap < l->d.nbytes))
     return fail(ADHA_ERR_INVALID, "host buffer is NULL or holds %llu bytes, the layout needs %llu",
                 (unsigned long long)buf_cap, (unsigned long long)l->d.nbytes);
-  if (sec->d.degree > 0 && n > 0 && (!idx || idx_count < (uint64_t)n * sec->d.degree))
+  if (sec->d.degree > 0 && !sec->d.stencil && n > 0 && (!idx || idx_count < (uint64_t)n * sec->d.degree))
     return fail(ADHA_ERR_INVALID, "gather section needs a host index array of N*d entries");
   if (sec->d.op == ADHA_OP_REDUCE && (!table || table_cap < (uint64_t)sec->d.reduce_cells() * 8))
     return fail(ADHA_ERR_INVALID, "reduction needs a host table of %u cells", sec->d.reduce_cells());

@@ -179,6 +179,7 @@ uint64_t SectionDesc::algorithmic_bytes() const {
   uint64_t n = (uint64_t)shape.n;
   if (key >= 0) rb += shape.ebytes[key];
   if (degree == 0) return n * (rb + wb);
+  if (stencil) return n * ((uint64_t)degree * rb + wb);
   return n * (4ull * degree + (uint64_t)degree * rb + wb);
 }
 

@@ -214,12 +214,15 @@ static double group_random_bytes(const LayoutDesc &l, size_t gi, const std::vect
 double analytic_bytes_per_record(const SectionDesc &s, const LayoutDesc &l) {
   double b = 0.0;
   const std::vector<int32_t> streamed = s.streamed_reads();
+  // a stencil's neighbours are the record's own neighbourhood, served from
+  // cache after the first touch: it moves the bytes of a direct pass
+  const bool stream = s.degree == 0 || s.stencil;
   for (size_t gi = 0; gi < l.groups.size(); ++gi) {
-    if (s.degree == 0) b += group_stream_bytes(l, gi, streamed);
+    if (stream) b += group_stream_bytes(l, gi, streamed);
     else b += s.degree * group_random_bytes(l, gi, s.rd);
     b += group_stream_bytes(l, gi, s.wr);
   }
-  if (s.degree) b += 4.0 * s.degree;
+  if (s.degree && !s.stencil) b += 4.0 * s.degree;
   return b;
 }
 
@@ -273,7 +276,7 @@ struct DevBuf {
 
 // Which section times measured_costs takes on the device (the remap figure
 // is always measured).
-enum TimeSections { kTimeAll, kTimeNone, kTimeReductions };
+enum TimeSections { kTimeAll, kTimeNone, kTimeUntrained };
 
 static adha_status measured_costs(Ctx *ctx, const Shape &sh, const std::vector<SectionDesc> &secs,
                                   const std::vector<adha_layout *> &cands, uint32_t reps,
@@ -301,7 +304,7 @@ static adha_status measured_costs(Ctx *ctx, const Shape &sh, const std::vector<S
   if (which == kTimeAll) T->assign(k * C, 0.0);
   for (size_t c = 0; c < C && sections; ++c)
     for (size_t s = 0; s < k; ++s) {
-      if (which == kTimeReductions && secs[s].op != ADHA_OP_REDUCE) continue;
+      if (which == kTimeUntrained && secs[s].op != ADHA_OP_REDUCE && !secs[s].stencil) continue;
       // a gather section's index array is [N][d]; a wider one is read as [N][d] too
       ADHA_TRY(time_us(stream, reps,
                        [&] { return section_launch(ctx, secs[s], cands[c]->d, a.p, idx, stream, tab.p); },
@@ -805,12 +808,12 @@ adha_status adha_plan_create(adha_ctx *ctx, const adha_program *p, const adha_pl
       pl->T = us;
       // remap weights: a few measured whole-struct remaps (milliseconds of
       // device time), the same figure the measured provider uses
-      // the network was trained on loops that write per record; reductions
-      // are timed on the device
-      bool any_reduce = false;
-      for (const SectionDesc &d : p->secs) any_reduce |= d.op == ADHA_OP_REDUCE;
+      // the network was trained on direct loops and index gathers;
+      // reductions and stencils are timed on the device
+      bool untrained = false;
+      for (const SectionDesc &d : p->secs) untrained |= d.op == ADHA_OP_REDUCE || d.stencil;
       ADHA_TRY(measured_costs(&ctx->c, p->shape, p->secs, pl->cands, std::max<uint32_t>(1, o->reps), idx,
-                              idx_count, st, &pl->T, &pl->R, any_reduce ? kTimeReductions : kTimeNone));
+                              idx_count, st, &pl->T, &pl->R, untrained ? kTimeUntrained : kTimeNone));
     }
   }
   if (src == ADHA_COST_ANALYTIC) {
@@ -1068,7 +1071,7 @@ adha_status adha_run_hetero(adha_ctx *ctx, const adha_plan *pl, const adha_layou
     uses_host |= d == 1;
     uses_dev |= d == 0 || d != at;  // a move between devices goes through the GPU's buffers
     at = d;
-    if (pl->secs[s].degree) (d == 1 ? host_gather : dev_gather) = true;
+    if (pl->secs[s].degree && !pl->secs[s].stencil) (d == 1 ? host_gather : dev_gather) = true;
   }
   const int64_t n = pl->shape.n;
   if (need) {
@@ -1087,7 +1090,8 @@ adha_status adha_run_hetero(adha_ctx *ctx, const adha_plan *pl, const adha_layou
   }
   if (n > 0) {
     uint32_t maxd = 0;
-    for (auto &d : pl->secs) maxd = std::max(maxd, d.degree);
+    for (auto &d : pl->secs)
+      if (!d.stencil) maxd = std::max(maxd, d.degree);
     if (host_gather && (!idx_host || idx_count < (uint64_t)n * maxd))
       return fail(ADHA_ERR_INVALID, "a gather on the host needs a host index array of N*d entries");
     if (dev_gather && (!idx_dev || ((uintptr_t)idx_dev & 255u) || idx_count < (uint64_t)n * maxd))

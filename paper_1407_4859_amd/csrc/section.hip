@@ -38,6 +38,34 @@ struct SectionArgs {
   uint32_t degree, n_read, n_write, op;
   SField rd[ADHA_MAX_READ];
   SField wr[ADHA_MAX_WRITE];
+  // stencils: neighbours at grid offsets (x, y, z) instead of idx
+  uint32_t stencil, nx, ny, nz;
+  int32_t off[ADHA_MAX_DEGREE][3];
+  int32_t lin[ADHA_MAX_DEGREE];  // the same offsets as record-index steps
+};
+
+// Neighbour j of record i: from the index array, or for a stencil the
+// record at the grid offset (-1 when outside the grid).
+struct Neighbours {
+  const int32_t *row = nullptr;
+  int32_t x = 0, y = 0, z = 0, i = 0;
+  __device__ __forceinline__ Neighbours(const SectionArgs &a, uint64_t rec) {
+    if (a.stencil) {
+      i = (int32_t)rec;
+      x = i % (int32_t)a.nx;
+      const int32_t t = i / (int32_t)a.nx;
+      y = t % (int32_t)a.ny;
+      z = t / (int32_t)a.ny;
+    } else {
+      row = a.idx + rec * (uint64_t)a.degree;
+    }
+  }
+  __device__ __forceinline__ int32_t get(const SectionArgs &a, int j) const {
+    if (!a.stencil) return row[j];
+    const int32_t xx = x + a.off[j][0], yy = y + a.off[j][1], zz = z + a.off[j][2];
+    const bool in = xx >= 0 && xx < (int32_t)a.nx && yy >= 0 && yy < (int32_t)a.ny && zz >= 0 && zz < (int32_t)a.nz;
+    return in ? i + a.lin[j] : -1;
+  }
 };
 
 __device__ __forceinline__ uint64_t faddr(const SField &F, uint64_t r) {
@@ -178,21 +206,21 @@ __global__ __launch_bounds__(256) void section_kernel(const SectionArgs a) {
     // folded in neighbour order.
     constexpr int NB = MAXR >= 32 ? 1 : 32 / MAXR;
     const int deg = (int)a.degree;
-    const int32_t *row = a.idx + i * (uint64_t)deg;
+    const Neighbours nb(a, i);
     int32_t cur[NB], nxt[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) cur[b] = b < deg ? row[b] : 0;
+    for (int b = 0; b < NB; ++b) cur[b] = b < deg ? nb.get(a, b) : 0;
     bool bad = false;
     for (int j0 = 0; j0 < deg; j0 += NB) {
 #pragma unroll
-      for (int b = 0; b < NB; ++b) nxt[b] = j0 + NB + b < deg ? row[j0 + NB + b] : 0;
+      for (int b = 0; b < NB; ++b) nxt[b] = j0 + NB + b < deg ? nb.get(a, j0 + NB + b) : 0;
       uint64_t t[NB][MAXR];
       bool ok[NB];
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const bool live = j0 + b < deg;
         ok[b] = live && cur[b] >= 0 && (int64_t)cur[b] < a.n;
-        bad |= live && !ok[b];
+        bad |= live && !ok[b] && !a.stencil;   // a stencil neighbour off the grid is no error
 #pragma unroll
         for (int q = 0; q < MAXR; ++q)
           if (q < (int)nr) t[b][q] = ok[b] ? load_term(a.buf, a.rd[q], (uint64_t)cur[b]) : 0;
@@ -304,14 +332,14 @@ __global__ __launch_bounds__(256) void section_span_kernel(const SectionArgs a, 
   Acc acc[2];
   acc[0] = acc[1] = Acc{0.0f, 0.0, 0u};
   const int deg = (int)a.degree;
-  const int32_t *row = a.idx + i * (uint64_t)deg;
+  const Neighbours nb(a, i);
   const uint8_t *gb = a.buf + sp.gbase + sp.lo;
-  int32_t cur = deg > 0 ? row[0] : 0;
+  int32_t cur = deg > 0 ? nb.get(a, 0) : 0;
   bool bad = false;
   for (int j = 0; j < deg; ++j) {
-    const int32_t nxt = j + 1 < deg ? row[j + 1] : 0;
+    const int32_t nxt = j + 1 < deg ? nb.get(a, j + 1) : 0;
     const bool ok = cur >= 0 && (int64_t)cur < a.n;
-    bad |= !ok;
+    bad |= !ok && !a.stencil;
     uint32_t w[MAXW];
     span_load<VEC, MAXW>(gb, sp, cur, ok, w);
     if (ok) span_fold<MAXW, MAXR>(a, sp, w, acc);
@@ -687,6 +715,16 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
   a.op = (uint32_t)sec.op;
   for (size_t q = 0; q < sec.rd.size(); ++q) a.rd[q] = sfield(l, sec.rd[q]);
   for (size_t k = 0; k < sec.wr.size(); ++k) a.wr[k] = sfield(l, sec.wr[k]);
+  if (sec.stencil) {
+    a.stencil = 1;
+    a.nx = sec.nx;
+    a.ny = sec.ny;
+    a.nz = sec.nz;
+    for (uint32_t j = 0; j < sec.degree; ++j) {
+      for (int c = 0; c < 3; ++c) a.off[j][c] = sec.offsets[3 * j + c];
+      a.lin[j] = a.off[j][0] + (int32_t)sec.nx * (a.off[j][1] + (int32_t)sec.ny * a.off[j][2]);
+    }
+  }
   const dim3 grid((uint32_t)((n + 255) / 256));
   const uint32_t nr = a.n_read;
   switch (sec.op) {

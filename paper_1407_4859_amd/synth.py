@@ -284,6 +284,25 @@ def kmeans_sections():
             (list(range(KMEANS_FEATURES)), KMEANS_KEY, KMEANS_K))
 
 
+STENCIL7 = [(0, 0, 0), (-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)]
+
+
+def medical_struct(side: int = 256) -> StructSpec:
+    """Medical-shaped workload: a side^3 image of 9 f32 fields (V1 V2 V3 U1
+    U2 U3 S T interpT, ids 0-8)."""
+    return StructSpec(side ** 3, [F32] * 9, [4] * 9)
+
+
+def medical_sections():
+    """Four loops: (read, write, stencil offsets or None for a direct loop).
+    Two 7-point stencils (over U into V1, over V into U1) and two direct
+    updates."""
+    return [([3, 4, 5], [0], STENCIL7),
+            ([0, 6, 7], [8], None),
+            ([0, 1, 2], [3], STENCIL7),
+            ([3, 4, 5, 8], [1, 2], None)]
+
+
 def config4_arrays(seed: int = 4, n_arrays: int = 512, lo_log2: int = 10, hi_log2: int = 22):
     """Batched-remap workload: per array (n, elem_bytes[], target partition, tiles).
 
