@@ -16,6 +16,8 @@ Besides the timed steps the run reports (outside the timed region):
   kmeans        the K-Means-shaped program (2^23 points, a direct loop and a
                 per-cluster reduction of 32 features): planned vs all-AoS and
                 all-SoA, per-section GB/s;
+  medical       the Medical-shaped stencil program (256^3 image, 9 fields):
+                planned vs all-AoS and all-SoA, per-section GB/s;
   flow          the multi-section workload with branches: expected time of
                 the branch-aware plan vs a plan ignoring branches, all-AoS and
                 all-SoA;
@@ -80,6 +82,8 @@ def parse():
     ap.add_argument("--skip-kmeans", action="store_true")
     ap.add_argument("--skip-hetero", action="store_true")
     ap.add_argument("--skip-flow", action="store_true")
+    ap.add_argument("--skip-medical", action="store_true")
+    ap.add_argument("--only-medical", action="store_true", help="the Medical-shaped stencil leg only")
     ap.add_argument("--only-flow", action="store_true", help="the branching-program leg only")
     ap.add_argument("--only-hetero", action="store_true", help="the GPU + host planning leg only")
     ap.add_argument("--only-kmeans", action="store_true", help="the K-Means-shaped leg only (for profiling)")
@@ -294,6 +298,49 @@ def kmeans_bench(A, synth, torch, timer, log2n=23):
     return res
 
 
+def medical_bench(A, synth, torch, timer, side=256):
+    """The Medical-shaped program on a side^3 image of 9 f32 fields: two
+    7-point stencils and two direct loops, planned with measured costs and
+    compared with all-AoS and all-SoA; per-section times and GB/s."""
+    spec = synth.medical_struct(side)
+    n = spec.n
+    st = A.Struct.from_spec(spec)
+    grid = (side, side, side)
+    ss = []
+    for rd, wr, offs in synth.medical_sections():
+        ss.append(A.Section.stencil(st, rd, wr, grid, offs) if offs else A.Section(st, A.OP_GEN, rd, wr, 0))
+    prog = A.Program(st, ss)
+    aos_l, soa_l = A.Layout.aos(st), A.Layout.soa(st)
+    cap = max(aos_l.nbytes, soa_l.nbytes) + (1 << 24)
+    buf_a = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    buf_b = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    fill_fields(buf_a, spec, 13, torch, synth)
+    ctx = A.Ctx(0)
+    t0 = time.perf_counter()
+    plan = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_MEASURED, catalogue=A.CAT_FULL, cap_bytes=64, reps=3))
+    plan_s = time.perf_counter() - t0
+    res = {"workload": f"{side}^3 image, 9 f32 fields (36 B); 7-point stencil U->V1, direct V1,S,T->interpT, "
+                       f"7-point stencil V->U1, direct U,interpT->V2,V3",
+           "candidates": plan.n_candidates, "plan_seconds": round(plan_s, 2)}
+    for name, pl in (("adha", plan), ("all_aos", A.Plan.uniform(prog, aos_l)), ("all_soa", A.Plan.uniform(prog, soa_l))):
+        first = pl.candidate(pl.choices()[0])
+        ms, _ = timer.time(lambda: A.run(ctx, pl, first, buf_a, buf_b), reps=5, warm=1)
+        res[name + "_ms"] = round(ms, 3)
+        res[name + "_choices"] = pl.choices()
+    ctx.check()
+    res["speedup_vs_best_uniform"] = round(min(res["all_aos_ms"], res["all_soa_ms"]) / res["adha_ms"], 3)
+    per = []
+    for s, (sec, c) in enumerate(zip(ss, plan.choices())):
+        for lname, lay in (("planned", plan.candidate(c)), ("aos", aos_l), ("soa", soa_l)):
+            ms, _ = timer.time(lambda: A.section_run(ctx, sec, lay, buf_a), reps=7, warm=1)
+            per.append({"section": s, "stencil": sec.degree > 0, "layout": lname, "us": round(ms * 1e3, 1),
+                        "alg_GBps": round(sec.bytes / (ms * 1e6), 1),
+                        "eff_GBps": round(sec.effective_bytes(lay) / (ms * 1e6), 1)})
+    ctx.check()
+    res["sections"] = per
+    return res
+
+
 FLOW_TOKENS = [0, 1, -1, 2, 3, -2, 4, -3, 5, -1, 6, -3, 7]   # IF = -1, ELSE = -2, END = -3
 FLOW_PROBS = [0.6, 0.3]
 
@@ -503,6 +550,9 @@ def main():
     if args.only_learned:
         print(json.dumps({"learned": learned_bench(A, synth, torch, args)}), flush=True)
         return
+    if args.only_medical:
+        print(json.dumps({"medical": medical_bench(A, synth, torch, timer)}), flush=True)
+        return
     if args.only_flow:
         print(json.dumps({"flow": flow_bench(A, synth, torch, timer, args.program_log2n)}), flush=True)
         return
@@ -611,6 +661,12 @@ def main():
                 line["kmeans"] = kmeans_bench(A, synth, torch, timer)
             except Exception as e:
                 line["kmeans"] = {"error": repr(e)}
+            torch.cuda.empty_cache()
+        if not args.skip_medical:
+            try:
+                line["medical"] = medical_bench(A, synth, torch, timer)
+            except Exception as e:
+                line["medical"] = {"error": repr(e)}
             torch.cuda.empty_cache()
         if not args.skip_flow:
             try:
