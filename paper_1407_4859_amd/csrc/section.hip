@@ -244,6 +244,50 @@ __global__ __launch_bounds__(256) void section_kernel(const SectionArgs a) {
   if (nw > 1) store_acc(a.buf, a.wr[1], i, acc[1]);
 }
 
+// Stencil sections: the neighbours are the record's grid neighbourhood, so
+// consecutive lanes read consecutive records at every offset and most loads
+// hit lines other lanes or offsets just brought in.  Here all the loads of
+// a batch of neighbours are issued together (no index array, no arithmetic
+// between the loads); an off-grid neighbour loads the record itself and is
+// dropped.  Terms are folded in neighbour order.
+template <int MAXR, bool W8>
+__global__ __launch_bounds__(256) void stencil_kernel(const SectionArgs a) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  if (i >= (uint64_t)a.n) return;
+  const uint32_t nr = a.n_read, nw = a.n_write;
+  Acc acc[2];
+  acc[0] = acc[1] = Acc{0.0f, 0.0, 0u};
+  constexpr int NB = MAXR >= 32 ? 1 : 32 / MAXR;
+  const int deg = (int)a.degree;
+  const Neighbours nb(a, i);
+  for (int j0 = 0; j0 < deg; j0 += NB) {
+    Words<MAXR, W8> w[NB];
+    bool ok[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int32_t r = j0 + b < deg ? nb.get(a, j0 + b) : -1;
+      ok[b] = r >= 0;
+      const uint64_t rr = ok[b] ? (uint64_t)r : i;
+#pragma unroll
+      for (int q = 0; q < MAXR; ++q)
+        if (q < (int)nr) w[b].load(q, a.buf, a.rd[q], rr);
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+      if (ok[b]) {
+#pragma unroll
+        for (int q = 0; q < MAXR; ++q)
+          if (q < (int)nr) {
+            const uint64_t t = w[b].term(q, a.rd[q]);
+            fold(acc[0], 0, a.wr[0].dt, a.rd[q].dt, t);
+            if (nw > 1) fold(acc[1], 1, a.wr[1].dt, a.rd[q].dt, t);
+          }
+      }
+  }
+  store_acc(a.buf, a.wr[0], i, acc[0]);
+  if (nw > 1) store_acc(a.buf, a.wr[1], i, acc[1]);
+}
+
 // Gather whose read fields all sit in one interleaved group: per neighbour
 // the span of the group record that holds them is fetched with VEC-byte
 // vector loads (VEC divides the record size, so every load is aligned) into
@@ -399,6 +443,14 @@ static SField sfield(const LayoutDesc &l, int f) {
   s.e = l.shape.ebytes[f];
   s.dt = (uint32_t)l.shape.dtype[f];
   return s;
+}
+
+template <bool W8>
+static void launch_stencil(uint32_t nr, dim3 grid, const SectionArgs &a, hipStream_t st) {
+  if (nr <= 4) hipLaunchKernelGGL((stencil_kernel<4, W8>), grid, dim3(256), 0, st, a);
+  else if (nr <= 8) hipLaunchKernelGGL((stencil_kernel<8, W8>), grid, dim3(256), 0, st, a);
+  else if (nr <= 16) hipLaunchKernelGGL((stencil_kernel<16, W8>), grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((stencil_kernel<32, W8>), grid, dim3(256), 0, st, a);
 }
 
 template <int OP, int DG, bool W8>
@@ -729,6 +781,13 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
   const uint32_t nr = a.n_read;
   switch (sec.op) {
     case ADHA_OP_GEN: {
+      if (sec.stencil) {
+        bool w8 = false;
+        for (uint32_t q = 0; q < nr; ++q) w8 |= a.rd[q].e == 8;
+        if (w8) launch_stencil<true>(nr, grid, a, stream);
+        else launch_stencil<false>(nr, grid, a, stream);
+        break;
+      }
       SpanArgs sp{};
       uint32_t vec = 0;
       if (sec.degree > 0 && !ctx->no_span && span_plan(sec, l, &sp, &vec)) {
