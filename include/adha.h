@@ -227,6 +227,7 @@ typedef struct {
   uint64_t descriptor_bytes;  /* size of the launch's descriptor blob */
   uint64_t grid;              /* workgroups of the main kernel */
   uint32_t lds_bytes;         /* LDS per workgroup of the main kernel */
+  uint32_t byte_path;         /* 1: main kernel assembles dwords from bytes (1- or 2-byte fields) */
 } adha_remap_info;
 adha_status adha_remap_describe(const adha_layout *src_l, const adha_layout *dst_l, int32_t cu_count,
                                 adha_remap_info *out);

@@ -52,7 +52,8 @@ class RemapItem(ctypes.Structure):
 
 class RemapInfo(ctypes.Structure):
     _fields_ = [("shape", TileShape), ("full_tiles", ctypes.c_uint64), ("tail_bytes", ctypes.c_uint64),
-                ("descriptor_bytes", ctypes.c_uint64), ("grid", ctypes.c_uint64), ("lds_bytes", ctypes.c_uint32)]
+                ("descriptor_bytes", ctypes.c_uint64), ("grid", ctypes.c_uint64), ("lds_bytes", ctypes.c_uint32),
+                ("byte_path", ctypes.c_uint32)]
 
 
 class PlanOpts(ctypes.Structure):

@@ -368,7 +368,6 @@ adha_status adha_remap_set_shape(adha_ctx *ctx, const adha_layout *src_l, const 
   s.strided = shape->order ? shape->order - 1 : d.strided;
   s.nt = shape->nontemporal ? shape->nontemporal - 1 : d.nt;
   if (s.R != 0) {
-    if (!src_l->d.dword_fields()) return fail(ADHA_ERR_UNSUPPORTED, "1- and 2-byte fields use the tail path only");
     ADHA_TRY(check_shape(src_l->d, dst_l->d, s));
   }
   ctx->c.forced_shapes[{src_l->id, dst_l->id}] = s;
@@ -411,6 +410,7 @@ adha_status adha_remap_describe(const adha_layout *src_l, const adha_layout *dst
   out->descriptor_bytes = p.desc_bytes;
   out->grid = p.grid;
   out->lds_bytes = p.lds;
+  out->byte_path = p.byte_path;
   return ADHA_OK;
 }
 

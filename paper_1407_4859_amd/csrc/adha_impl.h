@@ -152,6 +152,7 @@ struct RemapPrepared {
   uint64_t main_tiles = 0, tiles_per_wg = 0, grid = 0, tail_blocks = 0;
   uint32_t n_arrays = 0, n_main = 0, n_tails = 0;
   uint32_t K = 1, shift = 6, wg_per_cu = 1, lds = 0, strided = 0, nt = 0;
+  uint32_t byte_path = 0;  // some array has 1- or 2-byte fields: main kernel in byte mode
   uint64_t desc_bytes = 0, tail_bytes = 0;
 };
 // Builds the descriptor blob of a launch; with upload it is copied into a

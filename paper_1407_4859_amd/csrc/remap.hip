@@ -24,11 +24,18 @@
 // stores only.  The next tile's loads are issued before the current tile's
 // stores (software pipelining).
 //
+// Byte mode.  With 1- or 2-byte fields a destination dword can hold bytes of
+// up to four different (record, field) elements, so step 2 assembles each
+// destination dword from four LDS bytes instead of one LDS dword.  Each
+// thread keeps the sixteen LDS byte positions of each of its chunks packed
+// two to a register (LDS addresses fit in 16 bits); the loads, the LDS
+// image of the source runs and the 16-byte stores are those of the dword
+// mode.
+//
 // Tail kernel.  Records past the last full tile, the padding records of
 // tiled groups and the gaps between groups are written by a simple
-// per-dword kernel that decodes each destination byte on its own (it also
-// serves layouts with 1- or 2-byte fields, whose bytes do not fall on
-// dword boundaries).
+// per-dword kernel that decodes each destination byte on its own (through
+// a per-byte field table when fields are narrower than a dword).
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -46,6 +53,7 @@ struct RGroup {
   uint32_t logT;
   uint32_t tile_off;  // byte offset of the group's R-record run in the tile image
   uint32_t word_off;  // first entry of this group in word_field
+  uint32_t byte_off;  // first entry of this group in byte_field
 };
 
 struct RField {
@@ -69,6 +77,7 @@ struct RArray {
   const RGroup *dgrp;
   const RField *fld;
   const uint8_t *word_field;  // per destination group, the field of each record dword
+  const uint8_t *byte_field;  // per destination group, the field of each record byte
 };
 
 struct RTail {
@@ -97,11 +106,12 @@ __device__ __forceinline__ void store16(uint8_t *p, u32x4 v) {
   else *q = v;
 }
 
-// K: 16-byte slots per thread; NT: streaming (non-temporal) global accesses.
+// K: 16-byte slots per thread; NT: streaming (non-temporal) global accesses;
+// BY: byte mode (destination dwords assembled from LDS bytes).
 // Workgroup w takes tiles w*tiles_per_wg .. +tiles_per_wg (contiguous) or,
 // when `strided`, tiles w, w + G, w + 2G, ... so that at any moment the
 // grid works on neighbouring tiles.
-template <int K, bool NT>
+template <int K, bool NT, bool BY>
 __global__ __launch_bounds__(kBlock) void remap_tiles_kernel(const RArray *__restrict__ arrays,
                                                              uint32_t n_arrays, uint64_t total_tiles,
                                                              uint64_t tiles_per_wg, uint32_t shift,
@@ -136,9 +146,10 @@ __global__ __launch_bounds__(kBlock) void remap_tiles_kernel(const RArray *__res
     const uint64_t stop = min(g_end, A.tile_begin + A.n_full);
     const uint32_t nsg = A.nsg, ndg = A.ndg;
 
+    constexpr int P = BY ? 8 : 4;  // position registers per slot
     uint64_t ld_off[K], st_off[K];
     uint32_t ld_S[K], st_S[K], ld_pos[K];
-    uint32_t st_pos[K][4];
+    uint32_t st_pos[K][P];
     bool act[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -146,7 +157,8 @@ __global__ __launch_bounds__(kBlock) void remap_tiles_kernel(const RArray *__res
       act[k] = c < A.n_chunks;
       ld_off[k] = st_off[k] = 0;
       ld_S[k] = st_S[k] = ld_pos[k] = 0;
-      st_pos[k][0] = st_pos[k][1] = st_pos[k][2] = st_pos[k][3] = 0;
+#pragma unroll
+      for (int q = 0; q < P; ++q) st_pos[k][q] = 0;
       if (!act[k]) continue;
       const uint32_t o = 16u * c;
       uint32_t gs = 0;
@@ -162,6 +174,29 @@ __global__ __launch_bounds__(kBlock) void remap_tiles_kernel(const RArray *__res
       const RGroup D = A.dgrp[gd];
       st_off[k] = D.base + (o - D.tile_off);
       st_S[k] = D.S;
+      if constexpr (BY) {
+        // LDS byte address of each of the chunk's 16 destination bytes
+        const uint32_t Td = 1u << D.logT, tileB = Td * D.S;
+#pragma unroll
+        for (uint32_t j = 0; j < 16; ++j) {
+          const uint32_t ob = o - D.tile_off + j;
+          const uint32_t qq = ob / tileB;
+          const uint32_t within = ob - qq * tileB;
+          const RField F = A.fld[A.byte_field[D.byte_off + (within >> D.logT)]];
+          const uint32_t local = within - F.dp * Td;
+          const uint32_t rin = local / F.e;
+          const uint32_t eb = local - rin * F.e;
+          const uint32_t rec = qq * Td + rin;
+          const RGroup Sg = A.sgrp[F.sg];
+          const uint32_t Ts = 1u << Sg.logT;
+          const uint32_t pos = Sg.tile_off + (rec >> Sg.logT) * Ts * Sg.S + F.sp * Ts +
+                               (rec & (Ts - 1)) * F.e + eb;
+          const uint32_t w = pos >> 2;
+          const uint32_t lb = 4u * (w + (w >> shift)) + (pos & 3u);
+          st_pos[k][j >> 1] |= lb << (16u * (j & 1u));
+        }
+        continue;
+      }
       const uint32_t Td = 1u << D.logT, Swd = D.S >> 2, tileW = Td * Swd;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -215,10 +250,25 @@ __global__ __launch_bounds__(kBlock) void remap_tiles_kernel(const RArray *__res
       for (int k = 0; k < K; ++k)
         if (act[k]) {
           u32x4 o;
-          o.x = lds[st_pos[k][0]];
-          o.y = lds[st_pos[k][1]];
-          o.z = lds[st_pos[k][2]];
-          o.w = lds[st_pos[k][3]];
+          if constexpr (BY) {
+            const uint8_t *lb = reinterpret_cast<const uint8_t *>(lds);
+            uint32_t wv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const uint32_t p0 = st_pos[k][2 * q], p1 = st_pos[k][2 * q + 1];
+              wv[q] = (uint32_t)lb[p0 & 0xffffu] | ((uint32_t)lb[p0 >> 16] << 8) |
+                      ((uint32_t)lb[p1 & 0xffffu] << 16) | ((uint32_t)lb[p1 >> 16] << 24);
+            }
+            o.x = wv[0];
+            o.y = wv[1];
+            o.z = wv[2];
+            o.w = wv[3];
+          } else {
+            o.x = lds[st_pos[k][0]];
+            o.y = lds[st_pos[k][1]];
+            o.z = lds[st_pos[k][2]];
+            o.w = lds[st_pos[k][3]];
+          }
           store16<NT>(dst + st_off[k] + cur * st_S[k], o);
         }
       __syncthreads();
@@ -272,12 +322,7 @@ __global__ __launch_bounds__(kBlock) void remap_tail_kernel(const RArray *__rest
         const uint64_t q = byte / tileB;
         const uint64_t within = byte - q * tileB;
         const uint32_t col = (uint32_t)(within >> D.logT);
-        uint32_t fsel = 0;
-        for (uint32_t f = 0; f < A.nf; ++f) {
-          const RField &F = A.fld[f];
-          if (F.dg == Rg.dgroup && F.dp <= col && col < F.dp + F.e) fsel = f;
-        }
-        const RField &F = A.fld[fsel];
+        const RField &F = A.fld[A.byte_field[D.byte_off + col]];
         const uint64_t local = within - ((uint64_t)F.dp << D.logT);
         const uint64_t rec = q * T + local / F.e;
         const uint64_t eb = local % F.e;
@@ -329,7 +374,7 @@ adha_status policy_shape(const LayoutDesc &a, const LayoutDesc &b, uint32_t tile
   const uint64_t need = std::max<uint64_t>(tile_bytes, (uint64_t)Rmin * S);
   s.K = 1;
   while (s.K < 8 && (uint64_t)kBlock * 16 * s.K < need) s.K *= 2;
-  if (!a.dword_fields() || S == 0 || (uint64_t)kBlock * 16 * s.K < (uint64_t)Rmin * S) {
+  if (S == 0 || (uint64_t)kBlock * 16 * s.K < (uint64_t)Rmin * S) {
     s.R = 0;
   } else {
     s.R = (uint32_t)(std::min<uint64_t>((uint64_t)kBlock * 16 * s.K, std::max<uint64_t>(tile_bytes, (uint64_t)Rmin * S)) /
@@ -357,7 +402,7 @@ std::string tune_key(const LayoutDesc &a, const LayoutDesc &b) {
 // otherwise 16 KiB tiles (at least max(64, T) records), 4 workgroups per CU,
 // strided tile order and streaming accesses, the best setting measured for
 // 64-byte records.  R = 0 means "no full tiles": the tail kernel does
-// everything (1- and 2-byte fields, or records too large for one tile).
+// everything (records too large for one tile).
 adha_status choose_shape(const Ctx *ctx, const LayoutDesc &a, const LayoutDesc &b, TileShape *out) {
   if (ctx && !ctx->tunedb.empty()) {
     auto it = ctx->tunedb.find(tune_key(a, b));
@@ -382,7 +427,8 @@ struct BlobBuilder {
 };
 
 static void groups_of(const LayoutDesc &L, uint32_t R, std::vector<RGroup> &out,
-                      std::vector<uint8_t> *words, const std::vector<RField> *fl) {
+                      std::vector<uint8_t> *words, std::vector<uint8_t> *bytes,
+                      const std::vector<RField> *fl) {
   uint32_t tile_off = 0;
   for (size_t gi = 0; gi < L.groups.size(); ++gi) {
     const Group &g = L.groups[gi];
@@ -403,6 +449,15 @@ static void groups_of(const LayoutDesc &L, uint32_t R, std::vector<RGroup> &out,
         words->push_back(fsel);
       }
     }
+    if (bytes) {
+      r.byte_off = (uint32_t)bytes->size();
+      for (uint32_t b = 0; b < g.S; ++b) {
+        uint8_t fsel = 0;
+        for (int f : g.fields)
+          if ((*fl)[f].dp <= b && b < (*fl)[f].dp + (*fl)[f].e) fsel = (uint8_t)f;
+        bytes->push_back(fsel);
+      }
+    }
     out.push_back(r);
   }
 }
@@ -417,7 +472,7 @@ adha_status remap_prepare(Ctx *ctx, const std::vector<const LayoutDesc *> &src_l
   // offsets are known; device pointers are patched in after allocation.
   struct Pending {
     RArray arr;
-    size_t sg_at, dg_at, fl_at, wf_at;
+    size_t sg_at, dg_at, fl_at, wf_at, bf_at;
   };
   std::vector<Pending> pend(na);
   BlobBuilder blob;
@@ -439,9 +494,9 @@ adha_status remap_prepare(Ctx *ctx, const std::vector<const LayoutDesc *> &src_l
     }
     const uint32_t R = sh.R;
     std::vector<RGroup> sg, dg;
-    std::vector<uint8_t> words;
-    groups_of(A, R, sg, nullptr, nullptr);
-    groups_of(B, R, dg, B.dword_fields() ? &words : nullptr, &fl);
+    std::vector<uint8_t> words, bytes;
+    groups_of(A, R, sg, nullptr, nullptr, nullptr);
+    groups_of(B, R, dg, B.dword_fields() ? &words : nullptr, &bytes, &fl);
     Pending &Q = pend[i];
     memset(&Q.arr, 0, sizeof Q.arr);
     Q.arr.n = A.shape.n;
@@ -456,7 +511,9 @@ adha_status remap_prepare(Ctx *ctx, const std::vector<const LayoutDesc *> &src_l
     Q.dg_at = blob.add(dg.data(), dg.size() * sizeof(RGroup));
     Q.fl_at = blob.add(fl.data(), fl.size() * sizeof(RField));
     Q.wf_at = blob.add(words.data(), words.size(), 4);
+    Q.bf_at = blob.add(bytes.data(), bytes.size(), 4);
     if (Q.arr.n_full > 0) {
+      if (!Q.arr.dword) P.byte_path = 1;
       Q.arr.tile_begin = P.main_tiles;
       P.main_tiles += Q.arr.n_full;
       main_list.push_back((uint32_t)i);
@@ -514,6 +571,7 @@ adha_status remap_prepare(Ctx *ctx, const std::vector<const LayoutDesc *> &src_l
     Q.arr.dgrp = (const RGroup *)(dev + Q.dg_at);
     Q.arr.fld = (const RField *)(dev + Q.fl_at);
     Q.arr.word_field = dev + Q.wf_at;
+    Q.arr.byte_field = dev + Q.bf_at;
     memcpy(blob.bytes.data() + arr_at + i * sizeof(RArray), &Q.arr, sizeof(RArray));
   }
   for (size_t j = 0; j < main_list.size(); ++j)
@@ -540,24 +598,22 @@ adha_status remap_run(Ctx *ctx, const RemapPrepared &P, const void *src_override
     const RArray *arrs = (const RArray *)P.main_arrays;
     const dim3 grid((uint32_t)P.grid), block(kBlock);
     const uint32_t sd = P.strided;
-#define ADHA_REMAP_LAUNCH(KK, NTT)                                                                  \
-  hipLaunchKernelGGL((remap_tiles_kernel<KK, NTT>), grid, block, P.lds, stream, arrs, P.n_main,     \
+#define ADHA_REMAP_LAUNCH(KK, NTT, BYY)                                                             \
+  hipLaunchKernelGGL((remap_tiles_kernel<KK, NTT, BYY>), grid, block, P.lds, stream, arrs, P.n_main, \
                      P.main_tiles, P.tiles_per_wg, P.shift, sd, so, dov)
-    if (P.nt) {
-      switch (P.K) {
-        case 1: ADHA_REMAP_LAUNCH(1, true); break;
-        case 2: ADHA_REMAP_LAUNCH(2, true); break;
-        case 4: ADHA_REMAP_LAUNCH(4, true); break;
-        default: ADHA_REMAP_LAUNCH(8, true); break;
-      }
+#define ADHA_REMAP_K(NTT, BYY)                   \
+  switch (P.K) {                                 \
+    case 1: ADHA_REMAP_LAUNCH(1, NTT, BYY); break; \
+    case 2: ADHA_REMAP_LAUNCH(2, NTT, BYY); break; \
+    case 4: ADHA_REMAP_LAUNCH(4, NTT, BYY); break; \
+    default: ADHA_REMAP_LAUNCH(8, NTT, BYY); break; \
+  }
+    if (P.byte_path) {
+      if (P.nt) ADHA_REMAP_K(true, true) else ADHA_REMAP_K(false, true)
     } else {
-      switch (P.K) {
-        case 1: ADHA_REMAP_LAUNCH(1, false); break;
-        case 2: ADHA_REMAP_LAUNCH(2, false); break;
-        case 4: ADHA_REMAP_LAUNCH(4, false); break;
-        default: ADHA_REMAP_LAUNCH(8, false); break;
-      }
+      if (P.nt) ADHA_REMAP_K(true, false) else ADHA_REMAP_K(false, false)
     }
+#undef ADHA_REMAP_K
 #undef ADHA_REMAP_LAUNCH
     ADHA_HIP(hipGetLastError());
   }

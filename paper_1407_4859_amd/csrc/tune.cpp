@@ -69,7 +69,6 @@ adha_status adha_tune_remap(adha_ctx *ctx, const adha_layout *src_l, const void 
   if (!ctx || !best || !best_us || !default_us) return fail(ADHA_ERR_INVALID, "NULL argument");
   ADHA_TRY(validate_remap(src_l, src, src_cap, dst_l, dst, dst_cap));
   if (src_l->d.shape.n == 0) return fail(ADHA_ERR_INVALID, "nothing to tune on an empty struct");
-  if (!src_l->d.dword_fields()) return fail(ADHA_ERR_UNSUPPORTED, "1- and 2-byte fields use the tail path only");
   DeviceGuard g(ctx->c.device);
   Ctx *c = &ctx->c;
   hipStream_t st = (hipStream_t)stream;
