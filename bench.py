@@ -21,6 +21,8 @@ Besides the timed steps the run reports (outside the timed region):
   flow          the multi-section workload with branches: expected time of
                 the branch-aware plan vs a plan ignoring branches, all-AoS and
                 all-SoA;
+  subdword      remaps of structs with 1- and 2-byte fields (2^25 records,
+                AoS <-> SoA, default shapes);
   hetero        plans over the GPU and the host (plain small program, data
                 starting on the host, N = 2^10 .. 2^20): planned devices and
                 run time vs all-GPU and all-host;
@@ -83,6 +85,7 @@ def parse():
     ap.add_argument("--skip-hetero", action="store_true")
     ap.add_argument("--skip-flow", action="store_true")
     ap.add_argument("--skip-medical", action="store_true")
+    ap.add_argument("--skip-subdword", action="store_true")
     ap.add_argument("--only-medical", action="store_true", help="the Medical-shaped stencil leg only")
     ap.add_argument("--only-flow", action="store_true", help="the branching-program leg only")
     ap.add_argument("--only-hetero", action="store_true", help="the GPU + host planning leg only")
@@ -476,6 +479,31 @@ def batched_bench(A, synth, torch, timer):
             "graph_frac_of_peak": round(total / g_ms / 1e6 / HBM_PEAK_GBS, 3)}
 
 
+def subdword_bench(A, torch, timer, log2n=25):
+    """Remaps of structs with 1- and 2-byte fields (the tile kernel's byte
+    mode), default tile shapes, AoS <-> SoA."""
+    n = 1 << log2n
+    out = {"workload": "N=2^%d records; AoS->SoA and SoA->AoS with default shapes" % log2n}
+    ctx = A.Ctx(0)
+    for name, eb in (("8x1B+4x2B+4x4B", [1] * 8 + [2] * 4 + [4] * 4), ("8x2B+8x4B", [2] * 8 + [4] * 8),
+                     ("24x1B", [1] * 24)):
+        st = A.Struct(n, [A.RAW] * len(eb), eb)
+        La, Ls = A.Layout.aos(st), A.Layout.soa(st)
+        a = torch.empty(La.nbytes, dtype=torch.uint8, device="cuda").random_(0, 256)
+        b = torch.empty(Ls.nbytes, dtype=torch.uint8, device="cuda")
+        moved = 2 * n * sum(eb)
+        row = {"record_bytes": sum(eb), "shape": A.get_shape(ctx, La, Ls)}
+        for d, fn in (("aos_to_soa", lambda: A.remap(ctx, La, a, Ls, b)),
+                      ("soa_to_aos", lambda: A.remap(ctx, Ls, b, La, a))):
+            ms, _ = timer.time(fn, reps=7, warm=1)
+            row[d] = {"ms": round(ms, 4), "GBps": round(moved / ms / 1e6, 1),
+                      "frac": round(moved / ms / 1e6 / HBM_PEAK_GBS, 4)}
+        out[name] = row
+        del a, b
+    ctx.check()
+    return out
+
+
 def path_cost(T, R, path):
     """Cost of a layout choice per section under tables T (k x C) and R (C x C)."""
     c = T[0][path[0]]
@@ -679,6 +707,12 @@ def main():
                 line["hetero"] = hetero_bench(A, synth, torch)
             except Exception as e:
                 line["hetero"] = {"error": repr(e)}
+            torch.cuda.empty_cache()
+        if not args.skip_subdword:
+            try:
+                line["subdword"] = subdword_bench(A, torch, timer)
+            except Exception as e:
+                line["subdword"] = {"error": repr(e)}
             torch.cuda.empty_cache()
         if not args.skip_batched:
             try:

@@ -171,6 +171,7 @@ adha_status choose_shape(const Ctx *ctx, const LayoutDesc &a, const LayoutDesc &
 adha_status policy_shape(const LayoutDesc &a, const LayoutDesc &b, uint32_t tile_bytes, uint32_t wg_per_cu,
                          uint32_t strided, uint32_t nt, TileShape *out);
 std::string tune_key(const LayoutDesc &a, const LayoutDesc &b);
+uint32_t default_tile_bytes(const LayoutDesc &a);
 adha_status check_shape(const LayoutDesc &a, const LayoutDesc &b, const TileShape &s);
 uint32_t remap_lds_bytes(const LayoutDesc &a, const TileShape &s);
 

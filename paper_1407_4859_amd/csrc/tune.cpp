@@ -74,7 +74,7 @@ adha_status adha_tune_remap(adha_ctx *ctx, const adha_layout *src_l, const void 
   hipStream_t st = (hipStream_t)stream;
   reps = std::max<uint32_t>(1, reps);
   TileShape def;
-  ADHA_TRY(policy_shape(src_l->d, dst_l->d, 16384, 4, 1, 1, &def));
+  ADHA_TRY(policy_shape(src_l->d, dst_l->d, default_tile_bytes(src_l->d), 4, 1, 1, &def));
   if (def.R == 0) return fail(ADHA_ERR_UNSUPPORTED, "records too large for a tiled remap");
   double t_def = 0;
   ADHA_TRY(median_us(st, reps, [&] { return remap_with_shape(c, src_l, src, dst_l, dst, def, st); }, &t_def));
