@@ -13,6 +13,7 @@
 // order the section's definition fixes, and every floating-point step uses
 // the explicitly rounded intrinsics so that no multiply-add is fused.
 #include <algorithm>
+#include <cstdlib>
 
 #include "adha_impl.h"
 
@@ -83,6 +84,11 @@ struct Words {
   uint32_t hi[W8 ? N : 1];
   __device__ __forceinline__ void load(int q, const uint8_t *buf, const SField &F, uint64_t r) {
     const uint32_t *p = reinterpret_cast<const uint32_t *>(buf + faddr(F, r));
+    lo[q] = p[0];
+    if constexpr (W8) hi[q] = p[F.e >> 3];
+  }
+  __device__ __forceinline__ void load_at(int q, const uint8_t *at, const SField &F) {
+    const uint32_t *p = reinterpret_cast<const uint32_t *>(at);
     lo[q] = p[0];
     if constexpr (W8) hi[q] = p[F.e >> 3];
   }
@@ -244,48 +250,117 @@ __global__ __launch_bounds__(256) void section_kernel(const SectionArgs a) {
   if (nw > 1) store_acc(a.buf, a.wr[1], i, acc[1]);
 }
 
+// Workgroups go to the chip's 8 XCDs round-robin (workgroup b to XCD b mod
+// 8), and each XCD has an L2 of its own.  Block xcd_block(b, G) gives XCD x
+// one contiguous range of the G blocks, so that the records a neighbour at a
+// grid offset needs were brought into that XCD's L2 by its own recent
+// blocks.  A bijection of [0, G) for any G.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) {
+  const uint32_t x = b & 7u, q = G >> 3, r = G & 7u;
+  return x * q + min(x, r) + (b >> 3);
+}
+
 // Stencil sections: the neighbours are the record's grid neighbourhood, so
 // consecutive lanes read consecutive records at every offset and most loads
 // hit lines other lanes or offsets just brought in.  Here all the loads of
 // a batch of neighbours are issued together (no index array, no arithmetic
 // between the loads); an off-grid neighbour loads the record itself and is
 // dropped.  Terms are folded in neighbour order.
-template <int MAXR, bool W8>
+//
+// A stencil makes many terms per byte it streams, so the per-term work is
+// what bounds it rather than HBM:
+//  * LIN: every read field sits in a group with T = 1, where a field's
+//    address is linear in the record index (base + r*S + p), so a
+//    neighbour's field is the record's own field offset plus the offset's
+//    record step times S, a workgroup-uniform number.  The launch takes this
+//    form only when the layout fits in 4 GiB and every such step in 31 bits,
+//    so offsets are 32-bit and one neighbour's field costs a select and an
+//    add;
+//  * F32: every read and write field is F32 (W8 is then false), and the
+//    fold is straight-line code: an off-grid neighbour's term is computed
+//    and not selected, instead of branching on the field types per term
+//    (the generic fold spends tens of scalar instructions per term on them);
+//  * EXACT: the section reads exactly MAXR fields, so no load is guarded.
+// The load phase has no branches: a neighbour past the degree or off the
+// grid loads the record's own fields and is not selected, and the grid test
+// uses no short-circuit operators, so all loads of a batch stay in flight.
+template <int MAXR, bool W8, bool LIN, bool F32, bool EXACT>
 __global__ __launch_bounds__(256) void stencil_kernel(const SectionArgs a) {
-  const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  const uint64_t i = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
   if (i >= (uint64_t)a.n) return;
-  const uint32_t nr = a.n_read, nw = a.n_write;
+  const uint32_t nr = EXACT ? (uint32_t)MAXR : a.n_read, nw = a.n_write;
   Acc acc[2];
   acc[0] = acc[1] = Acc{0.0f, 0.0, 0u};
-  constexpr int NB = MAXR >= 32 ? 1 : 32 / MAXR;
+  constexpr int NB = MAXR >= 32 ? 1 : (MAXR <= 4 ? 8 : 32 / MAXR);
   const int deg = (int)a.degree;
-  const Neighbours nb(a, i);
+  // grid coordinates of record i
+  const int32_t ii = (int32_t)i;
+  const int32_t x = ii % (int32_t)a.nx, t = ii / (int32_t)a.nx;
+  const int32_t y = t % (int32_t)a.ny, z = t / (int32_t)a.ny;
+  uint32_t own[LIN ? MAXR : 1];
+  if constexpr (LIN) {
+#pragma unroll
+    for (int q = 0; q < MAXR; ++q) own[q] = q < (int)nr ? (uint32_t)faddr(a.rd[q], i) : 0u;
+  }
   for (int j0 = 0; j0 < deg; j0 += NB) {
     Words<MAXR, W8> w[NB];
     bool ok[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      const int32_t r = j0 + b < deg ? nb.get(a, j0 + b) : -1;
-      ok[b] = r >= 0;
-      const uint64_t rr = ok[b] ? (uint64_t)r : i;
-#pragma unroll
-      for (int q = 0; q < MAXR; ++q)
-        if (q < (int)nr) w[b].load(q, a.buf, a.rd[q], rr);
-    }
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-      if (ok[b]) {
+      const int jj = min(j0 + b, deg - 1);
+      // a coordinate off the grid wraps to a large unsigned value
+      ok[b] = (j0 + b < deg) & ((uint32_t)(x + a.off[jj][0]) < a.nx) & ((uint32_t)(y + a.off[jj][1]) < a.ny) &
+              ((uint32_t)(z + a.off[jj][2]) < a.nz);
+      if constexpr (LIN) {
+        const int32_t lin = a.lin[jj];
 #pragma unroll
         for (int q = 0; q < MAXR; ++q)
           if (q < (int)nr) {
-            const uint64_t t = w[b].term(q, a.rd[q]);
-            fold(acc[0], 0, a.wr[0].dt, a.rd[q].dt, t);
-            if (nw > 1) fold(acc[1], 1, a.wr[1].dt, a.rd[q].dt, t);
+            const int32_t step = lin * (int32_t)a.rd[q].TS;
+            w[b].load_at(q, a.buf + (own[q] + (uint32_t)(ok[b] ? step : 0)), a.rd[q]);
           }
+      } else {
+        const uint64_t rr = ok[b] ? (uint64_t)(ii + a.lin[jj]) : i;
+#pragma unroll
+        for (int q = 0; q < MAXR; ++q)
+          if (q < (int)nr) w[b].load(q, a.buf, a.rd[q], rr);
       }
+    }
+    if constexpr (F32) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int q = 0; q < MAXR; ++q)
+          if (q < (int)nr) {
+            const float v = __uint_as_float(w[b].lo[q]);
+            const float s0 = __fadd_rn(acc[0].f, v);
+            acc[0].f = ok[b] ? s0 : acc[0].f;
+            if (nw > 1) {
+              const float s1 = __fadd_rn(__fmul_rn(acc[1].f, 0.5f), v);
+              acc[1].f = ok[b] ? s1 : acc[1].f;
+            }
+          }
+    } else {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        if (ok[b]) {
+#pragma unroll
+          for (int q = 0; q < MAXR; ++q)
+            if (q < (int)nr) {
+              const uint64_t tv = w[b].term(q, a.rd[q]);
+              fold(acc[0], 0, a.wr[0].dt, a.rd[q].dt, tv);
+              if (nw > 1) fold(acc[1], 1, a.wr[1].dt, a.rd[q].dt, tv);
+            }
+        }
+    }
   }
-  store_acc(a.buf, a.wr[0], i, acc[0]);
-  if (nw > 1) store_acc(a.buf, a.wr[1], i, acc[1]);
+  if constexpr (F32) {
+    *reinterpret_cast<uint32_t *>(a.buf + faddr(a.wr[0], i)) = __float_as_uint(acc[0].f);
+    if (nw > 1) *reinterpret_cast<uint32_t *>(a.buf + faddr(a.wr[1], i)) = __float_as_uint(acc[1].f);
+  } else {
+    store_acc(a.buf, a.wr[0], i, acc[0]);
+    if (nw > 1) store_acc(a.buf, a.wr[1], i, acc[1]);
+  }
 }
 
 // Gather whose read fields all sit in one interleaved group: per neighbour
@@ -445,12 +520,31 @@ static SField sfield(const LayoutDesc &l, int f) {
   return s;
 }
 
-template <bool W8>
+template <bool W8, bool LIN, bool F32>
 static void launch_stencil(uint32_t nr, dim3 grid, const SectionArgs &a, hipStream_t st) {
-  if (nr <= 4) hipLaunchKernelGGL((stencil_kernel<4, W8>), grid, dim3(256), 0, st, a);
-  else if (nr <= 8) hipLaunchKernelGGL((stencil_kernel<8, W8>), grid, dim3(256), 0, st, a);
-  else if (nr <= 16) hipLaunchKernelGGL((stencil_kernel<16, W8>), grid, dim3(256), 0, st, a);
-  else hipLaunchKernelGGL((stencil_kernel<32, W8>), grid, dim3(256), 0, st, a);
+  if constexpr (F32) {
+    // exact field counts for the small stencils (the common case)
+    if (nr == 1) {
+      hipLaunchKernelGGL((stencil_kernel<1, W8, LIN, F32, true>), grid, dim3(256), 0, st, a);
+      return;
+    }
+    if (nr == 2) {
+      hipLaunchKernelGGL((stencil_kernel<2, W8, LIN, F32, true>), grid, dim3(256), 0, st, a);
+      return;
+    }
+    if (nr == 3) {
+      hipLaunchKernelGGL((stencil_kernel<3, W8, LIN, F32, true>), grid, dim3(256), 0, st, a);
+      return;
+    }
+    if (nr == 4) {
+      hipLaunchKernelGGL((stencil_kernel<4, W8, LIN, F32, true>), grid, dim3(256), 0, st, a);
+      return;
+    }
+  }
+  if (nr <= 4) hipLaunchKernelGGL((stencil_kernel<4, W8, LIN, F32, false>), grid, dim3(256), 0, st, a);
+  else if (nr <= 8) hipLaunchKernelGGL((stencil_kernel<8, W8, LIN, F32, false>), grid, dim3(256), 0, st, a);
+  else if (nr <= 16) hipLaunchKernelGGL((stencil_kernel<16, W8, LIN, F32, false>), grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((stencil_kernel<32, W8, LIN, F32, false>), grid, dim3(256), 0, st, a);
 }
 
 template <int OP, int DG, bool W8>
@@ -782,10 +876,25 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
   switch (sec.op) {
     case ADHA_OP_GEN: {
       if (sec.stencil) {
-        bool w8 = false;
-        for (uint32_t q = 0; q < nr; ++q) w8 |= a.rd[q].e == 8;
-        if (w8) launch_stencil<true>(nr, grid, a, stream);
-        else launch_stencil<false>(nr, grid, a, stream);
+        bool w8 = false, lin = l.nbytes <= (1ull << 32), f32 = true;
+        int64_t max_lin = 0;
+        for (uint32_t j = 0; j < sec.degree; ++j) max_lin = std::max<int64_t>(max_lin, std::abs((int64_t)a.lin[j]));
+        for (uint32_t q = 0; q < nr; ++q) {
+          w8 |= a.rd[q].e == 8;
+          lin &= a.rd[q].logT == 0 && max_lin * (int64_t)a.rd[q].TS < (int64_t(1) << 31);
+          f32 &= a.rd[q].dt == ADHA_F32;
+        }
+        for (uint32_t k = 0; k < a.n_write; ++k) f32 &= a.wr[k].dt == ADHA_F32;
+        if (f32) {
+          if (lin) launch_stencil<false, true, true>(nr, grid, a, stream);
+          else launch_stencil<false, false, true>(nr, grid, a, stream);
+        } else if (w8) {
+          if (lin) launch_stencil<true, true, false>(nr, grid, a, stream);
+          else launch_stencil<true, false, false>(nr, grid, a, stream);
+        } else {
+          if (lin) launch_stencil<false, true, false>(nr, grid, a, stream);
+          else launch_stencil<false, false, false>(nr, grid, a, stream);
+        }
         break;
       }
       SpanArgs sp{};
