@@ -292,6 +292,7 @@ __global__ __launch_bounds__(256) void stencil_kernel(const SectionArgs a) {
   Acc acc[2];
   acc[0] = acc[1] = Acc{0.0f, 0.0, 0u};
   constexpr int NB = MAXR >= 32 ? 1 : (MAXR <= 4 ? 8 : 32 / MAXR);
+  static_assert(ADHA_MAX_DEGREE % NB == 0, "batches must tile the offset tables");
   const int deg = (int)a.degree;
   // grid coordinates of record i
   const int32_t ii = (int32_t)i;
@@ -307,7 +308,9 @@ __global__ __launch_bounds__(256) void stencil_kernel(const SectionArgs a) {
     bool ok[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      const int jj = min(j0 + b, deg - 1);
+      // NB divides ADHA_MAX_DEGREE, so jj stays inside the offset tables;
+      // their entries past the degree are zero and not selected
+      const int jj = j0 + b;
       // a coordinate off the grid wraps to a large unsigned value
       ok[b] = (j0 + b < deg) & ((uint32_t)(x + a.off[jj][0]) < a.nx) & ((uint32_t)(y + a.off[jj][1]) < a.ny) &
               ((uint32_t)(z + a.off[jj][2]) < a.nz);
