@@ -86,6 +86,7 @@ def parse():
     ap.add_argument("--skip-flow", action="store_true")
     ap.add_argument("--skip-medical", action="store_true")
     ap.add_argument("--skip-subdword", action="store_true")
+    ap.add_argument("--only-subdword", action="store_true", help="the sub-dword remap leg only")
     ap.add_argument("--only-medical", action="store_true", help="the Medical-shaped stencil leg only")
     ap.add_argument("--only-flow", action="store_true", help="the branching-program leg only")
     ap.add_argument("--only-hetero", action="store_true", help="the GPU + host planning leg only")
@@ -580,6 +581,9 @@ def main():
         return
     if args.only_medical:
         print(json.dumps({"medical": medical_bench(A, synth, torch, timer)}), flush=True)
+        return
+    if args.only_subdword:
+        print(json.dumps({"subdword": subdword_bench(A, torch, timer)}), flush=True)
         return
     if args.only_flow:
         print(json.dumps({"flow": flow_bench(A, synth, torch, timer, args.program_log2n)}), flush=True)

@@ -59,6 +59,32 @@ def test_stencils_match_oracle(ctx, grid):
     ctx.set_option(A.OPT_SPAN_GATHER, 1)
 
 
+@pytest.mark.parametrize("grid", [(9, 7, 5), (40, 3, 21)])
+def test_stencils_with_mixed_types_and_wide_reads(ctx, grid):
+    """The generic forms: F64 and I32 fields (typed fold, 8-byte loads),
+    5 to 7 read fields (no exact field count), two writes, 27 neighbours."""
+    n = grid[0] * grid[1] * grid[2]
+    dts = [A.F32, A.F64, A.I32, A.F32, A.F64, A.I32, A.F32, A.F32, A.F64, A.I32]
+    eb = [8 if d == A.F64 else 4 for d in dts]
+    st = A.Struct(n, dts, eb)
+    sdts = [synth.F64 if d == A.F64 else synth.I32 if d == A.I32 else synth.F32 for d in dts]
+    cols = synth.record_matrix(21, n, sdts, eb)
+    secs = [([0, 3, 6, 7, 2], [9], synth.STENCIL7), ([1, 4, 0], [5, 8], OFFS27),
+            ([0, 1, 2, 3, 4, 5, 6], [7], synth.STENCIL7), ([0, 3], [6, 7], OFFS27[:13])]
+    secs_h = [(A.Section.stencil(st, rd, wr, grid, offs), rd, wr, offs) for rd, wr, offs in secs]
+    for O in (oaos(n, eb), osoa(n, eb), OLayout(n, eb, [0] * 10, [64]),
+              from_partition(n, eb, [[0, 3, 6, 7], [1, 4]], 1), from_partition(n, eb, [[0, 1, 2, 3, 4, 5, 6]], 4)):
+        want = oracle.pack(O, cols)
+        for _, rd, wr, offs in secs_h:
+            oracle.section(O, sdts, synth.OP_GEN, rd, wr, len(offs), oracle.stencil_index(*grid, offs), want)
+        dev = dev_bytes(oracle.pack(O, cols))
+        say("stencil mixed", grid, O)
+        for sec, *_ in secs_h:
+            A.section_run(ctx, sec, mirror(st, O), dev)
+        ctx.check()
+        assert np.array_equal(host(dev, O.nbytes), want), (grid, O)
+
+
 @pytest.mark.timeout(900)
 def test_medical_program_full_size(ctx):
     """The Medical-shaped program on a 256^3 image: planned, all-AoS and
