@@ -53,9 +53,9 @@ HBM_PEAK_GBS = 8000.0
 # dispatches), each scaled by what the same counter reads for a plain 1 GiB
 # device copy (fetch 524311.4 KiB, write 1048576 KiB).  It holds only for the
 # kernel source it was taken on; any other source reports null.
-REMAP_TRAFFIC = {"source_sha1": "0353914cd5d84e2020971dcf1f4e27cfefa5a8d0",
-                 "fetch_kib": 2097220.2, "write_kib": 4194323.4,
-                 "copy_fetch_kib": 524311.4, "copy_write_kib": 1048576.0, "copy_bytes": 1 << 30}
+REMAP_TRAFFIC = {"source_sha1": "2f60983d66d06b243a82110a7038279a7d756459",
+                 "fetch_kib": 2097216.0, "write_kib": 4194322.5,
+                 "copy_fetch_kib": 524311.5, "copy_write_kib": 1048576.0, "copy_bytes": 1 << 30}
 
 
 def remap_traffic_bytes():
