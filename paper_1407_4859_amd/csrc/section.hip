@@ -250,6 +250,42 @@ __global__ __launch_bounds__(256) void section_kernel(const SectionArgs a) {
   if (nw > 1) store_acc(a.buf, a.wr[1], i, acc[1]);
 }
 
+// Direct GEN / SUM sections whose read and write fields are all F32: the
+// generic kernel's fold branches on the field types per term, which costs
+// tens of scalar instructions per term and bounds the loop by instruction
+// issue; here the fold is straight-line.  Loads are not guarded: descriptors
+// past the read count are zero, so those slots load the buffer's first word
+// and are never folded.  LIN: every read field sits in a group with T = 1
+// and the layout fits in 4 GiB, so a field's offset is base + p + r*S in 32
+// bits.
+template <int MAXR, bool LIN>
+__global__ __launch_bounds__(256) void direct_f32_kernel(const SectionArgs a) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  if (i >= (uint64_t)a.n) return;
+  const uint32_t nr = a.n_read, nw = a.n_write;
+  uint32_t w[MAXR];
+#pragma unroll
+  for (int q = 0; q < MAXR; ++q) {
+    const SField &F = a.rd[q];
+    if constexpr (LIN) {
+      const uint32_t off = (uint32_t)F.base + F.pT + (uint32_t)i * F.TS;
+      w[q] = *reinterpret_cast<const uint32_t *>(a.buf + off);
+    } else {
+      w[q] = *reinterpret_cast<const uint32_t *>(a.buf + faddr(F, i));
+    }
+  }
+  float acc0 = 0.0f, acc1 = 0.0f;
+#pragma unroll
+  for (int q = 0; q < MAXR; ++q)
+    if (q < (int)nr) {
+      const float v = __uint_as_float(w[q]);
+      acc0 = __fadd_rn(acc0, v);
+      if (nw > 1) acc1 = __fadd_rn(__fmul_rn(acc1, 0.5f), v);
+    }
+  *reinterpret_cast<uint32_t *>(a.buf + faddr(a.wr[0], i)) = __float_as_uint(acc0);
+  if (nw > 1) *reinterpret_cast<uint32_t *>(a.buf + faddr(a.wr[1], i)) = __float_as_uint(acc1);
+}
+
 // Workgroups go to the chip's 8 XCDs round-robin (workgroup b to XCD b mod
 // 8), and each XCD has an L2 of its own.  Block xcd_block(b, G) gives XCD x
 // one contiguous range of the G blocks, so that the records a neighbour at a
@@ -558,6 +594,14 @@ static void launch_maxr_w(uint32_t nr, dim3 grid, const SectionArgs &a, hipStrea
   else hipLaunchKernelGGL((section_kernel<OP, DG, 32, W8>), grid, dim3(256), 0, st, a);
 }
 
+template <bool LIN>
+static void launch_direct_f32(uint32_t nr, dim3 grid, const SectionArgs &a, hipStream_t st) {
+  if (nr <= 4) hipLaunchKernelGGL((direct_f32_kernel<4, LIN>), grid, dim3(256), 0, st, a);
+  else if (nr <= 8) hipLaunchKernelGGL((direct_f32_kernel<8, LIN>), grid, dim3(256), 0, st, a);
+  else if (nr <= 16) hipLaunchKernelGGL((direct_f32_kernel<16, LIN>), grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((direct_f32_kernel<32, LIN>), grid, dim3(256), 0, st, a);
+}
+
 template <int OP, int DG>
 static void launch_maxr(uint32_t nr, dim3 grid, const SectionArgs &a, hipStream_t st) {
   bool w8 = false;
@@ -744,6 +788,83 @@ __global__ __launch_bounds__(256) void reduce_reg_kernel(const ReduceArgs a) {
   if (bad) atomicOr(a.err, 1u);
 }
 
+// Few keys, every read field F32: the same sums with no branch per column.
+// A column slot past the reads folds 0.0 (adding +0.0 to a sum that started
+// at +0.0 and only ever had values added leaves it unchanged, bit for bit),
+// and the record counts live in their own per-key registers, written by the
+// slice that holds the count column.  LIN: the read fields and the key sit
+// in groups with T = 1 and the layout fits in 4 GiB, so offsets are
+// base + p + r*S in 32 bits.
+template <bool LIN>
+__device__ __forceinline__ uint32_t reduce_word(const ReduceArgs &a, const SField &F, uint64_t i) {
+  if constexpr (LIN) return *reinterpret_cast<const uint32_t *>(a.buf + ((uint32_t)F.base + F.pT + (uint32_t)i * F.TS));
+  return load_word(a.buf, F, i);
+}
+
+template <int KR, int CR, bool LIN>
+__global__ __launch_bounds__(256) void reduce_reg_f32_kernel(const ReduceArgs a) {
+  __shared__ uint64_t wsum[4][KR * (CR + 1)];
+  const uint32_t nr = a.n_read, cols = nr + 1;
+  const uint32_t c0 = blockIdx.y * CR;
+  const uint32_t nc = min((uint32_t)CR, cols - c0);
+  double acc[KR][CR];
+  uint32_t cnt[KR];
+#pragma unroll
+  for (int kk = 0; kk < KR; ++kk) {
+    cnt[kk] = 0;
+#pragma unroll
+    for (int c = 0; c < CR; ++c) acc[kk][c] = 0.0;
+  }
+  bool bad = false;
+  const uint64_t stride = (uint64_t)gridDim.x * 256u;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < (uint64_t)a.n; i += stride) {
+    int32_t k = 0;
+    if (a.has_key) k = (int32_t)reduce_word<LIN>(a, a.key, i);
+    const bool ok = k >= 0 && (uint32_t)k < a.n_keys;
+    bad |= !ok;
+    uint32_t w[CR];
+#pragma unroll
+    for (int c = 0; c < CR; ++c) w[c] = reduce_word<LIN>(a, a.rd[c0 + c < nr ? c0 + c : ADHA_MAX_READ - 1], i);
+#pragma unroll
+    for (int c = 0; c < CR; ++c) {
+      const double d = c0 + c < nr ? (double)__uint_as_float(w[c]) : 0.0;
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) acc[kk][c] = __dadd_rn(acc[kk][c], (ok && k == kk) ? d : 0.0);
+    }
+#pragma unroll
+    for (int kk = 0; kk < KR; ++kk) cnt[kk] += (ok && k == kk) ? 1u : 0u;
+  }
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+#pragma unroll
+  for (int kk = 0; kk < KR; ++kk) {
+#pragma unroll
+    for (int c = 0; c < CR; ++c) {
+      const uint64_t x = (uint64_t)__double_as_longlong(wave_sum_f64(acc[kk][c]));
+      if (lane == 0) wsum[wave][kk * (CR + 1) + c] = x;
+    }
+    const uint64_t n = wave_sum_u64((uint64_t)cnt[kk]);
+    if (lane == 0) wsum[wave][kk * (CR + 1) + CR] = n;
+  }
+  __syncthreads();
+  const uint32_t t = threadIdx.x;
+  if (t < (uint32_t)(KR * CR)) {
+    const uint32_t kk = t / CR, c = t % CR, col = c0 + c;
+    if (kk < a.n_keys && c < nc) {
+      const bool count = col == nr;
+      const uint32_t slot = kk * (CR + 1) + (count ? CR : c);
+      double d = 0.0;
+      uint64_t u = 0;
+      for (int w = 0; w < 4; ++w) {
+        if (count) u += wsum[w][slot];
+        else d += __longlong_as_double((long long)wsum[w][slot]);
+      }
+      const uint32_t cell = kk * cols + col;
+      a.partials[(uint64_t)cell * gridDim.x + blockIdx.x] = count ? u : (uint64_t)__double_as_longlong(d);
+    }
+  }
+  if (bad) atomicOr(a.err, 1u);
+}
+
 __global__ __launch_bounds__(256) void reduce_final_kernel(const uint64_t *partials, uint32_t groups, uint32_t cols,
                                                            uint32_t fp_mask, uint64_t *out) {
   __shared__ double sd[256];
@@ -786,6 +907,20 @@ static void reduce_dispatch(uint32_t KR, uint32_t nr, dim3 grid, size_t lds, hip
   else hipLaunchKernelGGL((reduce_partial_kernel<32, W8>), grid, dim3(256), lds, stream, a);
 }
 
+template <bool LIN>
+static void reduce_f32_dispatch(uint32_t KR, dim3 grid, hipStream_t stream, const ReduceArgs &a) {
+  switch (KR) {
+    case 1: hipLaunchKernelGGL((reduce_reg_f32_kernel<1, 33, LIN>), grid, dim3(256), 0, stream, a); break;
+    case 2: hipLaunchKernelGGL((reduce_reg_f32_kernel<2, 17, LIN>), grid, dim3(256), 0, stream, a); break;
+    case 3: hipLaunchKernelGGL((reduce_reg_f32_kernel<3, 11, LIN>), grid, dim3(256), 0, stream, a); break;
+    case 4: hipLaunchKernelGGL((reduce_reg_f32_kernel<4, 9, LIN>), grid, dim3(256), 0, stream, a); break;
+    case 5: hipLaunchKernelGGL((reduce_reg_f32_kernel<5, 7, LIN>), grid, dim3(256), 0, stream, a); break;
+    case 6: hipLaunchKernelGGL((reduce_reg_f32_kernel<6, 6, LIN>), grid, dim3(256), 0, stream, a); break;
+    case 7: hipLaunchKernelGGL((reduce_reg_f32_kernel<7, 5, LIN>), grid, dim3(256), 0, stream, a); break;
+    default: hipLaunchKernelGGL((reduce_reg_f32_kernel<8, 5, LIN>), grid, dim3(256), 0, stream, a); break;
+  }
+}
+
 static adha_status reduce_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l, const void *buf,
                                  void *out, hipStream_t stream) {
   const int64_t n = l.shape.n;
@@ -821,8 +956,18 @@ static adha_status reduce_launch(Ctx *ctx, const SectionDesc &sec, const LayoutD
   const dim3 grid(groups, slices);
   bool w8 = false;
   for (int f : sec.rd) w8 |= l.shape.ebytes[f] == 8;
-  if (w8) reduce_dispatch<true>(KR, nr, grid, lds, stream, a);
-  else reduce_dispatch<false>(KR, nr, grid, lds, stream, a);
+  bool f32 = true;
+  for (int f : sec.rd) f32 &= l.shape.dtype[f] == ADHA_F32;
+  if (f32 && KR >= 1) {
+    bool lin = l.nbytes <= (1ull << 32) && (sec.key < 0 || a.key.logT == 0);
+    for (uint32_t q = 0; q < nr; ++q) lin &= a.rd[q].logT == 0;
+    if (lin) reduce_f32_dispatch<true>(KR, grid, stream, a);
+    else reduce_f32_dispatch<false>(KR, grid, stream, a);
+  } else if (w8) {
+    reduce_dispatch<true>(KR, nr, grid, lds, stream, a);
+  } else {
+    reduce_dispatch<false>(KR, nr, grid, lds, stream, a);
+  }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess)
     hipLaunchKernelGGL(reduce_final_kernel, dim3(a.cells), dim3(256), 0, stream, (const uint64_t *)partials, groups,
@@ -876,6 +1021,19 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
   }
   const dim3 grid((uint32_t)((n + 255) / 256));
   const uint32_t nr = a.n_read;
+  // direct GEN / SUM over F32 fields only: the straight-line kernel
+  bool all_f32 = true, all_t1 = l.nbytes <= (1ull << 32);
+  for (uint32_t q = 0; q < nr; ++q) {
+    all_f32 &= a.rd[q].dt == ADHA_F32;
+    all_t1 &= a.rd[q].logT == 0;
+  }
+  for (uint32_t k = 0; k < a.n_write; ++k) all_f32 &= a.wr[k].dt == ADHA_F32;
+  if ((sec.op == ADHA_OP_GEN || sec.op == ADHA_OP_SUM) && sec.degree == 0 && !sec.stencil && all_f32) {
+    if (all_t1) launch_direct_f32<true>(nr, grid, a, stream);
+    else launch_direct_f32<false>(nr, grid, a, stream);
+    ADHA_HIP(hipGetLastError());
+    return ADHA_OK;
+  }
   switch (sec.op) {
     case ADHA_OP_GEN: {
       if (sec.stencil) {

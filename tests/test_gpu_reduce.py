@@ -94,6 +94,27 @@ def test_reduce_matches_oracle_on_layouts(ctx, n):
         _check(got, table, spec.dtypes, read, _abs_sums(O, spec.dtypes, read, 6, 5, buf_h))
 
 
+@pytest.mark.parametrize("n_keys", [1, 2, 5, 8])
+def test_reduce_f32_reads_on_every_layout_kind(ctx, n_keys):
+    """All-F32 read sets (the straight-line register kernel) on interleaved,
+    single-field, tiled and grouped-tiled layouts, ragged N, with and
+    without a key field."""
+    n = 3 * 4096 + 77
+    spec, cols = _struct(n, 9, n_keys)
+    eb = spec.elem_bytes
+    read = [0, 1, 2, 3, 4, 5, 10]
+    key = -1 if n_keys == 1 else 6
+    for O in (oaos(n, eb), osoa(n, eb), OLayout(n, eb, [0] * 11, [64]),
+              from_partition(n, eb, [[0, 1, 6], [2, 3, 4, 5, 10]], 4),
+              from_partition(n, eb, [[0, 6], [2, 5, 8]], 16)):
+        say("reduce f32", n_keys, O)
+        buf_h, sec, out = _run(ctx, spec, cols, O, read, key, n_keys)
+        ctx.check()
+        table, bad = OR.reduce(O, spec.dtypes, read, key, n_keys, buf_h)
+        assert bad == 0
+        _check(host(out).view(np.uint64), table, spec.dtypes, read, {})
+
+
 @pytest.mark.parametrize("n_keys,read", [(1, [0, 1, 7, 9]), (1, [0, 1, 2]), (2, [0, 7, 8, 10]), (3, [1, 2, 3, 4, 5]),
                                          (6, [0, 2, 7, 9, 10]), (7, [0, 1, 2, 3, 4, 5, 7, 10]),
                                          (8, [0, 1, 7, 8, 9, 10]), (9, [0, 1, 7]), (64, [0, 1, 2, 3]),

@@ -137,6 +137,24 @@ def test_wide_read_sets(ctx):
     _run_sections(ctx, spec, oaos(n, spec.elem_bytes), secs, cols, idx, "wide")
 
 
+def test_f32_direct_sections_every_read_count_and_layout(ctx):
+    """All-F32 direct sections (the straight-line kernel) with 1 to 32 reads
+    and one or two writes, on interleaved, single-field and tiled layouts."""
+    n = 5 * 1024 + 3
+    spec = synth.StructSpec(n, [synth.F32] * 36, [4] * 36)
+    cols = synth.record_matrix(14, n, spec.dtypes, spec.elem_bytes)
+    secs = [synth.SectionSpec(synth.OP_GEN, [7], [33]),
+            synth.SectionSpec(synth.OP_GEN, [0, 3, 5, 8, 13], [34, 35]),
+            synth.SectionSpec(synth.OP_GEN, list(range(2, 11)), [32]),
+            synth.SectionSpec(synth.OP_SUM, list(range(17)), [33]),
+            synth.SectionSpec(synth.OP_GEN, list(range(32)), [34, 35])]
+    eb = spec.elem_bytes
+    for O in (oaos(n, eb), osoa(n, eb), OLayout(n, eb, [0] * 36, [64]),
+              from_partition(n, eb, [list(range(0, 12)), list(range(12, 36))], 8),
+              from_partition(n, eb, [[0, 1, 2, 3], [32, 33, 34, 35]], 1)):
+        _run_sections(ctx, spec, O, secs, cols, None, "f32 direct")
+
+
 @pytest.mark.parametrize("group,rd", [
     ([0, 1, 2, 3, 4], [0, 2, 3]),          # 24-byte records (8-byte loads), f64 in the middle
     ([1, 2, 3, 5, 6, 7], [1, 3, 6, 7]),    # 28 bytes (4-byte loads)
