@@ -555,10 +555,20 @@ def remap(ctx: Ctx, src_l: Layout, src, dst_l: Layout, dst, stream=None):
     check(lib().adha_remap(ctx.h, src_l.h, sp, sc, dst_l.h, dp, dc, stream_ptr(stream)))
 
 
+class BatchItems:
+    """The C item array of a batch, marshalled once, for callers that replay
+    one batch many times (its tensors and layouts must stay alive)."""
+
+    def __init__(self, items):
+        self.n = len(items)
+        self.arr = _items(items)
+
+
 def remap_batched(ctx: Ctx, items, flags: int = 0, stream=None):
-    """items: (src layout, src tensor, dst layout, dst tensor) tuples."""
-    arr = _items(items)
-    check(lib().adha_remap_batched(ctx.h, len(items), arr, flags, stream_ptr(stream)))
+    """items: (src layout, src tensor, dst layout, dst tensor) tuples, or a
+    BatchItems."""
+    b = items if isinstance(items, BatchItems) else BatchItems(items)
+    check(lib().adha_remap_batched(ctx.h, b.n, b.arr, flags, stream_ptr(stream)))
 
 
 def set_shape(ctx: Ctx, src_l: Layout, dst_l: Layout, tile_records=0, slots=0, pad_shift=0, wg_per_cu=0,

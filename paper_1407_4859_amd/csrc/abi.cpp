@@ -37,6 +37,43 @@ static bool overlap(const void *a, uint64_t na, const void *b, uint64_t nb) {
   return x < y + nb && y < x + na;
 }
 
+// No item's destination may overlap another item's destination or source
+// (an item's own source and destination were checked on their own).  Sorted
+// sweeps instead of all pairs: destinations by start with the running end,
+// then each destination against the sources that start before its end,
+// through the running maximum of their ends.
+static adha_status check_items_disjoint(uint32_t n, const adha_remap_item *items) {
+  struct Iv {
+    uintptr_t lo, hi;
+    uint32_t item;
+  };
+  std::vector<Iv> d, s;
+  d.reserve(n);
+  s.reserve(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    const uint64_t dn = items[i].dst_layout->d.nbytes, sn = items[i].src_layout->d.nbytes;
+    if (dn) d.push_back({(uintptr_t)items[i].dst, (uintptr_t)items[i].dst + dn, i});
+    if (sn) s.push_back({(uintptr_t)items[i].src, (uintptr_t)items[i].src + sn, i});
+  }
+  auto by_lo = [](const Iv &a, const Iv &b) { return a.lo < b.lo; };
+  std::sort(d.begin(), d.end(), by_lo);
+  std::sort(s.begin(), s.end(), by_lo);
+  auto report = [](uint32_t a, uint32_t b) {
+    return fail(ADHA_ERR_INVALID, "items %u and %u overlap", std::min(a, b), std::max(a, b));
+  };
+  for (size_t k = 1, top = 0; k < d.size(); ++k) {
+    if (d[k].lo < d[top].hi) return report(d[top].item, d[k].item);
+    if (d[k].hi > d[top].hi) top = k;
+  }
+  std::vector<size_t> best(s.size());  // index of the largest end among s[0..k]
+  for (size_t k = 0; k < s.size(); ++k) best[k] = k && s[best[k - 1]].hi >= s[k].hi ? best[k - 1] : k;
+  for (const Iv &x : d) {
+    const size_t c = std::lower_bound(s.begin(), s.end(), Iv{x.hi, 0, 0}, by_lo) - s.begin();
+    if (c && s[best[c - 1]].hi > x.lo) return report(s[best[c - 1]].item, x.item);
+  }
+  return ADHA_OK;
+}
+
 static const size_t kCacheLimit = 4096;
 
 // Drops every cached descriptor blob and every graph that launches them.
@@ -424,14 +461,7 @@ adha_status adha_remap_batched(adha_ctx *ctx, uint32_t n, const adha_remap_item 
     adha_status st = validate_remap(it.src_layout, it.src, it.src_cap, it.dst_layout, it.dst, it.dst_cap);
     if (st < 0) return fail(st, "item %u: %s", i, adha::last_error());
   }
-  for (uint32_t i = 0; i < n; ++i)
-    for (uint32_t j = i + 1; j < n; ++j) {
-      const adha_remap_item &a = items[i], &b = items[j];
-      uint64_t an = a.dst_layout->d.nbytes, bn = b.dst_layout->d.nbytes;
-      if (overlap(a.dst, an, b.dst, bn) || overlap(a.dst, an, b.src, b.src_layout->d.nbytes) ||
-          overlap(b.dst, bn, a.src, a.src_layout->d.nbytes))
-        return fail(ADHA_ERR_INVALID, "items %u and %u overlap", i, j);
-    }
+  ADHA_TRY(check_items_disjoint(n, items));
   DeviceGuard g(ctx->c.device);
   return batch_run(&ctx->c, n, items, flags, (hipStream_t)stream);
 }
