@@ -91,6 +91,44 @@ def test_batched_rejects_overlapping_items(ctx):
         A.remap_batched(ctx, items)
 
 
+def test_batched_overlap_check_matches_all_pairs(ctx):
+    """Random batches of small items placed in one buffer: the library's
+    sorted-sweep check rejects a batch exactly when some item's destination
+    overlaps another item's destination or source (all pairs, here)."""
+    import random
+    rng = random.Random(11)
+    st = A.Struct(1000, [A.F32, A.F32, A.F32, A.F32])
+    la, ls = A.Layout.aos(st), A.Layout.soa(st)
+    na, ns = la.nbytes, ls.nbytes
+    slot = 4096
+    buf = torch.zeros(64 * slot + ns, dtype=torch.uint8, device="cuda")
+
+    def ov(a, x, b, y):
+        return a < b + y and b < a + x
+
+    rejected = 0
+    for trial in range(150):
+        k = rng.randint(1, 6)
+        spans = []
+        for _ in range(k):
+            s = rng.randrange(64) * slot
+            d = rng.randrange(64) * slot
+            while ov(s, na, d, ns):
+                d = rng.randrange(64) * slot
+            spans.append((s, d))
+        want = any(ov(spans[i][1], ns, spans[j][1], ns) or ov(spans[i][1], ns, spans[j][0], na) or
+                   ov(spans[j][1], ns, spans[i][0], na) for i in range(k) for j in range(i + 1, k))
+        items = [(la, buf[s:s + na], ls, buf[d:d + ns]) for s, d in spans]
+        if want:
+            with pytest.raises(A.AdhaError, match="overlap"):
+                A.remap_batched(ctx, items)
+            rejected += 1
+        else:
+            A.remap_batched(ctx, items)
+    ctx.check()
+    assert 0 < rejected < 150
+
+
 def test_tuner_picks_a_valid_shape_and_persists(ctx):
     n = (1 << 20) + 77
     spec = synth.config2_struct(n)
