@@ -42,7 +42,7 @@ static bool overlap(const void *a, uint64_t na, const void *b, uint64_t nb) {
 // sweeps instead of all pairs: destinations by start with the running end,
 // then each destination against the sources that start before its end,
 // through the running maximum of their ends.
-static adha_status check_items_disjoint(uint32_t n, const adha_remap_item *items) {
+adha_status check_items_disjoint(uint32_t n, const adha_remap_item *items) {
   struct Iv {
     uintptr_t lo, hi;
     uint32_t item;

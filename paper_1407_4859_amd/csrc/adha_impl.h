@@ -181,6 +181,8 @@ adha_status shape_for(Ctx *ctx, const adha_layout *a, const adha_layout *b, Tile
 adha_status remap_with_shape(Ctx *ctx, const adha_layout *sl, const void *src, const adha_layout *dl,
                              void *dst, const TileShape &sh, hipStream_t stream);
 adha_status batch_run(Ctx *c, uint32_t n, const adha_remap_item *items, uint32_t flags, hipStream_t st);
+// No item's destination overlaps another item's destination or source.
+adha_status check_items_disjoint(uint32_t n, const adha_remap_item *items);
 adha_status prepared_for(Ctx *ctx, const adha_layout *a, const adha_layout *b, const TileShape &sh,
                          const RemapPrepared **out);
 

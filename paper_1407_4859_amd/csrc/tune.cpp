@@ -112,6 +112,7 @@ adha_status adha_tune_batched(adha_ctx *ctx, uint32_t n, const adha_remap_item *
     adha_status s = validate_remap(it.src_layout, it.src, it.src_cap, it.dst_layout, it.dst, it.dst_cap);
     if (s < 0) return s;
   }
+  ADHA_TRY(check_items_disjoint(n, items));
   DeviceGuard g(ctx->c.device);
   Ctx *c = &ctx->c;
   hipStream_t st = (hipStream_t)stream;
