@@ -88,6 +88,7 @@ def parse():
     ap.add_argument("--skip-subdword", action="store_true")
     ap.add_argument("--only-subdword", action="store_true", help="the sub-dword remap leg only")
     ap.add_argument("--only-batched", action="store_true", help="the batched remap leg only")
+    ap.add_argument("--cap-bytes", type=int, default=64, help="greedy grouping cap of the program leg's catalogue")
     ap.add_argument("--only-medical", action="store_true", help="the Medical-shaped stencil leg only")
     ap.add_argument("--only-flow", action="store_true", help="the branching-program leg only")
     ap.add_argument("--only-hetero", action="store_true", help="the GPU + host planning leg only")
@@ -190,7 +191,7 @@ def cpu_baseline(synth):
                       f"{cores} threads over record ranges; {t * 1e3:.0f} ms"}
 
 
-def program_bench(A, synth, torch, timer, log2n, cost="measured"):
+def program_bench(A, synth, torch, timer, log2n, cost="measured", cap_bytes=64):
     n = 1 << log2n
     spec = synth.config3_struct(n)
     st = A.Struct.from_spec(spec)
@@ -208,14 +209,14 @@ def program_bench(A, synth, torch, timer, log2n, cost="measured"):
     log("program: planning (%s costs)" % cost)
     t0 = time.perf_counter()
     src = A.COST_MEASURED if cost == "measured" else A.COST_ANALYTIC
-    plan = A.Plan.create(ctx, prog, A.plan_opts(cost=src, catalogue=A.CAT_FULL, cap_bytes=64, reps=3), idx=idx)
+    plan = A.Plan.create(ctx, prog, A.plan_opts(cost=src, catalogue=A.CAT_FULL, cap_bytes=cap_bytes, reps=3), idx=idx)
     plan_s = time.perf_counter() - t0
-    analytic = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_ANALYTIC, catalogue=A.CAT_FULL, cap_bytes=64))
+    analytic = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_ANALYTIC, catalogue=A.CAT_FULL, cap_bytes=cap_bytes))
     plans = {"adha": plan, "all_aos": A.Plan.uniform(prog, aos_l), "all_soa": A.Plan.uniform(prog, soa_l),
              "adha_analytic": analytic}
     out = {"workload": f"N=2^{log2n} records, 32 fields (20 f32, 8 i32, 4 f64; 144 B), 8 GEN sections "
                        f"(seed 3), 4 gathering 16 uniform neighbours",
-           "candidates": plan.n_candidates, "plan_seconds": round(plan_s, 2)}
+           "candidates": plan.n_candidates, "cap_bytes": cap_bytes, "plan_seconds": round(plan_s, 2)}
     for name, pl in plans.items():
         first = pl.candidate(pl.choices()[0])
         def go(pl=pl, first=first):
@@ -400,6 +401,59 @@ def flow_bench(A, synth, torch, timer, log2n=24):
     res["speedup_vs_best_uniform"] = round(best_uniform / res["adha_flow_expected_ms"], 3)
     res["gain_vs_ignoring_branches"] = round(res["adha_ignoring_branches_expected_ms"] /
                                              res["adha_flow_expected_ms"], 3)
+
+    # Other branch probabilities on the same measured tables: the predicted
+    # expected cost of the branch-aware plan (the library's solver) against
+    # that of the plan that ignores branches, then the setting with the
+    # largest predicted gain planned and measured like the default one.
+    T, R = plan.tables()
+    cands = [plan.candidate(c) for c in range(plan.n_candidates)]
+    blind_nodes = [next(i for i, L in enumerate(cands) if L.equals(lin.candidate(c))) for c in lin.choices()]
+
+    def blind_expected(probs):
+        total = 0.0
+        for taken in itertools.product([1, 0], repeat=2):
+            prob = 1.0
+            for p, t in zip(probs, taken):
+                prob *= p if t else 1.0 - p
+            path = [0, 1] + ([2, 3] if taken[0] else [4]) + [5] + ([6] if taken[1] else []) + [7]
+            c = [blind_nodes[s] for s in path]
+            cost = sum(T[s][blind_nodes[s]] for s in path) + sum(R[a][b] for a, b in zip(c, c[1:]))
+            total += prob * cost
+        return total
+
+    sweep = []
+    for p1 in (0.05, 0.2, 0.5, 0.8, 0.95):
+        for p2 in (0.05, 0.2, 0.5, 0.8, 0.95):
+            aware = A.flow_solve(T, R, FLOW_TOKENS, [p1, p2])[0]
+            sweep.append((blind_expected([p1, p2]) / aware, p1, p2))
+    sweep.sort(reverse=True)
+    g, p1, p2 = sweep[0]
+    res["probability_sweep"] = {"predicted_gain_max": round(g, 3), "at": [p1, p2],
+                                "predicted_gain_min": round(sweep[-1][0], 3)}
+    if g > 1.01:
+        prog2 = A.Program(st, ss)
+        prog2.set_flow(FLOW_TOKENS, [p1, p2])
+        log("flow: planning at probabilities", p1, p2)
+        plan2 = A.Plan.create(ctx, prog2, A.plan_opts(cost=A.COST_MEASURED, catalogue=A.CAT_FULL, cap_bytes=64,
+                                                      reps=3), idx=idx)
+        blind2 = A.Plan.explicit(prog2, [lin.candidate(c) for c in lin.choices()])
+        measured = {}
+        for name, pl in (("adha_flow", plan2), ("adha_ignoring_branches", blind2)):
+            first = pl.candidate(pl.choices()[0])
+            exp_ms = 0.0
+            for taken in itertools.product([1, 0], repeat=2):
+                prob = 1.0
+                for p, t in zip((p1, p2), taken):
+                    prob *= p if t else 1.0 - p
+                ms, _ = timer.time(lambda: A.run_flow(ctx, pl, first, buf_a, buf_b, taken, idx), reps=3, warm=1)
+                exp_ms += prob * ms
+            measured[name + "_expected_ms"] = round(exp_ms, 3)
+        ctx.check()
+        measured["predicted_expected_ms"] = round(plan2.cost / 1e3, 3)
+        measured["measured_gain"] = round(measured["adha_ignoring_branches_expected_ms"] /
+                                          measured["adha_flow_expected_ms"], 3)
+        res["probability_sweep"]["measured_at_max"] = measured
     return res
 
 
@@ -605,7 +659,8 @@ def main():
         print(json.dumps({"kmeans": kmeans_bench(A, synth, torch, timer)}), flush=True)
         return
     if args.only_program:
-        print(json.dumps({"program": program_bench(A, synth, torch, timer, args.program_log2n, args.program_cost)}),
+        print(json.dumps({"program": program_bench(A, synth, torch, timer, args.program_log2n, args.program_cost,
+                                                   args.cap_bytes)}),
               flush=True)
         return
     n = 1 << args.log2n
@@ -694,7 +749,7 @@ def main():
         torch.cuda.empty_cache()
         if not args.skip_program:
             try:
-                line["program"] = program_bench(A, synth, torch, timer, args.program_log2n)
+                line["program"] = program_bench(A, synth, torch, timer, args.program_log2n, cap_bytes=args.cap_bytes)
             except Exception as e:  # report, keep the main line
                 line["program"] = {"error": repr(e)}
             torch.cuda.empty_cache()
