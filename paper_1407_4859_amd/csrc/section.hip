@@ -316,24 +316,35 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) {
 //    fold is straight-line code: an off-grid neighbour's term is computed
 //    and not selected, instead of branching on the field types per term
 //    (the generic fold spends tens of scalar instructions per term on them);
-//  * EXACT: the section reads exactly MAXR fields, so no load is guarded.
+//  * EXACT: the section reads exactly MAXR fields, so no load is guarded;
+//  * DEG > 0: the stencil has exactly DEG neighbours, taken in one batch
+//    (a 7-point stencil in batches of 8 would load an eighth, unused one);
+//  * ROW: nx is a multiple of 64, so the 64 records of a wave lie in one
+//    grid row and share y and z: those two tests are scalar, and only x is
+//    tested per lane.
 // The load phase has no branches: a neighbour past the degree or off the
 // grid loads the record's own fields and is not selected, and the grid test
 // uses no short-circuit operators, so all loads of a batch stay in flight.
-template <int MAXR, bool W8, bool LIN, bool F32, bool EXACT>
+template <int MAXR, bool W8, bool LIN, bool F32, bool EXACT, int DEG = 0, bool ROW = false>
 __global__ __launch_bounds__(256) void stencil_kernel(const SectionArgs a) {
   const uint64_t i = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
   if (i >= (uint64_t)a.n) return;
   const uint32_t nr = EXACT ? (uint32_t)MAXR : a.n_read, nw = a.n_write;
   Acc acc[2];
   acc[0] = acc[1] = Acc{0.0f, 0.0, 0u};
-  constexpr int NB = MAXR >= 32 ? 1 : (MAXR <= 4 ? 8 : 32 / MAXR);
-  static_assert(ADHA_MAX_DEGREE % NB == 0, "batches must tile the offset tables");
-  const int deg = (int)a.degree;
+  constexpr int NB = DEG > 0 ? DEG : (MAXR >= 32 ? 1 : (MAXR <= 4 ? 8 : 32 / MAXR));
+  static_assert(DEG > 0 ? DEG <= ADHA_MAX_DEGREE : ADHA_MAX_DEGREE % NB == 0,
+                "batches must tile the offset tables");
+  const int deg = DEG > 0 ? DEG : (int)a.degree;
   // grid coordinates of record i
   const int32_t ii = (int32_t)i;
   const int32_t x = ii % (int32_t)a.nx, t = ii / (int32_t)a.nx;
-  const int32_t y = t % (int32_t)a.ny, z = t / (int32_t)a.ny;
+  int32_t y = t % (int32_t)a.ny, z = t / (int32_t)a.ny;
+  if constexpr (ROW) {
+    // N is a multiple of nx, hence of 64: every wave is full and in one row
+    y = __builtin_amdgcn_readfirstlane(y);
+    z = __builtin_amdgcn_readfirstlane(z);
+  }
   uint32_t own[LIN ? MAXR : 1];
   if constexpr (LIN) {
 #pragma unroll
@@ -344,8 +355,9 @@ __global__ __launch_bounds__(256) void stencil_kernel(const SectionArgs a) {
     bool ok[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      // NB divides ADHA_MAX_DEGREE, so jj stays inside the offset tables;
-      // their entries past the degree are zero and not selected
+      // NB divides ADHA_MAX_DEGREE (or is the exact degree), so jj stays
+      // inside the offset tables; entries past the degree are zero and not
+      // selected
       const int jj = j0 + b;
       // a coordinate off the grid wraps to a large unsigned value
       ok[b] = (j0 + b < deg) & ((uint32_t)(x + a.off[jj][0]) < a.nx) & ((uint32_t)(y + a.off[jj][1]) < a.ny) &
@@ -559,8 +571,28 @@ static SField sfield(const LayoutDesc &l, int f) {
   return s;
 }
 
+template <bool LIN, int DEG, bool ROW>
+static void launch_stencil_f32_exact(uint32_t nr, dim3 grid, const SectionArgs &a, hipStream_t st) {
+  if (nr == 1) hipLaunchKernelGGL((stencil_kernel<1, false, LIN, true, true, DEG, ROW>), grid, dim3(256), 0, st, a);
+  else if (nr == 2) hipLaunchKernelGGL((stencil_kernel<2, false, LIN, true, true, DEG, ROW>), grid, dim3(256), 0, st, a);
+  else if (nr == 3) hipLaunchKernelGGL((stencil_kernel<3, false, LIN, true, true, DEG, ROW>), grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((stencil_kernel<4, false, LIN, true, true, DEG, ROW>), grid, dim3(256), 0, st, a);
+}
+
 template <bool W8, bool LIN, bool F32>
 static void launch_stencil(uint32_t nr, dim3 grid, const SectionArgs &a, hipStream_t st) {
+  if constexpr (F32 && LIN) {
+    // the common small stencils: exact field count, 7 neighbours, rows of a
+    // multiple of 64 records
+    if (nr >= 1 && nr <= 4) {
+      const bool row = a.nx % 64 == 0, d7 = a.degree == 7;
+      if (row && d7) launch_stencil_f32_exact<true, 7, true>(nr, grid, a, st);
+      else if (row) launch_stencil_f32_exact<true, 0, true>(nr, grid, a, st);
+      else if (d7) launch_stencil_f32_exact<true, 7, false>(nr, grid, a, st);
+      else launch_stencil_f32_exact<true, 0, false>(nr, grid, a, st);
+      return;
+    }
+  }
   if constexpr (F32) {
     // exact field counts for the small stencils (the common case)
     if (nr == 1) {

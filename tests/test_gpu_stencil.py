@@ -34,8 +34,10 @@ def _program(st, grid, extra=True):
     return secs
 
 
-@pytest.mark.parametrize("grid", [(7, 5, 3), (33, 17, 9)])
+@pytest.mark.parametrize("grid", [(7, 5, 3), (33, 17, 9), (64, 3, 5), (128, 2, 3)])
 def test_stencils_match_oracle(ctx, grid):
+    """Grids whose rows are a multiple of 64 records take the row-aligned
+    kernel forms; the others the general ones."""
     n = grid[0] * grid[1] * grid[2]
     spec = synth.StructSpec(n, [synth.F32] * 9, [4] * 9)
     st = A.Struct.from_spec(spec)
