@@ -308,10 +308,10 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) {
 //  * LIN: every read field sits in a group with T = 1, where a field's
 //    address is linear in the record index (base + r*S + p), so a
 //    neighbour's field is the record's own field offset plus the offset's
-//    record step times S, a workgroup-uniform number.  The launch takes this
-//    form only when the layout fits in 4 GiB and every such step in 31 bits,
-//    so offsets are 32-bit and one neighbour's field costs a select and an
-//    add;
+//    record step times S.  The launch takes this form only when the layout
+//    fits in 4 GiB, every such product in 31 bits, and steps and S in 24
+//    signed bits, so offsets are 32-bit and one neighbour's field costs one
+//    24-bit multiply-add;
 //  * F32: every read and write field is F32 (W8 is then false), and the
 //    fold is straight-line code: an off-grid neighbour's term is computed
 //    and not selected, instead of branching on the field types per term
@@ -363,13 +363,14 @@ __global__ __launch_bounds__(256) void stencil_kernel(const SectionArgs a) {
       ok[b] = (j0 + b < deg) & ((uint32_t)(x + a.off[jj][0]) < a.nx) & ((uint32_t)(y + a.off[jj][1]) < a.ny) &
               ((uint32_t)(z + a.off[jj][2]) < a.nz);
       if constexpr (LIN) {
-        const int32_t lin = a.lin[jj];
+        // the neighbour's record step (0 when it is not taken) times each
+        // field's record bytes: both fit in 24 signed bits (checked at
+        // launch), so one 24-bit multiply-add per field
+        const int32_t d = ok[b] ? a.lin[jj] : 0;
 #pragma unroll
         for (int q = 0; q < MAXR; ++q)
-          if (q < (int)nr) {
-            const int32_t step = lin * (int32_t)a.rd[q].TS;
-            w[b].load_at(q, a.buf + (own[q] + (uint32_t)(ok[b] ? step : 0)), a.rd[q]);
-          }
+          if (q < (int)nr)
+            w[b].load_at(q, a.buf + (own[q] + (uint32_t)__mul24(d, (int32_t)a.rd[q].TS)), a.rd[q]);
       } else {
         const uint64_t rr = ok[b] ? (uint64_t)(ii + a.lin[jj]) : i;
 #pragma unroll
@@ -1072,9 +1073,10 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
         bool w8 = false, lin = l.nbytes <= (1ull << 32), f32 = true;
         int64_t max_lin = 0;
         for (uint32_t j = 0; j < sec.degree; ++j) max_lin = std::max<int64_t>(max_lin, std::abs((int64_t)a.lin[j]));
+        lin &= max_lin < (1 << 23);
         for (uint32_t q = 0; q < nr; ++q) {
           w8 |= a.rd[q].e == 8;
-          lin &= a.rd[q].logT == 0 && max_lin * (int64_t)a.rd[q].TS < (int64_t(1) << 31);
+          lin &= a.rd[q].logT == 0 && a.rd[q].TS < (1u << 23) && max_lin * (int64_t)a.rd[q].TS < (int64_t(1) << 31);
           f32 &= a.rd[q].dt == ADHA_F32;
         }
         for (uint32_t k = 0; k < a.n_write; ++k) f32 &= a.wr[k].dt == ADHA_F32;
