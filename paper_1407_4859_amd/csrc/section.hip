@@ -41,6 +41,8 @@ struct SectionArgs {
   SField wr[ADHA_MAX_WRITE];
   // stencils: neighbours at grid offsets (x, y, z) instead of idx
   uint32_t stencil, nx, ny, nz;
+  // r / nx and r / ny for r < 2^31 as (r * m) >> s (m < 2^32, set at launch)
+  uint32_t mx, sx, my, sy;
   int32_t off[ADHA_MAX_DEGREE][3];
   int32_t lin[ADHA_MAX_DEGREE];  // the same offsets as record-index steps
 };
@@ -336,10 +338,12 @@ __global__ __launch_bounds__(256) void stencil_kernel(const SectionArgs a) {
   static_assert(DEG > 0 ? DEG <= ADHA_MAX_DEGREE : ADHA_MAX_DEGREE % NB == 0,
                 "batches must tile the offset tables");
   const int deg = DEG > 0 ? DEG : (int)a.degree;
-  // grid coordinates of record i
+  // grid coordinates of record i (a multiply and a shift per division)
   const int32_t ii = (int32_t)i;
-  const int32_t x = ii % (int32_t)a.nx, t = ii / (int32_t)a.nx;
-  int32_t y = t % (int32_t)a.ny, z = t / (int32_t)a.ny;
+  const uint32_t t = (uint32_t)(((uint64_t)(uint32_t)ii * a.mx) >> a.sx);
+  const int32_t x = ii - (int32_t)(t * a.nx);
+  int32_t z = (int32_t)(((uint64_t)t * a.my) >> a.sy);
+  int32_t y = (int32_t)t - z * (int32_t)a.ny;
   if constexpr (ROW) {
     // N is a multiple of nx, hence of 64: every wave is full and in one row
     y = __builtin_amdgcn_readfirstlane(y);
@@ -348,7 +352,8 @@ __global__ __launch_bounds__(256) void stencil_kernel(const SectionArgs a) {
   uint32_t own[LIN ? MAXR : 1];
   if constexpr (LIN) {
 #pragma unroll
-    for (int q = 0; q < MAXR; ++q) own[q] = q < (int)nr ? (uint32_t)faddr(a.rd[q], i) : 0u;
+    for (int q = 0; q < MAXR; ++q)
+      own[q] = q < (int)nr ? (uint32_t)a.rd[q].base + a.rd[q].pT + (uint32_t)i * a.rd[q].TS : 0u;
   }
   for (int j0 = 0; j0 < deg; j0 += NB) {
     Words<MAXR, W8> w[NB];
@@ -1011,6 +1016,17 @@ static adha_status reduce_launch(Ctx *ctx, const SectionDesc &sec, const LayoutD
   return ADHA_OK;
 }
 
+// Division by d >= 1 of any r < 2^31 as (r * m) >> s: with l = ceil(log2 d),
+// m = ceil(2^(31+l) / d) < 2^32 and s = 31 + l.  m / 2^s exceeds 1/d by less
+// than 2^-(31+l), so r * m / 2^s exceeds r / d by less than 2^-l <= 1/d,
+// which never carries past the next integer: the floor is r / d exactly.
+static void magic_div(uint32_t d, uint32_t *m, uint32_t *s) {
+  uint32_t l = 0;
+  while ((uint64_t(1) << l) < d) ++l;
+  *m = (uint32_t)(((uint64_t(1) << (31 + l)) + d - 1) / d);
+  *s = 31 + l;
+}
+
 // A reduction over no records writes a table of zeros.
 __global__ void zero_u64_kernel(uint64_t *p, uint32_t n) {
   const uint32_t i = blockIdx.x * 256u + threadIdx.x;
@@ -1047,6 +1063,8 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
     a.nx = sec.nx;
     a.ny = sec.ny;
     a.nz = sec.nz;
+    magic_div(sec.nx, &a.mx, &a.sx);
+    magic_div(sec.ny, &a.my, &a.sy);
     for (uint32_t j = 0; j < sec.degree; ++j) {
       for (int c = 0; c < 3; ++c) a.off[j][c] = sec.offsets[3 * j + c];
       a.lin[j] = a.off[j][0] + (int32_t)sec.nx * (a.off[j][1] + (int32_t)sec.ny * a.off[j][2]);
