@@ -287,7 +287,7 @@ def kmeans_bench(A, synth, torch, timer, log2n=23):
                      ("all_soa", A.Plan.uniform(prog, soa_l))):
         first = pl.candidate(pl.choices()[0])
         load(first)      # runs start from the plan's first layout and leave buf_a's keys as they are
-        ms, _ = timer.time(lambda: A.run(ctx, pl, first, buf_a, buf_b), reps=5, warm=1)
+        ms = back_to_back_ms(timer, lambda: A.run(ctx, pl, first, buf_a, buf_b))
         res[name + "_ms"] = round(ms, 3)
         res[name + "_choices"] = pl.choices()
     ctx.check()
@@ -296,7 +296,7 @@ def kmeans_bench(A, synth, torch, timer, log2n=23):
     for s, sec in enumerate((gen, red)):
         for lname, lay in (("planned", plan.candidate(plan.choices()[s])), ("aos", aos_l), ("soa", soa_l)):
             load(lay)
-            ms, _ = timer.time(lambda: A.section_run(ctx, sec, lay, buf_a), reps=7, warm=1)
+            ms = back_to_back_ms(timer, lambda: A.section_run(ctx, sec, lay, buf_a))
             per.append({"section": s, "layout": lname, "us": round(ms * 1e3, 1),
                         "alg_GBps": round(sec.bytes / (ms * 1e6), 1)})
     ctx.check()
@@ -330,7 +330,7 @@ def medical_bench(A, synth, torch, timer, side=256):
            "candidates": plan.n_candidates, "plan_seconds": round(plan_s, 2)}
     for name, pl in (("adha", plan), ("all_aos", A.Plan.uniform(prog, aos_l)), ("all_soa", A.Plan.uniform(prog, soa_l))):
         first = pl.candidate(pl.choices()[0])
-        ms, _ = timer.time(lambda: A.run(ctx, pl, first, buf_a, buf_b), reps=5, warm=1)
+        ms = back_to_back_ms(timer, lambda: A.run(ctx, pl, first, buf_a, buf_b))
         res[name + "_ms"] = round(ms, 3)
         res[name + "_choices"] = pl.choices()
     ctx.check()
@@ -338,7 +338,7 @@ def medical_bench(A, synth, torch, timer, side=256):
     per = []
     for s, (sec, c) in enumerate(zip(ss, plan.choices())):
         for lname, lay in (("planned", plan.candidate(c)), ("aos", aos_l), ("soa", soa_l)):
-            ms, _ = timer.time(lambda: A.section_run(ctx, sec, lay, buf_a), reps=7, warm=1)
+            ms = back_to_back_ms(timer, lambda: A.section_run(ctx, sec, lay, buf_a))
             per.append({"section": s, "stencil": sec.degree > 0, "layout": lname, "us": round(ms * 1e3, 1),
                         "alg_GBps": round(sec.bytes / (ms * 1e6), 1),
                         "eff_GBps": round(sec.effective_bytes(lay) / (ms * 1e6), 1)})
@@ -539,6 +539,14 @@ def batched_bench(A, synth, torch, timer):
             "separate_launches_ms": round(s_ms, 3), "graph_GBps": round(total / g_ms / 1e6, 1),
             "separate_GBps": round(total / s_ms / 1e6, 1),
             "graph_frac_of_peak": round(total / g_ms / 1e6 / HBM_PEAK_GBS, 3)}
+
+
+def back_to_back_ms(timer, fn, inner=10, reps=5):
+    """Milliseconds per call of fn over `inner` calls between two events:
+    for programs of a few hundred microseconds the host work of one call
+    then overlaps the GPU work of the previous one, as in a loop."""
+    ms, _ = timer.time(lambda: [fn() for _ in range(inner)], reps=reps, warm=1)
+    return ms / inner
 
 
 def subdword_bench(A, torch, timer, log2n=25):
