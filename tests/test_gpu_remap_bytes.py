@@ -119,10 +119,20 @@ def test_batched_mixes_byte_and_dword_structs(ctx):
                          want=oracle.remap(OA, src_h, OB),
                          dst=torch.full((OB.nbytes,), 0xA5, dtype=torch.uint8, device="cuda")))
     say("byte batched", len(arrs))
-    A.remap_batched(ctx, [(a["la"], a["src"], a["lb"], a["dst"]) for a in arrs], 0)
+    batch = A.BatchItems([(a["la"], a["src"], a["lb"], a["dst"]) for a in arrs])
+    A.remap_batched(ctx, batch, 0)
     ctx.check()
     for i, a in enumerate(arrs):
         assert first_diff(host(a["dst"], a["OB"].nbytes), a["want"]) is None, i
+    for rep in range(2):                    # graph replays, with eager work between them
+        for a in arrs:
+            a["dst"].fill_(0x3C)
+        torch.cuda.synchronize()
+        say("byte batched graph replay", rep)
+        A.remap_batched(ctx, batch, A.BATCH_GRAPH)
+        ctx.check()
+        for i, a in enumerate(arrs):
+            assert first_diff(host(a["dst"], a["OB"].nbytes), a["want"]) is None, (rep, i)
 
 
 @pytest.mark.timeout(600)
