@@ -40,7 +40,11 @@ static adha_status median_us(hipStream_t stream, uint32_t reps, Fn fn, double *o
 }
 
 static const uint32_t kTileBytes[] = {4096, 8192, 16384, 32768};
-static const uint32_t kWgPerCu[] = {1, 2, 4, 8, 16};
+static const uint32_t kWgPerCu[] = {1, 2, 4, 8, 16, 32};
+// A batch mixes arrays whose tiles hold different byte counts; more
+// workgroups than fit at once let the ones that finish early take the rest,
+// so the batch policy also tries 64 per CU.
+static const uint32_t kBatchWgPerCu[] = {1, 2, 4, 8, 16, 32, 64};
 
 static void to_abi(const TileShape &s, adha_tile_shape *o) {
   o->tile_records = s.R;
@@ -124,7 +128,7 @@ adha_status adha_tune_batched(adha_ctx *ctx, uint32_t n, const adha_remap_item *
   Ctx::BatchPolicy bp = c->batch;
   double bt = t_def;
   for (uint32_t tb : kTileBytes)
-    for (uint32_t wg : kWgPerCu)
+    for (uint32_t wg : kBatchWgPerCu)
       for (uint32_t order = 0; order < 2; ++order)
         for (uint32_t nt = 0; nt < 2; ++nt) {
           c->batch.tile_bytes = tb;
@@ -195,7 +199,7 @@ adha_status adha_tune_load(adha_ctx *ctx, const char *path) {
     return fail(ADHA_ERR_IO, "%s failed its checksum", path);
   Ctx::BatchPolicy bp;
   if (sscanf(lines[1].c_str(), "batch %u %u %u %u", &bp.tile_bytes, &bp.wg_per_cu, &bp.strided, &bp.nt) != 4 ||
-      bp.wg_per_cu == 0 || bp.wg_per_cu > 32 || bp.strided > 1 || bp.nt > 1)
+      bp.wg_per_cu == 0 || bp.wg_per_cu > 64 || bp.strided > 1 || bp.nt > 1)
     return fail(ADHA_ERR_IO, "%s: bad batch line", path);
   std::map<std::string, TileShape> db;
   for (size_t i = 2; i + 1 < lines.size(); ++i) {
