@@ -87,6 +87,29 @@ def test_stencils_with_mixed_types_and_wide_reads(ctx, grid):
         assert np.array_equal(host(dev, O.nbytes), want), (grid, O)
 
 
+@pytest.mark.parametrize("grid", [(1000, 999, 3), (321, 1023, 7)])
+def test_stencil_on_large_irregular_grids(ctx, grid):
+    """Millions of records on grids whose sides are not powers of two: the
+    kernel's multiply-shift division for the grid coordinates against the
+    oracle's neighbour array, every record, on SoA (linear form) and on a
+    tiled layout (general form)."""
+    n = grid[0] * grid[1] * grid[2]
+    spec = synth.StructSpec(n, [synth.F32] * 5, [4] * 5)
+    st = A.Struct.from_spec(spec)
+    cols = synth.record_matrix(17, n, spec.dtypes, spec.elem_bytes)
+    rd, wr = [0, 1, 2], [3]
+    idx = oracle.stencil_index(*grid, synth.STENCIL7)
+    sec = A.Section.stencil(st, rd, wr, grid, synth.STENCIL7)
+    for O in (osoa(n, spec.elem_bytes), OLayout(n, spec.elem_bytes, [0] * 5, [64])):
+        want = oracle.pack(O, cols)
+        oracle.section(O, spec.dtypes, synth.OP_GEN, rd, wr, 7, idx, want)
+        dev = dev_bytes(oracle.pack(O, cols))
+        say("stencil large", grid, O)
+        A.section_run(ctx, sec, mirror(st, O), dev)
+        ctx.check()
+        assert np.array_equal(host(dev, O.nbytes), want), (grid, O)
+
+
 @pytest.mark.timeout(900)
 def test_medical_program_full_size(ctx):
     """The Medical-shaped program on a 256^3 image: planned, all-AoS and
