@@ -499,7 +499,8 @@ def hetero_bench(A, synth, torch):
                "predicted_us": round(plan.cost, 1), "plan_s": round(plan_s, 2),
                "planned_us": round(timed(plan), 1), "all_gpu_us": round(timed(gpu), 1),
                "all_host_us": round(timed(host_only), 1)}
-        row["planned_not_worse"] = row["planned_us"] <= 1.1 * min(row["all_gpu_us"], row["all_host_us"])
+        best = min(row["all_gpu_us"], row["all_host_us"])
+        row["planned_vs_best_single_device"] = round(row["planned_us"] / best, 3)
         ctx.check()
         rows.append(row)
         log("hetero:", row)
