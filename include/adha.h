@@ -125,10 +125,10 @@ typedef enum {
   /* reductions: workgroups per compute unit in the first pass (1..32,
    * default 8) */
   ADHA_OPT_REDUCE_WG_PER_CU = 2,
-  /* reductions: LDS bytes a workgroup may spend on copies of the table
-   * (1024..65536, default 12288); more copies mean fewer lanes adding to
-   * one LDS cell at once */
-  ADHA_OPT_REDUCE_LDS_BYTES = 3,
+  /* reductions: 1 (default) compensated double-double sums of floating-
+   * point columns; 0 plain double sums (same fixed order, faster, error up
+   * to about (m-1) * 2^-53 * sum|x| for m values) */
+  ADHA_OPT_REDUCE_COMPENSATED = 3,
   /* host backend threads (0: one per core, at most 64; up to 256) */
   ADHA_OPT_HOST_THREADS = 4
 } adha_option;
@@ -280,15 +280,24 @@ adha_status adha_section_create_stencil(const adha_struct *s, uint32_t n_read, c
  * n_keys rows of n_read + 1 eight-byte cells, written to the device array
  * `out` (caller-owned, 256-byte aligned, out_cap >= n_keys*(n_read+1)*8):
  *   cell [k][j], j < n_read: the sum over those records of read field j
- *     (ascending id): an IEEE double for F32/F64 fields, accumulated in
- *     double; a two's-complement int64 for I32 fields (exact);
+ *     (ascending id): an IEEE double for F32/F64 fields; a two's-complement
+ *     int64 for I32 fields (exact);
  *   cell [k][n_read]: the number of those records (uint64).
  * Without a key every record has key 0 and n_keys must be 1.  Records whose
  * key is outside [0, n_keys) are left out and reported by adha_ctx_check.
- * Double sums are exact when every partial sum is a double (for example
- * F32 values that are multiples of 2^-23 with partial sums below 2^30 in
- * magnitude); otherwise they lie within (m-1)*2^-53 * sum|x| of the exact
- * sum of the m values (any summation order).
+ * Floating-point sums are compensated: each thread keeps its rounded sum
+ * and the exact rounding errors, and partial sums are combined as
+ * double-double numbers, in an order fixed by N, n_keys, n_read and the
+ * device's CU count -- repeated runs give the same bits, and no
+ * floating-point atomics are used.  The cell holds the double nearest the
+ * double-double result.  For a cell with exact sum S and A = sum|x| over
+ * its values, that result is within 2^-92 * A of S when n_keys <= 8 and
+ * N <= 2^26 (more keys add at most 2^-105 * A per record of one workgroup),
+ * so the cell is within 1 ulp of S correctly rounded whenever
+ * A <= 2^38 * |S| in that range.  An exact zero sum is +0.0.  Values must be
+ * finite, with partial sums below 2^1023 in magnitude.  Option
+ * ADHA_OPT_REDUCE_COMPENSATED = 0 switches to plain double sums in the same
+ * order (error up to (m-1) * 2^-53 * A for m values).
  * n_keys*(n_read+1) <= ADHA_MAX_REDUCE_CELLS.  The key may not be read.
  * Each run overwrites the whole table; `out` must not overlap the data. */
 adha_status adha_section_create_reduce(const adha_struct *s, uint32_t n_read, const int32_t *read,

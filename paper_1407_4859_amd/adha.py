@@ -27,7 +27,7 @@ COST_MEASURED, COST_ANALYTIC, COST_LEARNED = 0, 1, 2
 CAT_AOS_SOA, CAT_FULL = 0, 1
 INIT_FREE, INIT_AOS, INIT_HOST_AOS = 0, 1, 2
 BATCH_GRAPH, BATCH_SEPARATE = 1, 2
-OPT_SPAN_GATHER, OPT_REDUCE_WG_PER_CU, OPT_REDUCE_LDS_BYTES, OPT_HOST_THREADS = 1, 2, 3, 4
+OPT_SPAN_GATHER, OPT_REDUCE_WG_PER_CU, OPT_REDUCE_COMPENSATED, OPT_HOST_THREADS = 1, 2, 3, 4
 DEVICES_GPU, DEVICES_GPU_HOST = 0, 1
 N_FEATURES = 16
 MLP_PARAMS = 64 * 16 + 64 + 64 * 64 + 64 + 64 * 64 + 64 + 64 + 1

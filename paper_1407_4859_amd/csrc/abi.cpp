@@ -17,6 +17,16 @@ Ctx::~Ctx() {
   for (auto &kv : remap_cache)
     if (kv.second.dev) (void)hipFree(kv.second.dev);
   if (err_flag) (void)hipFree(err_flag);
+  if (reduce_partials) (void)hipFree(reduce_partials);
+}
+
+adha_status ctx_reduce_scratch(Ctx *ctx) {
+  if (ctx->reduce_partials) return ADHA_OK;
+  if (hipMalloc(&ctx->reduce_partials, kReducePartialPairs * 16) != hipSuccess) {
+    ctx->reduce_partials = nullptr;
+    return fail(ADHA_ERR_OOM, "reduction scratch of %llu bytes failed", (unsigned long long)(kReducePartialPairs * 16));
+  }
+  return ADHA_OK;
 }
 
 static bool aligned(const void *p) { return ((uintptr_t)p & 255u) == 0; }
@@ -255,9 +265,9 @@ adha_status adha_ctx_set_option(adha_ctx *ctx, adha_option opt, int64_t value) {
       if (value < 0 || value > 256) return fail(ADHA_ERR_INVALID, "host threads %lld not in [0, 256]", (long long)value);
       ctx->c.host_threads = (uint32_t)value;
       return ADHA_OK;
-    case ADHA_OPT_REDUCE_LDS_BYTES:
-      if (value < 1024 || value > 65536) return fail(ADHA_ERR_INVALID, "LDS bytes %lld not in [1024, 65536]", (long long)value);
-      ctx->c.reduce_lds_bytes = (uint32_t)value;
+    case ADHA_OPT_REDUCE_COMPENSATED:
+      if (value != 0 && value != 1) return fail(ADHA_ERR_INVALID, "compensated-reduction option is 0 or 1");
+      ctx->c.reduce_plain = value == 0;
       return ADHA_OK;
     default:
       return fail(ADHA_ERR_INVALID, "unknown option %d", (int)opt);

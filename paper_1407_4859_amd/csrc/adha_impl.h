@@ -187,8 +187,25 @@ adha_status prepared_for(Ctx *ctx, const adha_layout *a, const adha_layout *b, c
                          const RemapPrepared **out);
 
 // ------------------------------------------------------------------ sections
+// scratch: device memory for a reduction's per-workgroup partials (at least
+// kReducePartialPairs * 16 bytes); NULL = the context's own.
 adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l, void *buf,
-                           const int32_t *idx, hipStream_t stream, void *out_override = nullptr);
+                           const int32_t *idx, hipStream_t stream, void *out_override = nullptr,
+                           void *scratch = nullptr);
+
+// Reductions: pass 1 writes one partial table of (double, double) pairs per
+// workgroup; workgroups x cells never exceeds this many pairs (16 MiB).
+static const uint64_t kReducePartialPairs = 1ull << 20;
+struct ReducePlan {
+  uint32_t keys_in_regs = 0;  // 1..8: register form with that many key rows; 0: LDS form
+  uint32_t slices = 1;        // column slices (gridDim.y) of the register form
+  uint32_t groups = 1;        // workgroups per slice
+  size_t lds = 0;             // dynamic LDS of the LDS form
+  uint64_t partial_bytes = 0;
+};
+ReducePlan reduce_plan(const Ctx *ctx, const SectionDesc &sec, int64_t n);
+adha_status reduce_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l, const void *buf, void *out,
+                          uint64_t *partials, uint64_t partial_cap, hipStream_t stream);
 
 // ------------------------------------------------------------------ host backend
 uint32_t host_threads(const Ctx *ctx);
@@ -234,11 +251,15 @@ struct Ctx {
   bool has_model = false;
   bool no_span = false;      // gathers always take the per-field path
   uint32_t reduce_wg_per_cu = 8;     // reductions: first-pass workgroups per CU
-  uint32_t reduce_lds_bytes = 12288; // reductions: LDS for table copies
+  bool reduce_plain = false;         // reductions: plain double sums instead of compensated ones
+  void *reduce_partials = nullptr;   // reductions: kReducePartialPairs * 16 bytes, allocated on first use
   uint32_t host_threads = 0;         // host backend threads (0: one per core, at most 64)
   uint64_t host_bad = 0;             // out-of-range indices / keys met by host sections
   ~Ctx();
 };
+
+// Allocates the context's reduction partials once (no-op when present).
+adha_status ctx_reduce_scratch(Ctx *ctx);
 
 // Switches to the context's device for the lifetime of the guard.
 struct DeviceGuard {

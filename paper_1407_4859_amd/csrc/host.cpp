@@ -9,7 +9,8 @@
 // field's type (this file is compiled without contraction into fused
 // multiply-adds, and x86-64 evaluates float and double in their own
 // precision).  Records are split into contiguous ranges over host threads;
-// a reduction adds the threads' tables in thread order.
+// a reduction adds the threads' tables in thread order, with the device's
+// compensated summation.
 #include <algorithm>
 #include <atomic>
 #include <condition_variable>
@@ -28,7 +29,11 @@ namespace {
 // A process-wide pool of host threads, started on first use and kept until
 // exit (starting threads per call costs far more than the small sections it
 // would run).  One job at a time: its parts are taken from a counter by the
-// workers and by the calling thread.
+// workers and by the calling thread.  A worker takes its copy of the job
+// (function, part count) under the lock and counts itself active; run()
+// returns only when every part is done and no worker is active, so no
+// worker can still be inside one job, or claim a part of it, once the next
+// job has been published.
 class HostPool {
  public:
   static HostPool &get() {
@@ -47,9 +52,9 @@ class HostPool {
       ++gen_;
     }
     cv_.notify_all();
-    work();
+    work(fn, parts);
     std::unique_lock<std::mutex> lk(m_);
-    done_cv_.wait(lk, [&] { return done_.load() == parts_; });
+    done_cv_.wait(lk, [&] { return done_.load() == parts && active_ == 0; });
     job_ = nullptr;
   }
   ~HostPool() {
@@ -67,35 +72,42 @@ class HostPool {
     const uint32_t n = std::max(1u, std::min(hw ? hw : 1u, 256u)) - 1;
     for (uint32_t k = 0; k < n; ++k) workers_.emplace_back([this] { loop(); });
   }
-  void work() {
+  void work(const std::function<void(uint32_t)> &fn, uint32_t parts) {
     for (;;) {
       const uint32_t p = next_.fetch_add(1);
-      if (p >= parts_) return;
-      (*job_)(p);
-      if (done_.fetch_add(1) + 1 == parts_) {
-        std::lock_guard<std::mutex> lk(m_);
-        done_cv_.notify_all();
-      }
+      if (p >= parts) return;
+      fn(p);
+      done_.fetch_add(1);
     }
   }
   void loop() {
     uint64_t seen = 0;
     for (;;) {
+      const std::function<void(uint32_t)> *job;
+      uint32_t parts;
       {
         std::unique_lock<std::mutex> lk(m_);
-        cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+        cv_.wait(lk, [&] { return stop_ || (gen_ != seen && job_ != nullptr); });
         if (stop_) return;
         seen = gen_;
-        if (!job_) continue;
+        job = job_;
+        parts = parts_;
+        ++active_;
       }
-      work();
+      work(*job, parts);
+      {
+        std::lock_guard<std::mutex> lk(m_);
+        --active_;
+      }
+      done_cv_.notify_all();
     }
   }
   std::vector<std::thread> workers_;
   std::mutex m_, run_m_;
   std::condition_variable cv_, done_cv_;
-  const std::function<void(uint32_t)> *job_ = nullptr;
-  uint32_t parts_ = 0;
+  const std::function<void(uint32_t)> *job_ = nullptr;  // guarded by m_
+  uint32_t parts_ = 0;                                  // guarded by m_
+  uint32_t active_ = 0;                                 // workers inside work(); guarded by m_
   std::atomic<uint32_t> next_{0}, done_{0};
   uint64_t gen_ = 0;
   bool stop_ = false;
@@ -112,6 +124,34 @@ void parallel_ranges(int64_t n, uint32_t threads, Fn fn) {
   }
   const std::function<void(uint32_t)> part = [&](uint32_t k) { fn(k, n * k / t, n * (k + 1) / t); };
   HostPool::get().run(t, part);
+}
+
+// Reductions sum floating-point columns as the device does: per thread a
+// pair (s, c), s the rounded running sum and c collecting the exact rounding
+// errors (TwoSum), and the threads' pairs added in thread order as
+// double-double numbers; the result is the double nearest the final pair.
+inline void two_sum(double a, double b, double *s, double *e) {
+  const double t = a + b;
+  const double bb = t - a;
+  *e = (a - (t - bb)) + (b - bb);
+  *s = t;
+}
+
+// A host thread's chain is a whole record range, so the pair is renormalised
+// after every value (the error then grows with the chain's length, not with
+// its square).
+inline void comp_add(double &s, double &c, double v) {
+  double e;
+  two_sum(s, v, &s, &e);
+  two_sum(s, c + e, &s, &c);
+}
+
+inline void pair_add(double a1, double a2, double b1, double b2, double *hi, double *lo) {
+  double s, e, t, f, s2, e3;
+  two_sum(a1, b1, &s, &e);
+  two_sum(a2, b2, &t, &f);
+  two_sum(s, e + t, &s2, &e3);
+  two_sum(s2, e3 + f, hi, lo);
 }
 
 inline uint64_t read_term(const uint8_t *buf, const LayoutDesc &l, int64_t r, int f) {
@@ -197,8 +237,10 @@ adha_status host_section_run(uint32_t threads, const SectionDesc &sec, const Lay
   if (sec.op == ADHA_OP_REDUCE) {
     const uint32_t cols = (uint32_t)nr + 1, cells = sec.reduce_cells();
     const uint32_t t = std::max<uint32_t>(1, threads);
-    // per thread: double sums for floating-point columns, uint64 for the rest
+    // per thread: compensated pairs (s, c) for floating-point columns (c in
+    // cs), uint64 for the rest
     std::vector<std::vector<double>> fs(t, std::vector<double>(cells, 0.0));
+    std::vector<std::vector<double>> cs(t, std::vector<double>(cells, 0.0));
     std::vector<std::vector<uint64_t>> us(t, std::vector<uint64_t>(cells, 0));
     parallel_ranges(n, t, [&](uint32_t k, int64_t b, int64_t e) {
       for (int64_t r = b; r < e; ++r) {
@@ -213,7 +255,7 @@ adha_status host_section_run(uint32_t threads, const SectionDesc &sec, const Lay
           const int f = sec.rd[q];
           const uint64_t v = read_term(buf, l, r, f);
           if (l.shape.dtype[f] == ADHA_I32) us[k][row + q] += (uint64_t)(int64_t)(int32_t)(uint32_t)v;
-          else fs[k][row + q] += as_f64(l.shape.dtype[f], v);
+          else comp_add(fs[k][row + q], cs[k][row + q], as_f64(l.shape.dtype[f], v));
         }
         us[k][row + nr] += 1;
       }
@@ -223,9 +265,9 @@ adha_status host_section_run(uint32_t threads, const SectionDesc &sec, const Lay
       const uint32_t q = c % cols;
       const bool fp = q < nr && l.shape.dtype[sec.rd[q]] != ADHA_I32;
       if (fp) {
-        double s = 0.0;
-        for (uint32_t k = 0; k < t; ++k) s += fs[k][c];
-        std::memcpy(&out[c], &s, 8);
+        double hi = 0.0, lo = 0.0;
+        for (uint32_t k = 0; k < t; ++k) pair_add(hi, lo, fs[k][c], cs[k][c], &hi, &lo);
+        std::memcpy(&out[c], &hi, 8);
       } else {
         uint64_t s = 0;
         for (uint32_t k = 0; k < t; ++k) s += us[k][c];

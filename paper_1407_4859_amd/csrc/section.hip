@@ -650,38 +650,81 @@ static void launch_maxr(uint32_t nr, dim3 grid, const SectionArgs &a, hipStream_
 
 // ------------------------------------------------------------ reductions
 // A reduction adds the read fields of every record into row `key` of a small
-// table.  Floating-point fields are summed in double and integer fields in
-// int64 (two's complement); the last column counts records.
-// Pass 1 has two forms.
-//  * Few keys (at most 8): every thread keeps its own sums for a slice of
-//    the table's columns in registers (all keys x about 40 / keys columns)
-//    over a grid-stride walk of the records; gridDim.y runs over the
-//    column slices.  At the end the 64 lanes of each wave are summed
-//    (a butterfly), then the 4 waves in order.  No LDS atomics at all.
-//  * More keys: each workgroup adds its records into LDS copies of the
-//    table with LDS atomics.  The copies ("replicas") split the lanes into
-//    groups of 256 / replicas, so lanes whose records share a key rarely add
-//    to the same cell in one instruction.
-// Either way pass 1 writes one partial table per workgroup (column slice).
-// Pass 2: one workgroup per cell adds those partials in a fixed order
-// (strided per thread, then a tree in LDS), so a given grid always adds in
-// the same order.
+// table; the last column counts records.  Integer fields are summed in int64
+// (two's complement), which is exact in any order.  Floating-point fields are
+// summed in double with compensation, in an order fixed by N and the grid:
+//  * each thread walks its records in a fixed grid-stride sequence and keeps
+//    per cell a pair (s, c): s the rounded running sum, c the sum of the
+//    exact rounding errors of s (Knuth's TwoSum; Ogita, Rump and Oishi's
+//    Sum2), so s + c carries about twice the precision of a double;
+//  * pairs are then combined pairwise with TwoSum on both parts and
+//    renormalised (double-double addition) in fixed trees: the 64 lanes of a
+//    wave by a butterfly, the waves of a workgroup in order, and in pass 2
+//    the workgroups of a cell (strided per thread, then a tree in LDS);
+//  * the table gets the double nearest the final pair.
+// No floating-point atomics are used anywhere, so two runs on one device give
+// the same bits.
+// Pass 1 has two forms:
+//  * at most 8 keys: every thread keeps its pairs for a slice of the table's
+//    columns in registers; gridDim.y runs over the slices;
+//  * more keys: one wave per workgroup with its own table in LDS.  Lanes of
+//    one wave that hit the same key add in lane order: a lane's rank among
+//    the lanes with its key is found with ballots, and the wave adds in
+//    rounds of rank 0, 1, ..., so no two lanes of a round touch one row.
+// Either way pass 1 writes one partial table of pairs per workgroup.
 struct ReduceArgs {
   const uint8_t *buf;
   uint32_t *err;
-  uint64_t *partials;  // [cells][gridDim.x]
+  uint64_t *partials;  // [cells][gridDim.x][2]: a pair (s, c) of doubles, or an int64 and a zero word
   int64_t n;
   uint32_t n_read, n_keys, cells, has_key;
-  uint32_t replicas;   // power of two in [1, 64]
   uint32_t fp_mask;    // bit q: read field q is floating point
+  uint32_t plain;      // 1: plain double sums in the same order (no compensation)
   SField rd[ADHA_MAX_READ];
   SField key;
 };
 
-__device__ __forceinline__ double wave_sum_f64(double v) {
+// s + e = a + b exactly with s = fl(a + b), for any doubles a, b (no
+// ordering of the operands needed; Knuth's TwoSum).
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+  const double t = __dadd_rn(a, b);
+  const double bb = __dsub_rn(t, a);
+  e = __dadd_rn(__dsub_rn(a, __dsub_rn(t, bb)), __dsub_rn(b, bb));
+  s = t;
+}
+
+// One value into a compensated pair (s, c).  PLAIN: s += v only.
+template <bool PLAIN>
+__device__ __forceinline__ void comp_add(double &s, double &c, double v) {
+  if constexpr (PLAIN) {
+    s = __dadd_rn(s, v);
+  } else {
+    double e;
+    two_sum(s, v, s, e);
+    c = __dadd_rn(c, e);
+  }
+}
+
+// (a1 + a2) + (b1 + b2) as a pair (hi, lo) with hi = fl(hi + lo).  Every
+// step but two is exact; the two roundings are of quantities of the order of
+// the low parts, so the pair keeps about 106 bits of the exact sum.
+__device__ __forceinline__ void pair_add(double a1, double a2, double b1, double b2, double &hi, double &lo) {
+  double s, e, t, f, s2, e3;
+  two_sum(a1, b1, s, e);
+  two_sum(a2, b2, t, f);
+  two_sum(s, __dadd_rn(e, t), s2, e3);
+  two_sum(s2, __dadd_rn(e3, f), hi, lo);
+}
+
+__device__ __forceinline__ double bits_f64(uint64_t b) { return __longlong_as_double((long long)b); }
+__device__ __forceinline__ uint64_t f64_bits(double d) { return (uint64_t)__double_as_longlong(d); }
+
+__device__ __forceinline__ void wave_pair_sum(double &hi, double &lo) {
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-  return v;
+  for (int m = 32; m >= 1; m >>= 1) {
+    const double oh = __shfl_xor(hi, m, 64), ol = __shfl_xor(lo, m, 64);
+    pair_add(hi, lo, oh, ol, hi, lo);
+  }
 }
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
@@ -690,75 +733,75 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
   return v;
 }
 
-__device__ __forceinline__ void cell_add(uint64_t *cell, bool fp, double d, uint64_t u) {
-  if (fp) atomicAdd(reinterpret_cast<double *>(cell), d);
-  else atomicAdd(reinterpret_cast<unsigned long long *>(cell), (unsigned long long)u);
-}
-
 __device__ __forceinline__ uint64_t as_i64(uint64_t t) { return (uint64_t)(int64_t)(int32_t)(uint32_t)t; }
 
-template <int MAXR, bool W8>
-__global__ __launch_bounds__(256) void reduce_partial_kernel(const ReduceArgs a) {
-  extern __shared__ uint64_t tab[];
-  const uint32_t nr = a.n_read, cols = nr + 1, cells = a.cells;
-  for (uint32_t c = threadIdx.x; c < cells * a.replicas; c += 256) tab[c] = 0;
-  __syncthreads();
-  uint64_t *mine = tab + (threadIdx.x * a.replicas / 256u) * cells;
-  bool bad = false;
-  const uint64_t stride = (uint64_t)gridDim.x * 256u;
-  for (uint64_t i0 = (uint64_t)blockIdx.x * 256u; i0 < (uint64_t)a.n; i0 += stride) {
-    const uint64_t i = i0 + threadIdx.x;
-    const bool live = i < (uint64_t)a.n;
-    int32_t k = 0;
-    if (a.has_key && live) k = (int32_t)load_word(a.buf, a.key, i);
-    const bool ok = live && k >= 0 && (uint32_t)k < a.n_keys;
-    bad |= live && !ok;
-    Words<MAXR, W8> w;
-    const uint64_t rr = live ? i : 0;     // lanes past N load record 0, unused
+// End of a register-form workgroup: per cell of the slice, the wave sums
+// (lane 0 of each wave into LDS), then the 4 waves in order, into the
+// workgroup's partial.  fp(c) tells a floating-point column slot; hi/lo hold
+// a pair (or hi the int64 bits) per (key, slot).
+template <int KR, int CR, class IsFp>
+__device__ __forceinline__ void reduce_reg_finish(const ReduceArgs &a, uint64_t (&hi)[KR][CR], double (&lo)[KR][CR],
+                                                  uint32_t c0, uint32_t nc, IsFp fp) {
+  __shared__ uint64_t wsum[4][KR * CR][2];
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
 #pragma unroll
-    for (int q = 0; q < MAXR; ++q)
-      if (q < (int)nr) w.load(q, a.buf, a.rd[q], rr);
-
-    if (ok) {
-      uint64_t *row = mine + (uint32_t)k * cols;
+  for (int c = 0; c < CR; ++c) {
 #pragma unroll
-      for (int q = 0; q < MAXR; ++q)
-        if (q < (int)nr) {
-          const bool fp = a.fp_mask >> q & 1u;
-          const uint64_t t = w.term(q, a.rd[q]);
-          cell_add(row + q, fp, fp ? to_f64(a.rd[q].dt, t) : 0.0, fp ? 0 : as_i64(t));
+    for (int kk = 0; kk < KR; ++kk) {
+      if (fp(c)) {
+        double h = bits_f64(hi[kk][c]), l = lo[kk][c];
+        wave_pair_sum(h, l);
+        if (lane == 0) {
+          wsum[wave][kk * CR + c][0] = f64_bits(h);
+          wsum[wave][kk * CR + c][1] = f64_bits(l);
         }
-      cell_add(row + nr, false, 0.0, 1);
+      } else {
+        const uint64_t u = wave_sum_u64(hi[kk][c]);
+        if (lane == 0) {
+          wsum[wave][kk * CR + c][0] = u;
+          wsum[wave][kk * CR + c][1] = 0;
+        }
+      }
     }
   }
   __syncthreads();
-  for (uint32_t c = threadIdx.x; c < cells; c += 256) {
-    const uint32_t q = c % cols;
-    const bool fp = q < nr && (a.fp_mask >> q & 1u);
-    double d = 0.0;
-    uint64_t u = 0;
-    for (uint32_t r = 0; r < a.replicas; ++r) {
-      const uint64_t v = tab[r * cells + c];
-      if (fp) d += __longlong_as_double((long long)v);
-      else u += v;
+  const uint32_t t = threadIdx.x;
+  if (t < (uint32_t)(KR * CR)) {
+    const uint32_t kk = t / CR, c = t % CR, col = c0 + c;
+    if (kk < a.n_keys && c < nc) {
+      const uint32_t cols = a.n_read + 1;
+      uint64_t o0, o1;
+      if (fp(c)) {
+        double h = bits_f64(wsum[0][t][0]), l = bits_f64(wsum[0][t][1]);
+        for (int w = 1; w < 4; ++w) pair_add(h, l, bits_f64(wsum[w][t][0]), bits_f64(wsum[w][t][1]), h, l);
+        o0 = f64_bits(h);
+        o1 = f64_bits(l);
+      } else {
+        o0 = wsum[0][t][0] + wsum[1][t][0] + wsum[2][t][0] + wsum[3][t][0];
+        o1 = 0;
+      }
+      const uint64_t at = ((uint64_t)(kk * cols + col) * gridDim.x + blockIdx.x) * 2;
+      a.partials[at] = o0;
+      a.partials[at + 1] = o1;
     }
-    a.partials[(uint64_t)c * gridDim.x + blockIdx.x] = fp ? (uint64_t)__double_as_longlong(d) : u;
   }
-  if (bad) atomicOr(a.err, 1u);
 }
 
-// Few keys: sums in registers.  KR >= n_keys rows, CR columns per slice.
-template <int KR, int CR, bool W8>
+// Few keys: pairs in registers.  KR >= n_keys rows, CR columns per slice.
+template <int KR, int CR, bool W8, bool PLAIN>
 __global__ __launch_bounds__(256) void reduce_reg_kernel(const ReduceArgs a) {
-  __shared__ uint64_t wsum[4][KR * CR];
   const uint32_t nr = a.n_read, cols = nr + 1;
   const uint32_t c0 = blockIdx.y * CR;
   const uint32_t nc = min((uint32_t)CR, cols - c0);
-  uint64_t acc[KR][CR];
+  uint64_t hi[KR][CR];  // fp: bits of s; integer and count columns: int64
+  double lo[KR][CR];
 #pragma unroll
   for (int kk = 0; kk < KR; ++kk)
 #pragma unroll
-    for (int c = 0; c < CR; ++c) acc[kk][c] = 0;
+    for (int c = 0; c < CR; ++c) {
+      hi[kk][c] = 0;
+      lo[kk][c] = 0.0;
+    }
   bool bad = false;
   const uint64_t stride = (uint64_t)gridDim.x * 256u;
   for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < (uint64_t)a.n; i += stride) {
@@ -783,75 +826,46 @@ __global__ __launch_bounds__(256) void reduce_reg_kernel(const ReduceArgs a) {
         const double d = to_f64(a.rd[col].dt, v[c]);
 #pragma unroll
         for (int kk = 0; kk < KR; ++kk) {
-          const double s = __longlong_as_double((long long)acc[kk][c]) + d;
-          acc[kk][c] = (ok && k == kk) ? (uint64_t)__double_as_longlong(s) : acc[kk][c];
+          // adding +0.0 leaves a pair unchanged bit for bit
+          double s = bits_f64(hi[kk][c]);
+          comp_add<PLAIN>(s, lo[kk][c], (ok && k == kk) ? d : 0.0);
+          hi[kk][c] = f64_bits(s);
         }
       } else {
         const uint64_t u = col < nr ? as_i64(v[c]) : v[c];
 #pragma unroll
-        for (int kk = 0; kk < KR; ++kk) acc[kk][c] = (ok && k == kk) ? acc[kk][c] + u : acc[kk][c];
+        for (int kk = 0; kk < KR; ++kk) hi[kk][c] = (ok && k == kk) ? hi[kk][c] + u : hi[kk][c];
       }
     }
   }
-  // the 64 lanes of each wave, then the 4 waves in order
-  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
-#pragma unroll
-  for (int c = 0; c < CR; ++c) {
-    const uint32_t col = c0 + c;
-    const bool fp = col < nr && (a.fp_mask >> col & 1u);
-#pragma unroll
-    for (int kk = 0; kk < KR; ++kk) {
-      uint64_t x = acc[kk][c];
-      if (fp) x = (uint64_t)__double_as_longlong(wave_sum_f64(__longlong_as_double((long long)x)));
-      else x = wave_sum_u64(x);
-      if (lane == 0) wsum[wave][kk * CR + c] = x;
-    }
-  }
-  __syncthreads();
-  const uint32_t t = threadIdx.x;
-  if (t < (uint32_t)(KR * CR)) {
-    const uint32_t kk = t / CR, c = t % CR, col = c0 + c;
-    if (kk < a.n_keys && c < nc) {
-      const bool fp = col < nr && (a.fp_mask >> col & 1u);
-      double d = 0.0;
-      uint64_t u = 0;
-      for (int w = 0; w < 4; ++w) {
-        if (fp) d += __longlong_as_double((long long)wsum[w][t]);
-        else u += wsum[w][t];
-      }
-      const uint32_t cell = kk * cols + col;
-      a.partials[(uint64_t)cell * gridDim.x + blockIdx.x] = fp ? (uint64_t)__double_as_longlong(d) : u;
-    }
-  }
+  reduce_reg_finish<KR, CR>(a, hi, lo, c0, nc,
+                            [&](int c) { return c0 + c < nr && (a.fp_mask >> (c0 + c) & 1u); });
   if (bad) atomicOr(a.err, 1u);
 }
 
-// Few keys, every read field F32: the same sums with no branch per column.
-// A column slot past the reads folds 0.0 (adding +0.0 to a sum that started
-// at +0.0 and only ever had values added leaves it unchanged, bit for bit),
-// and the record counts live in their own per-key registers, written by the
-// slice that holds the count column.  LIN: the read fields and the key sit
-// in groups with T = 1 and the layout fits in 4 GiB, so offsets are
-// base + p + r*S in 32 bits.
+// Few keys, every read field F32: the same pairs with no branch per column.
+// A column slot past the reads folds +0.0, and the record counts live in
+// their own per-key registers, written by the slice that holds the count
+// column.  LIN: the read fields and the key sit in groups with T = 1 and the
+// layout fits in 4 GiB, so offsets are base + p + r*S in 32 bits.
 template <bool LIN>
 __device__ __forceinline__ uint32_t reduce_word(const ReduceArgs &a, const SField &F, uint64_t i) {
   if constexpr (LIN) return *reinterpret_cast<const uint32_t *>(a.buf + ((uint32_t)F.base + F.pT + (uint32_t)i * F.TS));
   return load_word(a.buf, F, i);
 }
 
-template <int KR, int CR, bool LIN>
+template <int KR, int CR, bool LIN, bool PLAIN>
 __global__ __launch_bounds__(256) void reduce_reg_f32_kernel(const ReduceArgs a) {
-  __shared__ uint64_t wsum[4][KR * (CR + 1)];
   const uint32_t nr = a.n_read, cols = nr + 1;
   const uint32_t c0 = blockIdx.y * CR;
   const uint32_t nc = min((uint32_t)CR, cols - c0);
-  double acc[KR][CR];
+  double s[KR][CR], lo[KR][CR];
   uint32_t cnt[KR];
 #pragma unroll
   for (int kk = 0; kk < KR; ++kk) {
     cnt[kk] = 0;
 #pragma unroll
-    for (int c = 0; c < CR; ++c) acc[kk][c] = 0.0;
+    for (int c = 0; c < CR; ++c) s[kk][c] = lo[kk][c] = 0.0;
   }
   bool bad = false;
   const uint64_t stride = (uint64_t)gridDim.x * 256u;
@@ -867,100 +881,202 @@ __global__ __launch_bounds__(256) void reduce_reg_f32_kernel(const ReduceArgs a)
     for (int c = 0; c < CR; ++c) {
       const double d = c0 + c < nr ? (double)__uint_as_float(w[c]) : 0.0;
 #pragma unroll
-      for (int kk = 0; kk < KR; ++kk) acc[kk][c] = __dadd_rn(acc[kk][c], (ok && k == kk) ? d : 0.0);
+      for (int kk = 0; kk < KR; ++kk) comp_add<PLAIN>(s[kk][c], lo[kk][c], (ok && k == kk) ? d : 0.0);
     }
 #pragma unroll
     for (int kk = 0; kk < KR; ++kk) cnt[kk] += (ok && k == kk) ? 1u : 0u;
   }
-  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  // the count column takes the slot of the first column past the reads
+  uint64_t hi[KR][CR];
 #pragma unroll
-  for (int kk = 0; kk < KR; ++kk) {
+  for (int kk = 0; kk < KR; ++kk)
 #pragma unroll
-    for (int c = 0; c < CR; ++c) {
-      const uint64_t x = (uint64_t)__double_as_longlong(wave_sum_f64(acc[kk][c]));
-      if (lane == 0) wsum[wave][kk * (CR + 1) + c] = x;
+    for (int c = 0; c < CR; ++c) hi[kk][c] = c0 + c == nr ? (uint64_t)cnt[kk] : f64_bits(s[kk][c]);
+  reduce_reg_finish<KR, CR>(a, hi, lo, c0, nc, [&](int c) { return c0 + c < nr; });
+  if (bad) atomicOr(a.err, 1u);
+}
+
+// More keys: one wave per workgroup, with its own table of pairs in LDS.
+template <int MAXR, bool W8, bool PLAIN>
+__global__ __launch_bounds__(64) void reduce_lds_kernel(const ReduceArgs a) {
+  extern __shared__ uint64_t tab[];  // [cells][2]
+  const uint32_t nr = a.n_read, cols = nr + 1, cells = a.cells;
+  const uint32_t lane = threadIdx.x;
+  for (uint32_t c = lane; c < 2 * cells; c += 64) tab[c] = 0;
+  __syncthreads();
+  bool bad = false;
+  const uint64_t stride = (uint64_t)gridDim.x * 64u;
+  for (uint64_t i0 = (uint64_t)blockIdx.x * 64u; i0 < (uint64_t)a.n; i0 += stride) {
+    const uint64_t i = i0 + lane;
+    const bool live = i < (uint64_t)a.n;
+    int32_t k = 0;
+    if (a.has_key && live) k = (int32_t)load_word(a.buf, a.key, i);
+    const bool ok = live && k >= 0 && (uint32_t)k < a.n_keys;
+    bad |= live && !ok;
+    Words<MAXR, W8> w;
+    const uint64_t rr = live ? i : 0;  // lanes past N load record 0, unused
+#pragma unroll
+    for (int q = 0; q < MAXR; ++q)
+      if (q < (int)nr) w.load(q, a.buf, a.rd[q], rr);
+    // the terms as doubles (floating-point fields) or int64 bits (I32)
+    uint64_t v[MAXR];
+#pragma unroll
+    for (int q = 0; q < MAXR; ++q) {
+      const uint64_t t = q < (int)nr ? w.term(q, a.rd[q]) : 0;
+      v[q] = (a.fp_mask >> q & 1u) ? f64_bits(to_f64(a.rd[q].dt, t)) : as_i64(t);
     }
-    const uint64_t n = wave_sum_u64((uint64_t)cnt[kk]);
-    if (lane == 0) wsum[wave][kk * (CR + 1) + CR] = n;
+    // rank of each lane among the lanes with its key, in lane order, and the
+    // number of rounds (the largest count of one key)
+    uint64_t pending = __ballot(ok);
+    uint32_t rank = 0, rounds = 0;
+    const uint64_t below = (1ull << lane) - 1ull;
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const int32_t lk = __shfl(k, leader, 64);
+      const bool same = ok && k == lk;
+      const uint64_t m = __ballot(same);
+      if (same) rank = (uint32_t)__popcll(m & below);
+      rounds = max(rounds, (uint32_t)__popcll(m));
+      pending &= ~m;
+    }
+    for (uint32_t r = 0; r < rounds; ++r) {
+      if (ok && rank == r) {
+        uint64_t *row = tab + (uint64_t)(uint32_t)k * cols * 2;
+#pragma unroll
+        for (int q = 0; q < MAXR; ++q)
+          if (q < (int)nr) {
+            if (a.fp_mask >> q & 1u) {
+              double sv = bits_f64(row[2 * q]), cv = bits_f64(row[2 * q + 1]);
+              comp_add<PLAIN>(sv, cv, bits_f64(v[q]));
+              // a cell's chain is every record of the workgroup with that
+              // key, so the pair is renormalised after each value: its error
+              // then grows with the chain's length, not with its square
+              if constexpr (!PLAIN) two_sum(sv, cv, sv, cv);
+              row[2 * q] = f64_bits(sv);
+              row[2 * q + 1] = f64_bits(cv);
+            } else {
+              row[2 * q] += v[q];
+            }
+          }
+        row[2 * nr] += 1;
+      }
+      __syncthreads();
+    }
   }
   __syncthreads();
-  const uint32_t t = threadIdx.x;
-  if (t < (uint32_t)(KR * CR)) {
-    const uint32_t kk = t / CR, c = t % CR, col = c0 + c;
-    if (kk < a.n_keys && c < nc) {
-      const bool count = col == nr;
-      const uint32_t slot = kk * (CR + 1) + (count ? CR : c);
-      double d = 0.0;
-      uint64_t u = 0;
-      for (int w = 0; w < 4; ++w) {
-        if (count) u += wsum[w][slot];
-        else d += __longlong_as_double((long long)wsum[w][slot]);
-      }
-      const uint32_t cell = kk * cols + col;
-      a.partials[(uint64_t)cell * gridDim.x + blockIdx.x] = count ? u : (uint64_t)__double_as_longlong(d);
-    }
+  for (uint32_t c = lane; c < cells; c += 64) {
+    const uint64_t at = ((uint64_t)c * gridDim.x + blockIdx.x) * 2;
+    a.partials[at] = tab[2 * c];
+    a.partials[at + 1] = tab[2 * c + 1];
   }
   if (bad) atomicOr(a.err, 1u);
 }
 
+// Pass 2: one workgroup per cell adds the workgroups' partials, each thread
+// striding over them in order, then a tree in LDS.
+template <bool PLAIN>
 __global__ __launch_bounds__(256) void reduce_final_kernel(const uint64_t *partials, uint32_t groups, uint32_t cols,
                                                            uint32_t fp_mask, uint64_t *out) {
-  __shared__ double sd[256];
+  __shared__ double sh[256], sl[256];
   __shared__ uint64_t su[256];
   const uint32_t c = blockIdx.x, q = c % cols;
   const bool fp = q + 1 < cols && (fp_mask >> q & 1u);
-  const uint64_t *p = partials + (uint64_t)c * groups;
-  double d = 0.0;
+  const uint64_t *p = partials + (uint64_t)c * groups * 2;
+  double h = 0.0, l = 0.0;
   uint64_t u = 0;
   for (uint32_t g = threadIdx.x; g < groups; g += 256) {
-    if (fp) d += __longlong_as_double((long long)p[g]);
-    else u += p[g];
+    if (fp) {
+      if constexpr (PLAIN) h = __dadd_rn(h, bits_f64(p[2 * g]));
+      else pair_add(h, l, bits_f64(p[2 * g]), bits_f64(p[2 * g + 1]), h, l);
+    } else {
+      u += p[2 * g];
+    }
   }
-  sd[threadIdx.x] = d;
+  sh[threadIdx.x] = h;
+  sl[threadIdx.x] = l;
   su[threadIdx.x] = u;
   __syncthreads();
-  for (uint32_t h = 128; h >= 1; h >>= 1) {
-    if (threadIdx.x < h) {
-      sd[threadIdx.x] += sd[threadIdx.x + h];
-      su[threadIdx.x] += su[threadIdx.x + h];
+  for (uint32_t w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) {
+      const uint32_t t = threadIdx.x;
+      if constexpr (PLAIN) {
+        sh[t] = __dadd_rn(sh[t], sh[t + w]);
+      } else {
+        double hh, ll;
+        pair_add(sh[t], sl[t], sh[t + w], sl[t + w], hh, ll);
+        sh[t] = hh;
+        sl[t] = ll;
+      }
+      su[threadIdx.x] += su[threadIdx.x + w];
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[c] = fp ? (uint64_t)__double_as_longlong(sd[0]) : su[0];
+  if (threadIdx.x == 0) out[c] = fp ? f64_bits(sh[0]) : su[0];
 }
 
-template <bool W8>
+template <bool W8, bool PLAIN>
 static void reduce_dispatch(uint32_t KR, uint32_t nr, dim3 grid, size_t lds, hipStream_t stream, const ReduceArgs &a) {
-  if (KR == 1) hipLaunchKernelGGL((reduce_reg_kernel<1, 33, W8>), grid, dim3(256), 0, stream, a);
-  else if (KR == 2) hipLaunchKernelGGL((reduce_reg_kernel<2, 17, W8>), grid, dim3(256), 0, stream, a);
-  else if (KR == 3) hipLaunchKernelGGL((reduce_reg_kernel<3, 11, W8>), grid, dim3(256), 0, stream, a);
-  else if (KR == 4) hipLaunchKernelGGL((reduce_reg_kernel<4, 9, W8>), grid, dim3(256), 0, stream, a);
-  else if (KR == 5) hipLaunchKernelGGL((reduce_reg_kernel<5, 7, W8>), grid, dim3(256), 0, stream, a);
-  else if (KR == 6) hipLaunchKernelGGL((reduce_reg_kernel<6, 6, W8>), grid, dim3(256), 0, stream, a);
-  else if (KR == 7) hipLaunchKernelGGL((reduce_reg_kernel<7, 5, W8>), grid, dim3(256), 0, stream, a);
-  else if (KR == 8) hipLaunchKernelGGL((reduce_reg_kernel<8, 5, W8>), grid, dim3(256), 0, stream, a);
-  else if (nr <= 4) hipLaunchKernelGGL((reduce_partial_kernel<4, W8>), grid, dim3(256), lds, stream, a);
-  else if (nr <= 8) hipLaunchKernelGGL((reduce_partial_kernel<8, W8>), grid, dim3(256), lds, stream, a);
-  else if (nr <= 16) hipLaunchKernelGGL((reduce_partial_kernel<16, W8>), grid, dim3(256), lds, stream, a);
-  else hipLaunchKernelGGL((reduce_partial_kernel<32, W8>), grid, dim3(256), lds, stream, a);
+  switch (KR) {
+    case 1: hipLaunchKernelGGL((reduce_reg_kernel<1, 17, W8, PLAIN>), grid, dim3(256), 0, stream, a); return;
+    case 2: hipLaunchKernelGGL((reduce_reg_kernel<2, 9, W8, PLAIN>), grid, dim3(256), 0, stream, a); return;
+    case 3: hipLaunchKernelGGL((reduce_reg_kernel<3, 6, W8, PLAIN>), grid, dim3(256), 0, stream, a); return;
+    case 4: hipLaunchKernelGGL((reduce_reg_kernel<4, 5, W8, PLAIN>), grid, dim3(256), 0, stream, a); return;
+    case 5: hipLaunchKernelGGL((reduce_reg_kernel<5, 4, W8, PLAIN>), grid, dim3(256), 0, stream, a); return;
+    case 6: hipLaunchKernelGGL((reduce_reg_kernel<6, 3, W8, PLAIN>), grid, dim3(256), 0, stream, a); return;
+    case 7: hipLaunchKernelGGL((reduce_reg_kernel<7, 3, W8, PLAIN>), grid, dim3(256), 0, stream, a); return;
+    case 8: hipLaunchKernelGGL((reduce_reg_kernel<8, 3, W8, PLAIN>), grid, dim3(256), 0, stream, a); return;
+    default: break;
+  }
+  if (nr <= 4) hipLaunchKernelGGL((reduce_lds_kernel<4, W8, PLAIN>), grid, dim3(64), lds, stream, a);
+  else if (nr <= 8) hipLaunchKernelGGL((reduce_lds_kernel<8, W8, PLAIN>), grid, dim3(64), lds, stream, a);
+  else if (nr <= 16) hipLaunchKernelGGL((reduce_lds_kernel<16, W8, PLAIN>), grid, dim3(64), lds, stream, a);
+  else hipLaunchKernelGGL((reduce_lds_kernel<32, W8, PLAIN>), grid, dim3(64), lds, stream, a);
 }
 
-template <bool LIN>
+template <bool LIN, bool PLAIN>
 static void reduce_f32_dispatch(uint32_t KR, dim3 grid, hipStream_t stream, const ReduceArgs &a) {
   switch (KR) {
-    case 1: hipLaunchKernelGGL((reduce_reg_f32_kernel<1, 33, LIN>), grid, dim3(256), 0, stream, a); break;
-    case 2: hipLaunchKernelGGL((reduce_reg_f32_kernel<2, 17, LIN>), grid, dim3(256), 0, stream, a); break;
-    case 3: hipLaunchKernelGGL((reduce_reg_f32_kernel<3, 11, LIN>), grid, dim3(256), 0, stream, a); break;
-    case 4: hipLaunchKernelGGL((reduce_reg_f32_kernel<4, 9, LIN>), grid, dim3(256), 0, stream, a); break;
-    case 5: hipLaunchKernelGGL((reduce_reg_f32_kernel<5, 7, LIN>), grid, dim3(256), 0, stream, a); break;
-    case 6: hipLaunchKernelGGL((reduce_reg_f32_kernel<6, 6, LIN>), grid, dim3(256), 0, stream, a); break;
-    case 7: hipLaunchKernelGGL((reduce_reg_f32_kernel<7, 5, LIN>), grid, dim3(256), 0, stream, a); break;
-    default: hipLaunchKernelGGL((reduce_reg_f32_kernel<8, 5, LIN>), grid, dim3(256), 0, stream, a); break;
+    case 1: hipLaunchKernelGGL((reduce_reg_f32_kernel<1, 17, LIN, PLAIN>), grid, dim3(256), 0, stream, a); break;
+    case 2: hipLaunchKernelGGL((reduce_reg_f32_kernel<2, 9, LIN, PLAIN>), grid, dim3(256), 0, stream, a); break;
+    case 3: hipLaunchKernelGGL((reduce_reg_f32_kernel<3, 6, LIN, PLAIN>), grid, dim3(256), 0, stream, a); break;
+    case 4: hipLaunchKernelGGL((reduce_reg_f32_kernel<4, 5, LIN, PLAIN>), grid, dim3(256), 0, stream, a); break;
+    case 5: hipLaunchKernelGGL((reduce_reg_f32_kernel<5, 4, LIN, PLAIN>), grid, dim3(256), 0, stream, a); break;
+    case 6: hipLaunchKernelGGL((reduce_reg_f32_kernel<6, 3, LIN, PLAIN>), grid, dim3(256), 0, stream, a); break;
+    case 7: hipLaunchKernelGGL((reduce_reg_f32_kernel<7, 3, LIN, PLAIN>), grid, dim3(256), 0, stream, a); break;
+    default: hipLaunchKernelGGL((reduce_reg_f32_kernel<8, 3, LIN, PLAIN>), grid, dim3(256), 0, stream, a); break;
   }
 }
 
-static adha_status reduce_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l, const void *buf,
-                                 void *out, hipStream_t stream) {
+// Register slice widths per key count (pairs per thread: keys x columns).
+static const uint32_t kRedCols[9] = {0, 17, 9, 6, 5, 4, 3, 3, 3};
+
+ReducePlan reduce_plan(const Ctx *ctx, const SectionDesc &sec, int64_t n) {
+  ReducePlan p;
+  const uint32_t cells = sec.reduce_cells(), cols = (uint32_t)sec.rd.size() + 1;
+  p.keys_in_regs = sec.n_keys <= 8 ? sec.n_keys : 0;
+  p.slices = p.keys_in_regs ? (cols + kRedCols[p.keys_in_regs] - 1) / kRedCols[p.keys_in_regs] : 1;
+  const uint64_t per_wg = p.keys_in_regs ? 256 : 64;
+  const uint64_t want = std::max<uint64_t>(1, ((uint64_t)n + per_wg - 1) / per_wg);
+  uint64_t budget;
+  if (p.keys_in_regs) {
+    budget = (uint64_t)std::max(1, ctx->cu_count) * ctx->reduce_wg_per_cu / p.slices;
+  } else {
+    // one-wave workgroups, as many per CU as their LDS tables allow (at most 16)
+    const uint64_t per_cu = std::min<uint64_t>(16, std::max<uint64_t>(1, 163840 / ((uint64_t)cells * 16)));
+    budget = (uint64_t)std::max(1, ctx->cu_count) * per_cu;
+  }
+  // register form: enough workgroups that a thread's chain (records per
+  // thread) stays within 32 where the partial tables allow it
+  const uint64_t short_chains = p.keys_in_regs ? ((uint64_t)n + 256 * 32 - 1) / (256 * 32) : 1;
+  const uint64_t cap = std::max<uint64_t>(1, kReducePartialPairs / cells);
+  p.groups = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(want, std::max<uint64_t>({1, budget, short_chains})), cap);
+  p.lds = p.keys_in_regs ? 0 : (size_t)cells * 16;
+  p.partial_bytes = (uint64_t)p.groups * cells * 16;
+  return p;
+}
+
+adha_status reduce_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l, const void *buf, void *out,
+                          uint64_t *partials, uint64_t partial_cap, hipStream_t stream) {
   const int64_t n = l.shape.n;
   ReduceArgs a{};
   a.buf = (const uint8_t *)buf;
@@ -970,48 +1086,45 @@ static adha_status reduce_launch(Ctx *ctx, const SectionDesc &sec, const LayoutD
   a.n_keys = sec.n_keys;
   a.cells = sec.reduce_cells();
   a.has_key = sec.key >= 0;
+  a.plain = ctx->reduce_plain ? 1u : 0u;
   for (size_t q = 0; q < sec.rd.size(); ++q) {
     a.rd[q] = sfield(l, sec.rd[q]);
     if (l.shape.dtype[sec.rd[q]] != ADHA_I32) a.fp_mask |= 1u << q;
   }
   if (sec.key >= 0) a.key = sfield(l, sec.key);
-  a.replicas = 1;
-  while (a.replicas < 64 && (size_t)a.cells * 8 * a.replicas * 2 <= ctx->reduce_lds_bytes) a.replicas *= 2;
-  const uint32_t nr = a.n_read, cols = nr + 1;
-  // few keys: sums in registers, KR = n_keys rows by CR columns per slice
-  // (about 40 accumulators per thread)
-  static const uint32_t kCols[9] = {0, 33, 17, 11, 9, 7, 6, 5, 5};
-  const uint32_t KR = sec.n_keys <= 8 ? sec.n_keys : 0, CR = kCols[KR];
-  const uint32_t slices = KR ? (cols + CR - 1) / CR : 1;
-  // a fixed grid for a given N, so the order of pass 2 is fixed too
-  const uint64_t want = std::max<uint64_t>(1, ((uint64_t)n + 255) / 256);
-  const uint64_t budget = (uint64_t)std::max(1, ctx->cu_count) * ctx->reduce_wg_per_cu;
-  const uint32_t groups = (uint32_t)std::min<uint64_t>(want, std::max<uint64_t>(1, budget / slices));
-  uint64_t *partials = nullptr;
-  ADHA_HIP(hipMallocAsync((void **)&partials, (size_t)groups * a.cells * 8, stream));
+  const ReducePlan p = reduce_plan(ctx, sec, n);
+  if (p.partial_bytes > partial_cap)
+    return fail(ADHA_ERR_INVALID, "reduction partials need %llu bytes, the scratch holds %llu",
+                (unsigned long long)p.partial_bytes, (unsigned long long)partial_cap);
   a.partials = partials;
-  const size_t lds = (size_t)a.cells * 8 * a.replicas;
-  const dim3 grid(groups, slices);
-  bool w8 = false;
-  for (int f : sec.rd) w8 |= l.shape.ebytes[f] == 8;
-  bool f32 = true;
-  for (int f : sec.rd) f32 &= l.shape.dtype[f] == ADHA_F32;
+  const uint32_t nr = a.n_read, cols = nr + 1, KR = p.keys_in_regs;
+  const dim3 grid(p.groups, p.slices);
+  bool w8 = false, f32 = true;
+  for (int f : sec.rd) {
+    w8 |= l.shape.ebytes[f] == 8;
+    f32 &= l.shape.dtype[f] == ADHA_F32;
+  }
+  const bool plain = a.plain != 0;
   if (f32 && KR >= 1) {
     bool lin = l.nbytes <= (1ull << 32) && (sec.key < 0 || a.key.logT == 0);
     for (uint32_t q = 0; q < nr; ++q) lin &= a.rd[q].logT == 0;
-    if (lin) reduce_f32_dispatch<true>(KR, grid, stream, a);
-    else reduce_f32_dispatch<false>(KR, grid, stream, a);
+    if (lin) plain ? reduce_f32_dispatch<true, true>(KR, grid, stream, a) : reduce_f32_dispatch<true, false>(KR, grid, stream, a);
+    else plain ? reduce_f32_dispatch<false, true>(KR, grid, stream, a) : reduce_f32_dispatch<false, false>(KR, grid, stream, a);
   } else if (w8) {
-    reduce_dispatch<true>(KR, nr, grid, lds, stream, a);
+    plain ? reduce_dispatch<true, true>(KR, nr, grid, p.lds, stream, a) : reduce_dispatch<true, false>(KR, nr, grid, p.lds, stream, a);
   } else {
-    reduce_dispatch<false>(KR, nr, grid, lds, stream, a);
+    plain ? reduce_dispatch<false, true>(KR, nr, grid, p.lds, stream, a) : reduce_dispatch<false, false>(KR, nr, grid, p.lds, stream, a);
   }
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess)
-    hipLaunchKernelGGL(reduce_final_kernel, dim3(a.cells), dim3(256), 0, stream, (const uint64_t *)partials, groups,
-                       cols, a.fp_mask, (uint64_t *)out);
-  if (e == hipSuccess) e = hipGetLastError();
-  (void)hipFreeAsync(partials, stream);
+  if (e == hipSuccess) {
+    if (plain)
+      hipLaunchKernelGGL(reduce_final_kernel<true>, dim3(a.cells), dim3(256), 0, stream, (const uint64_t *)partials,
+                         p.groups, cols, a.fp_mask, (uint64_t *)out);
+    else
+      hipLaunchKernelGGL(reduce_final_kernel<false>, dim3(a.cells), dim3(256), 0, stream, (const uint64_t *)partials,
+                         p.groups, cols, a.fp_mask, (uint64_t *)out);
+    e = hipGetLastError();
+  }
   if (e != hipSuccess) return fail(ADHA_ERR_DEVICE, "reduction launch failed: %s", hipGetErrorString(e));
   return ADHA_OK;
 }
@@ -1034,7 +1147,7 @@ __global__ void zero_u64_kernel(uint64_t *p, uint32_t n) {
 }
 
 adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l, void *buf,
-                           const int32_t *idx, hipStream_t stream, void *out_override) {
+                           const int32_t *idx, hipStream_t stream, void *out_override, void *scratch) {
   const int64_t n = l.shape.n;
   if (sec.op == ADHA_OP_REDUCE) {
     void *out = out_override ? out_override : sec.out;
@@ -1044,7 +1157,11 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
       ADHA_HIP(hipGetLastError());
       return ADHA_OK;
     }
-    return reduce_launch(ctx, sec, l, buf, out, stream);
+    if (!scratch) {
+      ADHA_TRY(ctx_reduce_scratch(ctx));
+      scratch = ctx->reduce_partials;
+    }
+    return reduce_launch(ctx, sec, l, buf, out, (uint64_t *)scratch, kReducePartialPairs * 16ull, stream);
   }
   if (n == 0) return ADHA_OK;
   SectionArgs a{};

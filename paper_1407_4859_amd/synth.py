@@ -87,6 +87,26 @@ def decode(z: np.ndarray, dtype: int, elem_bytes: int = 4) -> np.ndarray:
     return np.ascontiguousarray(v).view(np.uint8).reshape(len(z), v.dtype.itemsize)
 
 
+def decode_wide(z: np.ndarray, dtype: int, lo_exp: int = -40, hi_exp: int = 40) -> np.ndarray:
+    """Floating-point values spread over many binades (uint8 [n, e]): sign from
+    bit 63, a binade 2^E with E uniform-ish in [lo_exp, hi_exp] from the bits
+    above the mantissa, and a full random mantissa, so the value is
+    +-(1 + m) * 2^E exactly (F32: 23 mantissa bits, F64: 52)."""
+    span = np.uint64(hi_exp - lo_exp + 1)
+    sign = np.where((z >> np.uint64(63)) != 0, -1.0, 1.0)
+    if dtype == F32:
+        m = (z & np.uint64(0x7FFFFF)).astype(np.float64) * 2.0 ** -23
+        e = ((z >> np.uint64(23)) & np.uint64(0xFFFF)) % span
+        v = (sign * (1.0 + m) * np.exp2(e.astype(np.float64) + lo_exp)).astype(np.float32)
+    elif dtype == F64:
+        m = (z & np.uint64((1 << 52) - 1)).astype(np.float64) * 2.0 ** -52
+        e = ((z >> np.uint64(52)) & np.uint64(0x7FF)) % span
+        v = sign * (1.0 + m) * np.exp2(e.astype(np.float64) + lo_exp)
+    else:
+        raise ValueError(dtype)
+    return np.ascontiguousarray(v).view(np.uint8).reshape(len(z), v.dtype.itemsize)
+
+
 def field_values(seed: int, stream: int, n: int, dtype: int, elem_bytes: int = 4,
                  start: int = 0) -> np.ndarray:
     return decode(splitmix64(seed, stream, start, n), dtype, elem_bytes)

@@ -60,3 +60,29 @@ def fill_aos_device(spec, seed: int, extra: int = 0):
             view[s:s + c, off:off + e] = synth.decode_torch(z, dt, e)
         off += e
     return t
+
+
+def host_cores(cap: int = 16) -> int:
+    """Host threads the oracle may use (the CPU share given to this process)."""
+    import os
+    try:
+        return max(1, min(cap, len(os.sched_getaffinity(0))))
+    except AttributeError:
+        return 1
+
+
+def oracle_remap_threaded(src_layout: OLayout, src: np.ndarray, dst_layout: OLayout,
+                          threads: int = 0) -> np.ndarray:
+    """The oracle's remap of a whole buffer, its record range split over host
+    threads (records are independent; every thread writes its own records
+    into the one zero-filled destination)."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    n = src_layout.n
+    t = threads or host_cores()
+    out = np.zeros(dst_layout.nbytes, np.uint8)
+    bounds = [n * i // t for i in range(t + 1)]
+    with ThreadPoolExecutor(t) as ex:
+        list(ex.map(lambda i: oracle.remap(src_layout, src, dst_layout, bounds[i], bounds[i + 1], out=out),
+                    range(t)))
+    return out

@@ -173,3 +173,68 @@ def test_tuner_picks_a_valid_shape_and_persists(ctx):
         assert e.value.status == A.ERR_IO
         with pytest.raises(A.AdhaError):
             A.tune_load(ctx2, os.path.join(d, "missing.txt"))
+
+
+def _aos_device_array(i, n, eb, seed):
+    """AoS buffer of array i drawn on the device: field f of record r holds
+    draw r of stream 64*i + f, packed in field order."""
+    S = sum(eb)
+    t = torch.zeros(max(256, -(-n * S // 256) * 256), dtype=torch.uint8, device="cuda")
+    if n == 0:
+        return t
+    view = t[: n * S].view(n, S)
+    off = 0
+    for f, e in enumerate(eb):
+        z = synth.splitmix64_torch(seed, 64 * i + f, 0, n, "cuda")
+        view[:, off:off + e] = synth.decode_torch(z, synth.RAW, e)
+        off += e
+    return t
+
+
+@pytest.mark.timeout(900)
+def test_config4_full_batch_tuned_policy_matches_oracle(ctx):
+    """The whole 512-array batched workload (lengths log-uniform in 2^10 ..
+    2^22, 4-24 fields of 4 or 8 bytes, AoS -> SoA or AoSoA): the batch policy
+    is tuned as the benchmark tunes it, then the graph launch's output of
+    every array is compared byte for byte with the oracle's remap of that
+    array, and so is a persistent launch under the default policy of a
+    fresh context."""
+    arrs = synth.config4_arrays()
+    c2 = A.Ctx(0)
+    items, keep = [], []
+    say("config4 full: drawing", len(arrs), "arrays on the device")
+    for i, a in enumerate(arrs):
+        eb = a["elem_bytes"]
+        st = A.Struct(a["n"], [A.RAW] * len(eb), eb)
+        Oa = oaos(a["n"], eb)
+        Ob = OLayout(a["n"], eb, a["target_gof"], a["target_tiles"])
+        src = _aos_device_array(i, a["n"], eb, 4)
+        assert src.numel() >= Oa.nbytes
+        dst = torch.full((Ob.nbytes,), 0xA5, dtype=torch.uint8, device="cuda")
+        items.append((mirror(st, Oa), src, mirror(st, Ob), dst))
+        keep.append((st, Oa, Ob))
+    say("config4 full: tuning the batch policy")
+    tuned = A.tune_batched(ctx, items, reps=2)
+    say("config4 full: tuned", tuned)
+
+    def check(label):
+        bad = []
+        for i, ((_, Oa, Ob), (_, src, _, dst)) in enumerate(zip(keep, items)):
+            want = oracle.remap(Oa, src[: Oa.nbytes].cpu().numpy(), Ob)
+            d = first_diff(dst.cpu().numpy(), want)
+            if d is not None:
+                bad.append((i, d))
+        assert not bad, (label, bad[:5])
+
+    for (_, _, _, dst) in items:
+        dst.fill_(0xA5)
+    say("config4 full: graph launch under the tuned policy")
+    A.remap_batched(ctx, items, A.BATCH_GRAPH)
+    ctx.check()
+    check("tuned graph")
+    for (_, _, _, dst) in items:
+        dst.fill_(0x5A)
+    say("config4 full: persistent launch under the default policy")
+    A.remap_batched(c2, items, 0)
+    c2.check()
+    check("default persistent")

@@ -6,8 +6,9 @@ The planned run on the device is compared with the oracle over the whole
 struct. The oracle runs on the host cores over record ranges; records are
 independent within a section, and a gather never writes a field it reads.
 
-The plan is the one the benchmark builds: the full catalogue, so remaps
-happen between runs. The all-SoA and all-AoS uniform plans are checked too.
+The plans are the one the benchmark builds and times (the full catalogue
+with measured costs, so remaps happen between runs) and the analytic-cost
+plan; the all-SoA and all-AoS uniform plans are checked too.
 Device results are remapped back to the packed record image on the device
 and compared byte for byte; a floating-point field may differ by at most
 1 ulp."""
@@ -83,8 +84,11 @@ def test_config3_full_size_plans_match_oracle(ctx):
     buf_a = torch.empty(cap, dtype=torch.uint8, device="cuda")
     buf_b = torch.empty(cap, dtype=torch.uint8, device="cuda")
     back = torch.empty(La.nbytes, dtype=torch.uint8, device="cuda")
-    plans = [("planned", A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_ANALYTIC, catalogue=A.CAT_FULL,
-                                                             cap_bytes=64))),
+    say("program full: planning with measured costs (the benchmark's plan)")
+    plans = [("measured", A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_MEASURED, catalogue=A.CAT_FULL,
+                                                              cap_bytes=64), idx=idx)),
+             ("analytic", A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_ANALYTIC, catalogue=A.CAT_FULL,
+                                                              cap_bytes=64))),
              ("all-SoA", A.Plan.uniform(prog, A.Layout.soa(st))),
              ("all-AoS", A.Plan.uniform(prog, La))]
     for name, plan in plans:

@@ -9,7 +9,8 @@ import oracle
 from oracle.layout import Layout as OLayout, aos as oaos, soa as osoa
 from paper_1407_4859_amd import adha as A
 from paper_1407_4859_amd import synth
-from gpu_util import dev_bytes, dev_empty, first_diff, host, mirror, say
+from gpu_util import (dev_bytes, dev_empty, fill_aos_device, first_diff, host, host_cores, mirror,
+                      oracle_remap_threaded, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -127,38 +128,85 @@ def test_empty_and_invalid(ctx):
     ctx.check()
 
 
-def test_config2_full_size_sampled_and_round_trip(ctx):
+def _config2_full():
     n = 1 << 26
     spec = synth.config2_struct(n)
     st = A.Struct.from_spec(spec)
     eb = spec.elem_bytes
-    OA, OS = oaos(n, eb), osoa(n, eb)
     gof, tiles = synth.config2_aosoa()
-    OT = OLayout(n, eb, gof, tiles)
-    LA, LS, LT = mirror(st, OA), mirror(st, OS), mirror(st, OT)
-    say("config2 full: generating", n, "records")
-    src = torch.empty(OA.nbytes, dtype=torch.uint8, device="cuda")
-    view = src.view(n, 64)
+    return n, spec, st, oaos(n, eb), osoa(n, eb), OLayout(n, eb, gof, tiles)
+
+
+def _soa_device(spec, seed, OS):
+    """Device buffer in the SoA layout OS holding the seeded values of every
+    record (field f's column starts at its group base)."""
+    n = spec.n
+    t = torch.zeros(OS.nbytes, dtype=torch.uint8, device="cuda")
     chunk = 1 << 24
-    for f in range(16):
+    for f, (dt, e) in enumerate(zip(spec.dtypes, spec.elem_bytes)):
+        base = int(OS.addr_vec(np.array([0]), f)[0])
+        col = t[base:base + n * e].view(n, e)
         for s in range(0, n, chunk):
-            z = synth.splitmix64_torch(2, f, s, chunk, "cuda")
-            view[s:s + chunk, 4 * f:4 * f + 4] = synth.decode_torch(z, spec.dtypes[f])
-    dst = torch.empty(max(OS.nbytes, OT.nbytes), dtype=torch.uint8, device="cuda")
-    back = torch.empty(OA.nbytes, dtype=torch.uint8, device="cuda")
-    rng = np.random.default_rng(0)
-    recs = np.unique(np.concatenate([rng.integers(0, n, 4000), [0, 1, n - 1, n - 64, n // 2]]))
-    for OB, LB in ((OS, LS), (OT, LT)):
-        say("config2 full: AoS ->", OB)
-        A.remap(ctx, LA, src, LB, dst[: OB.nbytes])
-        ctx.check()
-        dh = dst[: OB.nbytes]
-        for f in range(16):
-            want = np.stack([synth.field_values(2, f, 1, spec.dtypes[f], 4, start=int(r))[0]
-                             for r in recs[:200]])
-            addr = torch.from_numpy(OB.addr_vec(recs[:200], f)).cuda()
-            got = torch.stack([dh[addr + b] for b in range(4)], 1).cpu().numpy()
-            assert np.array_equal(got, want), f
-        A.remap(ctx, LB, dh, LA, back)
-        ctx.check()
-        assert torch.equal(back, src)
+            c = min(chunk, n - s)
+            col[s:s + c] = synth.decode_torch(synth.splitmix64_torch(seed, f, s, c, "cuda"), dt, e)
+    return t
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("target", ["SoA", "AoSoA"])
+def test_config2_full_size_from_aos_every_record(ctx, target):
+    """AoS -> SoA and AoS -> AoSoA at 2^26 records: the whole destination
+    (every record, every padding byte) against the oracle's remap of the
+    same input, run over record ranges on the host cores; then the way back
+    to AoS against the input."""
+    n, spec, st, OA, OS, OT = _config2_full()
+    OB = OS if target == "SoA" else OT
+    say("config2 full: generating", n, "records in AoS; target", target)
+    src = fill_aos_device(spec, 2)
+    assert src.numel() == OA.nbytes
+    LA, LB = mirror(st, OA), mirror(st, OB)
+    dst = dev_empty(OB.nbytes)
+    say("config2 full: AoS ->", target, "on the device")
+    A.remap(ctx, LA, src, LB, dst)
+    ctx.check()
+    src_h = src.cpu().numpy()
+    say("config2 full: oracle AoS ->", target, "on", host_cores(), "host threads")
+    want = oracle_remap_threaded(OA, src_h, OB)
+    got = dst.cpu().numpy()
+    assert first_diff(got, want) is None, first_diff(got, want)
+    del got, want
+    say("config2 full:", target, "-> AoS on the device")
+    back = dev_empty(OA.nbytes)
+    A.remap(ctx, LB, dst, LA, back)
+    ctx.check()
+    assert torch.equal(back, src)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("source", ["SoA", "AoSoA"])
+def test_config2_full_size_to_aos_fresh_input(ctx, source):
+    """SoA -> AoS and AoSoA -> AoS at 2^26 records from an input drawn
+    directly in the source layout (not produced by the library): every byte
+    of the AoS result against the oracle, and against the generator's packed
+    record image."""
+    n, spec, st, OA, OS, OT = _config2_full()
+    OB = OS if source == "SoA" else OT
+    say("config2 full: generating", n, "records in", source)
+    if source == "SoA":
+        src = _soa_device(spec, 2, OS)
+    else:
+        src_h = oracle_remap_threaded(OA, fill_aos_device(spec, 2).cpu().numpy(), OT)
+        src = torch.from_numpy(src_h).cuda()
+        del src_h
+    LA, LB = mirror(st, OA), mirror(st, OB)
+    dst = dev_empty(OA.nbytes)
+    say("config2 full:", source, "-> AoS on the device")
+    A.remap(ctx, LB, src, LA, dst)
+    ctx.check()
+    say("config2 full: oracle", source, "-> AoS on", host_cores(), "host threads")
+    want = oracle_remap_threaded(OB, src.cpu().numpy(), OA)
+    got = dst.cpu().numpy()
+    assert first_diff(got, want) is None, first_diff(got, want)
+    del got
+    packed = fill_aos_device(spec, 2).cpu().numpy()
+    assert np.array_equal(packed, want)
