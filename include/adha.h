@@ -309,6 +309,18 @@ adha_status adha_section_destroy(adha_section *sec);
 adha_status adha_section_run(adha_ctx *ctx, const adha_section *sec, const adha_layout *l,
                              void *buf, uint64_t buf_cap, const int32_t *idx, uint64_t idx_count,
                              void *stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * as adha_section_run, but it allocates nothing.  A reduction's partial sums
+ * (at most 16 MiB) live in a static device array of the library, one per
+ * GPU, held until the process ends; pass 1 writes every partial pass 2
+ * reads, so nothing has to start at zero.  All calls on one GPU share that
+ * array: calls that overlap in time on one GPU (two streams, two threads)
+ * race, so serialise them.  ERR_INVALID if a reduction would need more than
+ * the array holds; other sections use no scratch. */
+adha_status adha_section_run_static(adha_ctx *ctx, const adha_section *sec, const adha_layout *l,
+                                    void *buf, uint64_t buf_cap, const int32_t *idx, uint64_t idx_count,
+                                    void *stream);
 /* Algorithmic bytes one run moves: N*(read + write bytes) for direct
  * sections, N*(4*d + d*read + write bytes) for gathers, N*(read + key
  * bytes) for reductions. */

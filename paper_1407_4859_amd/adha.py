@@ -114,6 +114,7 @@ _SIGS = {
     "adha_section_create_stencil": ([P, U32, P, U32, P, U32, U32, U32, U32, P, PP], I32T),
     "adha_section_destroy": ([P], I32T),
     "adha_section_run": ([P, P, P, P, U64, P, U64, P], I32T),
+    "adha_section_run_static": ([P, P, P, P, U64, P, U64, P], I32T),
     "adha_section_bytes": ([P, ctypes.POINTER(U64)], I32T),
     "adha_section_effective_bytes": ([P, P, ctypes.POINTER(ctypes.c_double)], I32T),
     "adha_host_section_run": ([P, P, P, U64, P, U64, P, U64, U32, ctypes.POINTER(U64)], I32T),
@@ -666,6 +667,13 @@ def section_run(ctx: Ctx, sec: Section, layout: Layout, buf, idx=None, stream=No
     bp, bc = _dev(buf)
     ip, icap = _dev(idx)
     check(lib().adha_section_run(ctx.h, sec.h, layout.h, bp, bc, ip, icap // 4, stream_ptr(stream)))
+
+
+def section_run_static(ctx: Ctx, sec: Section, layout: Layout, buf, idx=None, stream=None):
+    """adha_section_run_static: the same run with no device allocation."""
+    bp, bc = _dev(buf)
+    ip, icap = _dev(idx)
+    check(lib().adha_section_run_static(ctx.h, sec.h, layout.h, bp, bc, ip, icap // 4, stream_ptr(stream)))
 
 
 def run(ctx: Ctx, plan: Plan, in_layout: Layout, buf_a, buf_b, idx=None, stream=None):

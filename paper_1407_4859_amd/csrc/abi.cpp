@@ -213,6 +213,11 @@ adha_status adha_ctx_create(int32_t device, adha_ctx **out) {
     delete c;
     return fail(ADHA_ERR_OOM, "context scratch allocation failed");
   }
+  const adha_status ss = static_scratch_address(device, &c->c.static_scratch);
+  if (ss < 0) {
+    delete c;
+    return ss;
+  }
   *out = c;
   return ADHA_OK;
 }
@@ -722,6 +727,21 @@ adha_status adha_section_run(adha_ctx *ctx, const adha_section *sec, const adha_
   ADHA_TRY(validate_section_run(sec, l, buf, buf_cap, idx, idx_count));
   DeviceGuard g(ctx->c.device);
   return section_launch(&ctx->c, sec->d, l->d, buf, idx, (hipStream_t)stream);
+}
+
+adha_status adha_section_run_static(adha_ctx *ctx, const adha_section *sec, const adha_layout *l, void *buf,
+                                    uint64_t buf_cap, const int32_t *idx, uint64_t idx_count, void *stream) {
+  if (!ctx) return fail(ADHA_ERR_INVALID, "ctx is NULL");
+  ADHA_TRY(validate_section_run(sec, l, buf, buf_cap, idx, idx_count));
+  if (!ctx->c.static_scratch) return fail(ADHA_ERR_STATE, "the context has no static scratch address");
+  if (sec->d.op == ADHA_OP_REDUCE) {
+    const ReducePlan p = reduce_plan(&ctx->c, sec->d, l->d.shape.n);
+    if (p.partial_bytes > kReducePartialPairs * 16)
+      return fail(ADHA_ERR_INVALID, "the reduction's partials need %llu bytes, more than the %llu of the static scratch",
+                  (unsigned long long)p.partial_bytes, (unsigned long long)(kReducePartialPairs * 16));
+  }
+  DeviceGuard g(ctx->c.device);
+  return section_launch(&ctx->c, sec->d, l->d, buf, idx, (hipStream_t)stream, nullptr, ctx->c.static_scratch);
 }
 
 }  // extern "C"

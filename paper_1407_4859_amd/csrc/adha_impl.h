@@ -253,6 +253,7 @@ struct Ctx {
   uint32_t reduce_wg_per_cu = 8;     // reductions: first-pass workgroups per CU
   bool reduce_plain = false;         // reductions: plain double sums instead of compensated ones
   void *reduce_partials = nullptr;   // reductions: kReducePartialPairs * 16 bytes, allocated on first use
+  void *static_scratch = nullptr;    // the device address of this device's static scratch array
   uint32_t host_threads = 0;         // host backend threads (0: one per core, at most 64)
   uint64_t host_bad = 0;             // out-of-range indices / keys met by host sections
   ~Ctx();
@@ -260,6 +261,9 @@ struct Ctx {
 
 // Allocates the context's reduction partials once (no-op when present).
 adha_status ctx_reduce_scratch(Ctx *ctx);
+// Device address of `device`'s static scratch array (kReducePartialPairs * 16
+// bytes), looked up once per device with that device current.
+adha_status static_scratch_address(int device, void **out);
 
 // Switches to the context's device for the lifetime of the guard.
 struct DeviceGuard {

@@ -14,6 +14,8 @@
 // the explicitly rounded intrinsics so that no multiply-add is fused.
 #include <algorithm>
 #include <cstdlib>
+#include <map>
+#include <mutex>
 
 #include "adha_impl.h"
 
@@ -1254,6 +1256,35 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
       return fail(ADHA_ERR_UNSUPPORTED, "unknown op %d", sec.op);
   }
   ADHA_HIP(hipGetLastError());
+  return ADHA_OK;
+}
+
+// ------------------------------------------------------------ static scratch
+// Reduction partials for adha_section_run_static, which allocates nothing: a
+// file-scope device array (16 MiB, the most any reduction's pass 1 writes).
+// Each GPU the library runs on holds its own copy until the process ends,
+// and every call on that GPU shares it.  Host code never passes the array's
+// name (a host-side stand-in); it uses the device address looked up below.
+static __device__ __align__(256) uint64_t scratch[kReducePartialPairs * 2];
+
+adha_status static_scratch_address(int device, void **out) {
+  static std::mutex m;
+  static std::map<int, void *> addr;  // per device
+  std::lock_guard<std::mutex> lk(m);
+  auto it = addr.find(device);
+  if (it == addr.end()) {
+    DeviceGuard g(device);
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != device)
+      return fail(ADHA_ERR_DEVICE, "cannot make device %d current for its scratch array", device);
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(ADHA_ERR_DEVICE, "hipGetSymbolAddress(scratch) on device %d failed: %s", device,
+                  hipGetErrorString(e));
+    it = addr.emplace(device, p).first;
+  }
+  *out = it->second;
   return ADHA_OK;
 }
 
