@@ -82,6 +82,34 @@ def remap(src_layout: Layout, src: np.ndarray, dst_layout: Layout,
     return out
 
 
+def remap_in_place(src_layout: Layout, dst_layout: Layout, buf: np.ndarray) -> np.ndarray:
+    """A remap inside one buffer that moves only what changes.
+
+    Both layouts describe where the struct's groups sit in `buf` (placed
+    layouts).  A group of dst_layout that src_layout holds with the same
+    fields, tile and base stays as it is.  Every other group of dst_layout is
+    written: its region is zeroed, then each of its (record, field) elements
+    is copied from where src_layout holds it.  All other bytes of the buffer
+    keep their value.  Returns the new buffer (the input is not changed)."""
+    out = np.array(buf, dtype=np.uint8, copy=True)
+    stay = set()
+    for g, grp in enumerate(dst_layout.groups):
+        for h, other in enumerate(src_layout.groups):
+            if other == grp and src_layout.base[h] == dst_layout.base[g]:
+                stay.add(g)
+    moving = [f for f in range(len(dst_layout.elem_bytes)) if dst_layout.group_of[f] not in stay]
+    for g in range(len(dst_layout.groups)):
+        if g not in stay:
+            a, b = dst_layout.region(g)
+            out[a:b] = 0
+    if moving and src_layout.n:
+        sd = np.ascontiguousarray(src_layout.desc()[moving])
+        dd = np.ascontiguousarray(dst_layout.desc()[moving])
+        src = np.ascontiguousarray(buf, dtype=np.uint8)
+        lib().orc_remap(len(moving), _p(sd), _p(src), _p(dd), _p(out), 0, src_layout.n)
+    return out
+
+
 def section(layout: Layout, dtypes, op: int, read, write, degree: int, idx, buf: np.ndarray,
             r_begin: int = 0, r_end=None) -> int:
     """Run one section in place on `buf` (records [r_begin, r_end)); returns the

@@ -16,7 +16,8 @@ granule g = 64 bytes:
     group costs sum over touched fields of (e_f + g - 1);
   * a gather also reads its 4*d index bytes.
 Time = 4 us + N * bytes / (5.6e6 bytes per us); a remap between different
-layouts costs 4 us + 2 * N * S / 5.6e6.
+layouts costs 4 us + (bytes of its moving fields, read and written) / 5.6e6,
+or 4 us + 2 * N * S / 5.6e6 when the whole struct moves.
 
 Features (16 values, float32, fixed scaling), describing the section and
 the groups it touches:
@@ -84,10 +85,16 @@ def section_us(read, write, degree, L) -> float:
     return LAUNCH_US + L.n * bytes_per_record(read, write, degree, L) / BYTES_PER_US
 
 
-def remap_us(La, Lb) -> float:
+def remap_us(La, Lb, whole: bool = False) -> float:
+    """A remap between different layouts: the bytes of the moving fields
+    (planner.remap_bytes) at the model's bandwidth, plus the launch; with
+    `whole`, the whole struct moves (an executor that remaps between two
+    buffers)."""
+    from .planner import remap_bytes
     if La.key() == Lb.key():
         return 0.0
-    return LAUNCH_US + 2.0 * La.n * sum(La.elem_bytes) / BYTES_PER_US
+    b = 2.0 * La.n * sum(La.elem_bytes) if whole else float(remap_bytes(La, Lb))
+    return LAUNCH_US + b / BYTES_PER_US
 
 
 def layout_class(L) -> int:

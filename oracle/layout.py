@@ -85,6 +85,34 @@ class Layout:
             at = _roundup(at + b, GROUP_ALIGN)
         self.nbytes = at
 
+    # -- placement --------------------------------------------------------
+    def placed(self, bases) -> "Layout":
+        """The same groups at explicit byte offsets (one per group, in group
+        order, each a multiple of 256).  Group g then owns the bytes
+        [bases[g], bases[g] + roundup(B_g, 256)); regions may not overlap.
+        The size is the end of the last region."""
+        bases = [int(b) for b in bases]
+        if len(bases) != len(self.groups):
+            raise ValueError("one base per group is needed")
+        ends = []
+        for g, b in enumerate(bases):
+            if b < 0 or b % GROUP_ALIGN:
+                raise ValueError(f"base {b} of group {g} is not a multiple of {GROUP_ALIGN}")
+            ends.append(b + _roundup(self.B[g], GROUP_ALIGN))
+        spans = sorted((b, e) for b, e in zip(bases, ends) if e > b)
+        for (b0, e0), (b1, _) in zip(spans, spans[1:]):
+            if b1 < e0:
+                raise ValueError("group regions overlap")
+        out = Layout.__new__(Layout)
+        out.__dict__.update(self.__dict__)
+        out.base = bases
+        out.nbytes = max(ends) if ends else 0
+        return out
+
+    def region(self, g: int):
+        """Byte range [start, end) group g owns (its records and padding)."""
+        return self.base[g], self.base[g] + _roundup(self.B[g], GROUP_ALIGN)
+
     # -- identity ---------------------------------------------------------
     def key(self):
         return tuple(self.groups)

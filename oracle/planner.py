@@ -139,12 +139,24 @@ def catalogue(sections, n: int, elem_bytes, cap_bytes: int, full: bool = True):
     return uniq
 
 
+def moving_fields(La: Layout, Lb: Layout):
+    """Fields whose placement differs between La and Lb (section 2: the remap
+    edge is weighted by the fields the two layouts have in common).  A
+    field keeps its placement when its group in La and its group in Lb hold
+    the same fields with the same tile: that group's bytes are then the
+    same in both layouts and need not move.  Every other field moves."""
+    out = []
+    for f in range(len(La.elem_bytes)):
+        if La.groups[La.group_of[f]] != Lb.groups[Lb.group_of[f]]:
+            out.append(f)
+    return out
+
+
 def remap_bytes(La: Layout, Lb: Layout) -> int:
-    """Algorithmic bytes of the remap La -> Lb: the whole struct is read once
-    and written once (2 * N * S), or nothing when the layouts are equal."""
-    if La.key() == Lb.key():
-        return 0
-    return 2 * La.n * sum(La.elem_bytes)
+    """Algorithmic bytes of the remap La -> Lb: every moving field of every
+    record is read once and written once, 2 * N * (sum of their element
+    bytes); nothing when the layouts are equal."""
+    return 2 * La.n * sum(La.elem_bytes[f] for f in moving_fields(La, Lb))
 
 
 # --------------------------------------------------------------- shortest path
