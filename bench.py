@@ -199,11 +199,6 @@ def program_bench(A, synth, torch, timer, log2n, cost="measured", cap_bytes=64):
     ss = [A.Section.from_spec(st, s) for s in secs]
     prog = A.Program(st, ss)
     aos_l, soa_l = A.Layout.aos(st), A.Layout.soa(st)
-    log("program: filling", n, "records")
-    cap = max(aos_l.nbytes, soa_l.nbytes) + (1 << 26)
-    buf_a = torch.empty(cap, dtype=torch.uint8, device="cuda")
-    buf_b = torch.empty(cap, dtype=torch.uint8, device="cuda")
-    fill_fields(buf_a, spec, 3, torch, synth)
     idx = synth.uniform_index_torch(3, 999, n * 16, n, "cuda")
     ctx = A.Ctx(0)
     log("program: planning (%s costs)" % cost)
@@ -212,29 +207,51 @@ def program_bench(A, synth, torch, timer, log2n, cost="measured", cap_bytes=64):
     plan = A.Plan.create(ctx, prog, A.plan_opts(cost=src, catalogue=A.CAT_FULL, cap_bytes=cap_bytes, reps=3), idx=idx)
     plan_s = time.perf_counter() - t0
     analytic = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_ANALYTIC, catalogue=A.CAT_FULL, cap_bytes=cap_bytes))
+    # data that starts in AoS: the same tables solved with the entry remap charged
+    fixed = plan.with_init(A.INIT_AOS)
     plans = {"adha": plan, "all_aos": A.Plan.uniform(prog, aos_l), "all_soa": A.Plan.uniform(prog, soa_l),
-             "adha_analytic": analytic}
+             "adha_analytic": analytic, "adha_from_aos": fixed}
+    # every plan runs placed in one arena (only changed groups move)
+    arena = torch.empty(max(A.plan_arena(p)[0] for p in plans.values()), dtype=torch.uint8, device="cuda")
+    log("program: filling", n, "records; arena", arena.numel(), "bytes")
+    fill_fields(arena, spec, 3, torch, synth)
     out = {"workload": f"N=2^{log2n} records, 32 fields (20 f32, 8 i32, 4 f64; 144 B), 8 GEN sections "
                        f"(seed 3), 4 gathering 16 uniform neighbours",
-           "candidates": plan.n_candidates, "cap_bytes": cap_bytes, "plan_seconds": round(plan_s, 2)}
+           "candidates": plan.n_candidates, "cap_bytes": cap_bytes, "plan_seconds": round(plan_s, 2),
+           "executor": "placed in one arena; a remap moves only the groups that change"}
     for name, pl in plans.items():
-        first = pl.candidate(pl.choices()[0])
-        def go(pl=pl, first=first):
-            A.run(ctx, pl, first, buf_a, buf_b, idx)
+        def go(pl=pl):
+            A.run_placed(ctx, pl, arena, idx)
         ms, _ = timer.time(go, reps=5, warm=1)
         out[name + "_ms"] = round(ms, 3)
         out[name + "_choices"] = pl.choices()
+        out[name + "_arena_bytes"] = A.plan_arena(pl)[0]
     ctx.check()
     best_base = min(out["all_aos_ms"], out["all_soa_ms"])
     out["speedup_vs_best_uniform"] = round(best_base / out["adha_ms"], 3)
     out["adha_beats_both"] = out["adha_ms"] < best_base
     out["predicted_adha_ms"] = round(plan.cost / 1e3, 3)
+    # remap costs by pair: the measured table against the bytes each pair moves
+    T, R = plan.tables()
+    C = plan.n_candidates
+    offd = [R[a][b] for a in range(C) for b in range(C) if a != b and R[a][b] > 0]
+    out["remap_table_us"] = {"pairs": len(offd), "min": round(min(offd), 1), "median": round(sorted(offd)[len(offd) // 2], 1),
+                             "max": round(max(offd), 1), "aos_to_soa": round(R[0][1], 1)}
+    # data born in AoS (the entry remap charged): ADHA vs all-AoS vs all-SoA
+    # with the entry remap
+    soa_entry = A.Plan.uniform(prog, soa_l).with_init(A.INIT_AOS)
+    ms_soa_entry, _ = timer.time(lambda: A.run_placed(ctx, soa_entry, arena, idx), reps=5, warm=1)
+    out["from_aos"] = {"adha_ms": out["adha_from_aos_ms"], "all_aos_ms": out["all_aos_ms"],
+                       "all_soa_with_entry_remap_ms": round(ms_soa_entry, 3),
+                       "adha_choices": fixed.choices(), "predicted_adha_ms": round(fixed.cost / 1e3, 3)}
+    out["from_aos"]["speedup_vs_best_uniform"] = round(
+        min(out["all_aos_ms"], ms_soa_entry) / out["adha_from_aos_ms"], 3)
     # per-section kernel time under the chosen layouts (HIP events around
     # each launch; timings do not depend on the buffer's values)
     per = []
     for s, (sec, c) in enumerate(zip(ss, plan.choices())):
         lay = plan.candidate(c)
-        ms, _ = timer.time(lambda: A.section_run(ctx, sec, lay, buf_a, idx if secs[s].degree else None),
+        ms, _ = timer.time(lambda: A.section_run(ctx, sec, lay, arena, idx if secs[s].degree else None),
                            reps=7, warm=1)
         t_us = ms * 1e3
         per.append({"section": s, "degree": secs[s].degree, "read": len(secs[s].read),

@@ -166,8 +166,20 @@ adha_status adha_layout_addr(const adha_layout *l, int64_t r, int32_t f, uint64_
  * room for n_fields entries. */
 adha_status adha_layout_groups(const adha_layout *l, uint32_t *n_groups,
                                uint32_t *group_of_field, uint32_t *tile_of_group);
-/* *out = 1 when a and b have the same struct shape and address map. */
+/* *out = 1 when a and b have the same struct shape and address map (the
+ * same groups, tiles and group bases). */
 adha_status adha_layout_equal(const adha_layout *a, const adha_layout *b, int32_t *out);
+/* A placed copy of l: the same groups with explicit byte offsets bases[g]
+ * (one per group in canonical group order, multiples of 256).  Group g then
+ * owns the region [bases[g], bases[g] + roundup(roundup(N, T_g) * S_g, 256));
+ * regions may not overlap; the layout's size is the end of the last one.
+ * Bytes outside every region do not belong to the layout: remaps into it
+ * leave them alone.  Used to run a program in one buffer in which groups
+ * that two consecutive layouts share stay where they are. */
+adha_status adha_layout_place(const adha_layout *l, uint32_t n_groups, const uint64_t *bases,
+                              adha_layout **out);
+/* Group bases (n_groups entries, canonical group order). */
+adha_status adha_layout_bases(const adha_layout *l, uint64_t *bases);
 
 /* ------------------------------------------------------------ remap */
 /* Remap (section 2, the remap edge; section 3, the remap between the
@@ -178,6 +190,19 @@ adha_status adha_layout_equal(const adha_layout *a, const adha_layout *b, int32_
  * layout's size. */
 adha_status adha_remap(adha_ctx *ctx, const adha_layout *src_l, const void *src, uint64_t src_cap,
                        const adha_layout *dst_l, void *dst, uint64_t dst_cap, void *stream);
+
+/* Remap inside one buffer that moves only what changes (section 2: the
+ * remap edge is weighed by the fields two layouts have in common).  Both
+ * layouts describe where the struct's groups sit in buf (placed layouts,
+ * or canonical ones).  A group of dst_l that src_l holds with the same
+ * fields, tile and base stays untouched; every other group of dst_l is
+ * written -- its fields copied from where src_l holds them, its padding
+ * zeroed -- and so N * (their bytes) are read and written, where a whole
+ * remap moves N * S.  All other bytes of buf keep their values.  A moving
+ * group of dst_l may not overlap a group of src_l that moves
+ * (ERR_INVALID, checked before any launch); buf_cap must cover both. */
+adha_status adha_remap_in_place(adha_ctx *ctx, const adha_layout *src_l, const adha_layout *dst_l, void *buf,
+                                uint64_t buf_cap, void *stream);
 
 typedef struct {
   const adha_layout *src_layout;
@@ -426,12 +451,25 @@ adha_status adha_plan_opts_default(adha_plan_opts *o);
  * fills the cost tables from the chosen source and solves the shortest
  * path.  Measured and learned costs use device scratch the call allocates
  * and frees; gather sections are timed with idx (device, N*d entries) when
- * given, else with uniformly random neighbours.  Measured remap costs are
- * the median time of a whole-struct remap, the same for every pair of
- * different layouts.  Returns WARN_FALLBACK when LEARNED had no model. */
+ * given, else with uniformly random neighbours.  Remap costs (section 2:
+ * weighed by the fields two layouts have in common): for linear GPU
+ * programs a remap a -> b moves only the fields whose group (fields and
+ * tile) differs, as adha_run_placed runs it -- MEASURED times every ordered
+ * pair that way, ANALYTIC charges 4 us + 2*N*(their bytes) / 5.6 TB/s,
+ * LEARNED scales one measured whole-struct remap by the bytes each pair
+ * moves; for structured programs and plans over both devices every pair of
+ * different layouts costs one whole-struct remap (measured, or analytic
+ * with all N*S bytes), as their executors remap between two buffers.
+ * Returns WARN_FALLBACK when LEARNED had no model. */
 adha_status adha_plan_create(adha_ctx *ctx, const adha_program *p, const adha_plan_opts *o,
                              const int32_t *idx, uint64_t idx_count, void *stream,
                              adha_plan **out);
+/* The same linear GPU plan solved again, with its candidates and cost
+ * tables, for data that starts FREE (in the first chosen layout, at no
+ * cost) or in AoS (INIT_AOS: the entry remap from AoS is charged and run).
+ * No device work.  ERR_UNSUPPORTED for structured programs and plans over
+ * both devices. */
+adha_status adha_plan_with_init(const adha_plan *pl, adha_init init, adha_plan **out);
 /* A plan that keeps one layout for every section (the all-AoS / all-SoA
  * baselines). */
 adha_status adha_plan_uniform(const adha_program *p, const adha_layout *l, adha_plan **out);
@@ -472,15 +510,41 @@ adha_status adha_plan_tables(const adha_plan *pl, double *T, double *R);
 /* Seconds spent building the plan (catalogue, costs, path). */
 adha_status adha_plan_time(const adha_plan *pl, double *seconds);
 
-/* Runs the program under the plan.  The data starts in buf_a laid out by
- * in_layout (under INIT_FREE pass the plan's first layout, or any layout,
- * in which case a remap is made first).  Between sections with different
- * layouts the data is remapped into the other buffer.  *out_layout (owned
- * by the plan or equal to in_layout) and *out_in_b tell where it ends. */
+/* Runs the program under the plan with two buffers.  The data starts in
+ * buf_a laid out by in_layout (under INIT_FREE pass the plan's first
+ * layout, or any layout, in which case a remap is made first).  Between
+ * sections with different layouts the whole struct is remapped into the
+ * other buffer (so a linear plan priced for adha_run_placed may take longer
+ * than predicted).  *out_layout (owned by the plan or equal to in_layout)
+ * and *out_in_b tell where it ends. */
 adha_status adha_run(adha_ctx *ctx, const adha_plan *pl, const adha_layout *in_layout,
                      void *buf_a, void *buf_b, uint64_t buf_cap, const int32_t *idx,
                      uint64_t idx_count, void *stream, const adha_layout **out_layout,
                      int32_t *out_in_b);
+/* Placed execution (section 2: remap edges weighed by the fields two
+ * layouts have in common).  The program runs in one device buffer, the
+ * arena: between two sections the groups both layouts hold (same fields
+ * and tile) stay where they are and only the others are moved
+ * (adha_remap_in_place), into free space of the arena.  The placement is
+ * fixed when the plan is made: *bytes is the arena size it needs, *start
+ * the layout the data must be in before the run (the plan's first layout,
+ * or AoS under INIT_AOS, at its canonical bases from the arena's start),
+ * *end the placed layout the data ends in (both owned by the plan; remap
+ * *end to any layout to read the result).  Plans made by adha_plan_create
+ * for linear GPU programs are priced for this executor: their remap costs
+ * are per pair of layouts.  ERR_UNSUPPORTED for structured programs and
+ * plans over both devices. */
+adha_status adha_plan_arena(const adha_plan *pl, uint64_t *bytes, const adha_layout **start,
+                            const adha_layout **end);
+/* Placed layout i of the plan, i in [0, k]: i = 0 the start layout, i =
+ * s + 1 the layout section s runs in.  Owned by the plan. */
+adha_status adha_plan_placed(const adha_plan *pl, uint32_t i, const adha_layout **out);
+/* Runs the plan placed in `arena` (device, 256-byte aligned, arena_cap >=
+ * the plan's arena bytes), data starting in the plan's start layout.  idx
+ * as for adha_run.  Everything is validated before the first launch. */
+adha_status adha_run_placed(adha_ctx *ctx, const adha_plan *pl, void *arena, uint64_t arena_cap,
+                            const int32_t *idx, uint64_t idx_count, void *stream);
+
 /* Runs a plan whose sections may be mapped to the host (the same as
  * adha_run for GPU plans, which reject host sections).  The data starts in
  * dev_a (in_device 0) or host_a (in_device 1), laid out by in_layout.  A

@@ -115,6 +115,13 @@ _SIGS = {
     "adha_section_destroy": ([P], I32T),
     "adha_section_run": ([P, P, P, P, U64, P, U64, P], I32T),
     "adha_section_run_static": ([P, P, P, P, U64, P, U64, P], I32T),
+    "adha_layout_place": ([P, U32, P, PP], I32T),
+    "adha_layout_bases": ([P, P], I32T),
+    "adha_remap_in_place": ([P, P, P, P, U64, P], I32T),
+    "adha_plan_arena": ([P, ctypes.POINTER(U64), PP, PP], I32T),
+    "adha_run_placed": ([P, P, P, U64, P, U64, P], I32T),
+    "adha_plan_placed": ([P, U32, PP], I32T),
+    "adha_plan_with_init": ([P, ctypes.c_int, PP], I32T),
     "adha_section_bytes": ([P, ctypes.POINTER(U64)], I32T),
     "adha_section_effective_bytes": ([P, P, ctypes.POINTER(ctypes.c_double)], I32T),
     "adha_host_section_run": ([P, P, P, U64, P, U64, P, U64, U32, ctypes.POINTER(U64)], I32T),
@@ -310,6 +317,24 @@ class Layout:
         check(lib().adha_layout_equal(self.h, other.h, ctypes.byref(v)))
         return bool(v.value)
 
+    def n_groups(self) -> int:
+        ng = ctypes.c_uint32()
+        check(lib().adha_layout_groups(self.h, ctypes.byref(ng), None, None))
+        return ng.value
+
+    def place(self, bases):
+        """A placed copy (adha_layout_place): one base per group."""
+        h = ctypes.c_void_p()
+        arr = (ctypes.c_uint64 * max(1, len(bases)))(*[int(b) for b in bases])
+        check(lib().adha_layout_place(self.h, len(bases), arr, ctypes.byref(h)))
+        return Layout(h)
+
+    def bases(self):
+        ng = self.n_groups()
+        arr = (ctypes.c_uint64 * max(1, ng))()
+        check(lib().adha_layout_bases(self.h, arr))
+        return list(arr)[:ng]
+
 
 class Section:
     def __init__(self, st: Struct, op: int, read, write, degree: int = 0):
@@ -463,6 +488,12 @@ class Plan:
         st = check(lib().adha_plan_create(ctx.h, prog.h, ctypes.byref(opts), ip, icap // 4,
                                           stream_ptr(stream), ctypes.byref(h)))
         return cls(h, len(prog.sections), st)
+
+    def with_init(self, init: int):
+        """adha_plan_with_init: the same tables solved for another start."""
+        h = ctypes.c_void_p()
+        check(lib().adha_plan_with_init(self.h, init, ctypes.byref(h)))
+        return Plan(h, self.k)
 
     @classmethod
     def uniform(cls, prog: Program, layout: Layout):
@@ -674,6 +705,37 @@ def section_run_static(ctx: Ctx, sec: Section, layout: Layout, buf, idx=None, st
     bp, bc = _dev(buf)
     ip, icap = _dev(idx)
     check(lib().adha_section_run_static(ctx.h, sec.h, layout.h, bp, bc, ip, icap // 4, stream_ptr(stream)))
+
+
+def remap_in_place(ctx: Ctx, src_layout: Layout, dst_layout: Layout, buf, stream=None):
+    """adha_remap_in_place: move, inside buf, the groups dst_layout does not
+    share (same fields, tile and base) with src_layout."""
+    bp, bc = _dev(buf)
+    check(lib().adha_remap_in_place(ctx.h, src_layout.h, dst_layout.h, bp, bc, stream_ptr(stream)))
+
+
+def plan_arena(plan: Plan):
+    """(arena bytes, start layout, end layout) of a plan's placed execution;
+    the layouts are borrowed from the plan."""
+    b = ctypes.c_uint64()
+    s, e = ctypes.c_void_p(), ctypes.c_void_p()
+    check(lib().adha_plan_arena(plan.h, ctypes.byref(b), ctypes.byref(s), ctypes.byref(e)))
+    return b.value, Layout(s, owned=False, keep=plan), Layout(e, owned=False, keep=plan)
+
+
+def plan_placed(plan: Plan, i: int) -> Layout:
+    """The plan's placed layout i (0: start; s + 1: section s), borrowed."""
+    h = ctypes.c_void_p()
+    check(lib().adha_plan_placed(plan.h, i, ctypes.byref(h)))
+    return Layout(h, owned=False, keep=plan)
+
+
+def run_placed(ctx: Ctx, plan: Plan, arena, idx=None, stream=None):
+    """adha_run_placed: the plan in one buffer, data starting in the plan's
+    start layout (plan_arena)."""
+    ap, ac = _dev(arena)
+    ip, icap = _dev(idx)
+    check(lib().adha_run_placed(ctx.h, plan.h, ap, ac, ip, icap // 4, stream_ptr(stream)))
 
 
 def run(ctx: Ctx, plan: Plan, in_layout: Layout, buf_a, buf_b, idx=None, stream=None):

@@ -156,6 +156,42 @@ adha_status validate_remap(const adha_layout *sl, const void *src, uint64_t src_
   return ADHA_OK;
 }
 
+// A layout's content (shape, groups, tiles, bases) as key words.
+static void content_key(const LayoutDesc &L, std::vector<uint64_t> *k) {
+  k->push_back((uint64_t)L.shape.n);
+  k->push_back((uint64_t)L.shape.nfields());
+  for (int f = 0; f < L.shape.nfields(); ++f) k->push_back(((uint64_t)L.shape.dtype[f] << 32) | L.shape.ebytes[f]);
+  k->push_back(L.groups.size());
+  for (const Group &g : L.groups) {
+    k->push_back(((uint64_t)g.T << 32) | g.fields.size());
+    k->push_back(g.base);
+    for (int f : g.fields) k->push_back((uint64_t)f);
+  }
+}
+
+// The moving part of an in-place remap src -> dst inside one buffer, run
+// with a descriptor cached by the layouts' content (the same pairs recur
+// every time a plan runs).
+adha_status remap_in_place(Ctx *ctx, const LayoutDesc &src, const LayoutDesc &dst, void *buf, hipStream_t stream) {
+  LayoutDesc a, b;
+  bool moves = false;
+  ADHA_TRY(in_place_parts(src, dst, &a, &b, &moves));
+  if (!moves || a.shape.n == 0) return ADHA_OK;
+  TileShape sh;
+  ADHA_TRY(choose_shape(ctx, a, b, &sh));
+  std::vector<uint64_t> key{3, sh.R, sh.K, sh.shift, sh.wg_per_cu, sh.strided, sh.nt};
+  content_key(a, &key);
+  content_key(b, &key);
+  auto it = ctx->remap_cache.find(key);
+  if (it == ctx->remap_cache.end()) {
+    if (ctx->remap_cache.size() >= kCacheLimit) ADHA_TRY(flush_cache(ctx));
+    RemapPrepared p;
+    ADHA_TRY(remap_prepare(ctx, {&a}, {nullptr}, {&b}, {nullptr}, {sh}, &p));
+    it = ctx->remap_cache.emplace(key, p).first;
+  }
+  return remap_run(ctx, it->second, buf, buf, stream);
+}
+
 adha_status remap_one(Ctx *ctx, const adha_layout *sl, const void *src, const adha_layout *dl,
                       void *dst, hipStream_t stream) {
   if (sl->d.shape.n == 0 || dl->d.nbytes == 0) return ADHA_OK;
@@ -396,6 +432,24 @@ adha_status adha_layout_equal(const adha_layout *a, const adha_layout *b, int32_
   return ADHA_OK;
 }
 
+adha_status adha_layout_place(const adha_layout *l, uint32_t n_groups, const uint64_t *bases, adha_layout **out) {
+  if (!l || !out || (n_groups && !bases)) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (n_groups != l->d.groups.size())
+    return fail(ADHA_ERR_INVALID, "%u bases given, the layout has %zu groups", n_groups, l->d.groups.size());
+  LayoutDesc d = l->d;
+  ADHA_TRY(place_layout(&d, std::vector<uint64_t>(bases, bases + n_groups)));
+  adha_layout *p = new_layout(std::move(d));
+  if (!p) return fail(ADHA_ERR_OOM, "layout allocation failed");
+  *out = p;
+  return ADHA_OK;
+}
+
+adha_status adha_layout_bases(const adha_layout *l, uint64_t *bases) {
+  if (!l || !bases) return fail(ADHA_ERR_INVALID, "NULL argument");
+  for (size_t g = 0; g < l->d.groups.size(); ++g) bases[g] = l->d.groups[g].base;
+  return ADHA_OK;
+}
+
 // ------------------------------------------------------------------ remap
 adha_status adha_remap(adha_ctx *ctx, const adha_layout *src_l, const void *src, uint64_t src_cap,
                        const adha_layout *dst_l, void *dst, uint64_t dst_cap, void *stream) {
@@ -403,6 +457,19 @@ adha_status adha_remap(adha_ctx *ctx, const adha_layout *src_l, const void *src,
   ADHA_TRY(validate_remap(src_l, src, src_cap, dst_l, dst, dst_cap));
   DeviceGuard g(ctx->c.device);
   return remap_one(&ctx->c, src_l, src, dst_l, dst, (hipStream_t)stream);
+}
+
+adha_status adha_remap_in_place(adha_ctx *ctx, const adha_layout *src_l, const adha_layout *dst_l, void *buf,
+                                uint64_t buf_cap, void *stream) {
+  if (!ctx || !src_l || !dst_l) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (!src_l->d.shape.same(dst_l->d.shape)) return fail(ADHA_ERR_INVALID, "layouts describe different structs");
+  const uint64_t need = std::max(src_l->d.nbytes, dst_l->d.nbytes);
+  ADHA_TRY(check_dev_buf("buf", buf, buf_cap, need));
+  LayoutDesc a, b;
+  bool moves = false;
+  ADHA_TRY(in_place_parts(src_l->d, dst_l->d, &a, &b, &moves));  // checks the regions on the host
+  DeviceGuard g(ctx->c.device);
+  return remap_in_place(&ctx->c, src_l->d, dst_l->d, buf, (hipStream_t)stream);
 }
 
 adha_status adha_remap_set_shape(adha_ctx *ctx, const adha_layout *src_l, const adha_layout *dst_l,

@@ -64,10 +64,15 @@ struct LayoutDesc {
     return g.base + (uint64_t)(r >> g.logT) * g.T * g.S + (uint64_t)p[f] * g.T +
            (uint64_t)(r & (g.T - 1)) * shape.ebytes[f];
   }
-  uint64_t group_end(size_t gi) const {  // start of the next group (or the size)
-    return gi + 1 < groups.size() ? groups[gi + 1].base : nbytes;
-  }
+  // end of the region group gi owns: its records, its padding records and
+  // the padding up to the next multiple of 256 (in a canonical layout that
+  // is where the next group starts)
+  uint64_t group_end(size_t gi) const { return groups[gi].base + (groups[gi].bytes + 255) / 256 * 256; }
+  bool placed = false;  // group bases given explicitly (adha_layout_place), not canonical
+  // same shape, groups, tiles and group bases
   bool same_map(const LayoutDesc &o) const;
+  // same shape, groups and tiles (bases may differ)
+  bool same_groups(const LayoutDesc &o) const;
   bool dword_fields() const;   // every element is 4 or 8 bytes
   uint32_t max_tile() const;
   int layout_class() const;    // 0 AoS, 1 SoA, 2 tiled, 3 grouped interleaved / mixed
@@ -79,6 +84,27 @@ LayoutDesc layout_aos(const Shape &sh, uint32_t tile = 1);
 LayoutDesc layout_soa(const Shape &sh);
 LayoutDesc layout_from_parts(const Shape &sh, const std::vector<std::vector<int>> &parts,
                              uint32_t tile);
+// Gives the groups explicit bases (one per group, in group order, multiples
+// of 256, regions [base, group_end) disjoint); nbytes becomes the last end.
+adha_status place_layout(LayoutDesc *L, const std::vector<uint64_t> &bases);
+// The two groups hold the same fields with the same tile.
+inline bool same_group(const Group &a, const Group &b) { return a.T == b.T && a.fields == b.fields; }
+// Fields whose group (fields and tile) differs between a and b: the fields
+// a remap a -> b has to move when groups that agree stay where they are.
+std::vector<int> moving_fields(const LayoutDesc &a, const LayoutDesc &b);
+// Group placement for a sequence of layouts run one after another in one
+// buffer: seq[0] at its canonical bases; for every later layout, a group
+// that the previous one holds with the same fields and tile keeps its base,
+// and every other group goes to the lowest 256-aligned offset clear of all
+// of the previous layout's groups and of the new groups placed before it.
+// out[i] is seq[i] placed; *arena the bytes the whole sequence needs.
+void place_sequence(const std::vector<const LayoutDesc *> &seq, std::vector<LayoutDesc> *out, uint64_t *arena);
+// The sub-remap that an in-place remap src -> dst performs: the fields that
+// move, as a struct of their own, with the source groups they leave and the
+// destination groups they enter (bases kept).  false when nothing moves.
+// Fails when a destination group that moves overlaps a source group.
+adha_status in_place_parts(const LayoutDesc &src, const LayoutDesc &dst, LayoutDesc *sub_src, LayoutDesc *sub_dst,
+                           bool *moves);
 
 struct SectionDesc {
   Shape shape;
@@ -181,6 +207,9 @@ adha_status shape_for(Ctx *ctx, const adha_layout *a, const adha_layout *b, Tile
 adha_status remap_with_shape(Ctx *ctx, const adha_layout *sl, const void *src, const adha_layout *dl,
                              void *dst, const TileShape &sh, hipStream_t stream);
 adha_status batch_run(Ctx *c, uint32_t n, const adha_remap_item *items, uint32_t flags, hipStream_t st);
+// In one buffer: writes the groups of dst that src does not hold at the same
+// base (same fields and tile), from where src holds their fields.
+adha_status remap_in_place(Ctx *ctx, const LayoutDesc &src, const LayoutDesc &dst, void *buf, hipStream_t stream);
 // No item's destination overlaps another item's destination or source.
 adha_status check_items_disjoint(uint32_t n, const adha_remap_item *items);
 adha_status prepared_for(Ctx *ctx, const adha_layout *a, const adha_layout *b, const TileShape &sh,

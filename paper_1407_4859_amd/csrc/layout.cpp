@@ -142,11 +142,143 @@ LayoutDesc layout_from_parts(const Shape &sh, const std::vector<std::vector<int>
   return L;
 }
 
-bool LayoutDesc::same_map(const LayoutDesc &o) const {
+bool LayoutDesc::same_groups(const LayoutDesc &o) const {
   if (!shape.same(o.shape) || groups.size() != o.groups.size()) return false;
   for (size_t i = 0; i < groups.size(); ++i)
-    if (groups[i].fields != o.groups[i].fields || groups[i].T != o.groups[i].T) return false;
+    if (!same_group(groups[i], o.groups[i])) return false;
   return true;
+}
+
+bool LayoutDesc::same_map(const LayoutDesc &o) const {
+  if (!same_groups(o)) return false;
+  for (size_t i = 0; i < groups.size(); ++i)
+    if (groups[i].base != o.groups[i].base) return false;
+  return true;
+}
+
+adha_status place_layout(LayoutDesc *L, const std::vector<uint64_t> &bases) {
+  if (bases.size() != L->groups.size())
+    return fail(ADHA_ERR_INVALID, "%zu bases given for %zu groups", bases.size(), L->groups.size());
+  std::vector<std::pair<uint64_t, uint64_t>> spans;
+  for (size_t g = 0; g < bases.size(); ++g) {
+    if (bases[g] & 255u) return fail(ADHA_ERR_INVALID, "base %llu of group %zu is not a multiple of 256",
+                                     (unsigned long long)bases[g], g);
+    if (bases[g] > (1ull << 50)) return fail(ADHA_ERR_INVALID, "base of group %zu is too large", g);
+    const uint64_t size = (L->groups[g].bytes + 255) / 256 * 256;
+    if (size) spans.push_back({bases[g], bases[g] + size});
+  }
+  std::sort(spans.begin(), spans.end());
+  for (size_t i = 1; i < spans.size(); ++i)
+    if (spans[i].first < spans[i - 1].second) return fail(ADHA_ERR_INVALID, "group regions overlap");
+  uint64_t end = 0;
+  for (size_t g = 0; g < bases.size(); ++g) {
+    L->groups[g].base = bases[g];
+    end = std::max(end, L->group_end(g));
+  }
+  L->nbytes = end;
+  L->placed = true;
+  return ADHA_OK;
+}
+
+std::vector<int> moving_fields(const LayoutDesc &a, const LayoutDesc &b) {
+  std::vector<int> out;
+  for (int f = 0; f < a.shape.nfields(); ++f)
+    if (!same_group(a.groups[a.group_of[f]], b.groups[b.group_of[f]])) out.push_back(f);
+  return out;
+}
+
+void place_sequence(const std::vector<const LayoutDesc *> &seq, std::vector<LayoutDesc> *out, uint64_t *arena) {
+  out->clear();
+  *arena = 0;
+  if (seq.empty()) return;
+  out->push_back(*seq[0]);
+  *arena = seq[0]->nbytes;
+  for (size_t i = 1; i < seq.size(); ++i) {
+    const LayoutDesc &prev = out->back();
+    LayoutDesc L = *seq[i];
+    std::vector<uint64_t> bases(L.groups.size(), 0);
+    std::vector<std::pair<uint64_t, uint64_t>> busy;  // regions that may not be written
+    for (size_t h = 0; h < prev.groups.size(); ++h)
+      if (prev.groups[h].bytes) busy.push_back({prev.groups[h].base, prev.group_end(h)});
+    std::vector<char> stays(L.groups.size(), 0);
+    for (size_t g = 0; g < L.groups.size(); ++g)
+      for (size_t h = 0; h < prev.groups.size(); ++h)
+        if (same_group(L.groups[g], prev.groups[h])) {
+          bases[g] = prev.groups[h].base;
+          stays[g] = 1;
+        }
+    for (size_t g = 0; g < L.groups.size(); ++g) {
+      if (stays[g]) continue;
+      const uint64_t size = (L.groups[g].bytes + 255) / 256 * 256;
+      std::sort(busy.begin(), busy.end());
+      uint64_t at = 0;
+      for (auto &sp : busy) {
+        if (at + size <= sp.first) break;
+        at = std::max(at, sp.second);
+      }
+      bases[g] = at;
+      if (size) busy.push_back({at, at + size});
+    }
+    (void)place_layout(&L, bases);  // disjoint by construction
+    *arena = std::max(*arena, L.nbytes);
+    out->push_back(std::move(L));
+  }
+}
+
+adha_status in_place_parts(const LayoutDesc &src, const LayoutDesc &dst, LayoutDesc *sub_src, LayoutDesc *sub_dst,
+                           bool *moves) {
+  if (!src.shape.same(dst.shape)) return fail(ADHA_ERR_INVALID, "the layouts describe different structs");
+  const int F = src.shape.nfields();
+  // a destination group stays when the source holds it at the same base
+  std::vector<char> stay_d(dst.groups.size(), 0), stay_s(src.groups.size(), 0);
+  for (size_t g = 0; g < dst.groups.size(); ++g)
+    for (size_t h = 0; h < src.groups.size(); ++h)
+      if (same_group(dst.groups[g], src.groups[h]) && dst.groups[g].base == src.groups[h].base) {
+        stay_d[g] = 1;
+        stay_s[h] = 1;
+      }
+  std::vector<int> newid(F, -1);
+  Shape sub;
+  sub.n = src.shape.n;
+  for (int f = 0; f < F; ++f)
+    if (!stay_d[dst.group_of[f]]) {
+      newid[f] = sub.nfields();
+      sub.dtype.push_back(src.shape.dtype[f]);
+      sub.ebytes.push_back(src.shape.ebytes[f]);
+    }
+  *moves = sub.nfields() > 0;
+  if (!*moves) return ADHA_OK;
+  // a moving destination group may not overlap a source group that moves
+  for (size_t g = 0; g < dst.groups.size(); ++g) {
+    if (stay_d[g] || !dst.groups[g].bytes) continue;
+    const uint64_t a = dst.groups[g].base, b = dst.group_end(g);
+    for (size_t h = 0; h < src.groups.size(); ++h) {
+      if (stay_s[h] || !src.groups[h].bytes) continue;
+      const uint64_t c = src.groups[h].base, d = src.group_end(h);
+      if (a < d && c < b) return fail(ADHA_ERR_INVALID, "destination group %zu overlaps source group %zu", g, h);
+    }
+  }
+  auto part = [&](const LayoutDesc &L, const std::vector<char> &stay, LayoutDesc *out) {
+    LayoutDesc P;
+    P.shape = sub;
+    std::vector<uint64_t> bases;
+    for (size_t g = 0; g < L.groups.size(); ++g) {
+      if (stay[g]) continue;
+      Group G = L.groups[g];
+      for (int &f : G.fields) f = newid[f];
+      bases.push_back(G.base);
+      P.groups.push_back(G);
+    }
+    // the fields keep their relative order, so the canonical finish gives
+    // the same group order, offsets and sizes; then the real bases
+    finish(P);
+    std::vector<uint64_t> ordered(P.groups.size());
+    for (size_t g = 0; g < P.groups.size(); ++g) ordered[g] = bases[g];
+    return place_layout(&P, ordered) >= 0 ? (*out = std::move(P), true) : false;
+  };
+  if (!part(src, stay_s, sub_src) || !part(dst, stay_d, sub_dst))
+    return fail(ADHA_ERR_INVALID, "inconsistent group placement");
+  return ADHA_OK;
 }
 
 bool LayoutDesc::dword_fields() const {

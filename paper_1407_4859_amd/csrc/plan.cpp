@@ -38,8 +38,17 @@ struct adha_plan {
   std::vector<double> probs;
   std::vector<uint32_t> join;
   double cost = 0.0, seconds = 0.0;
+  // placed execution in one arena (adha_run_placed): the layout the data
+  // starts in, then section s's layout at s + 1, with the groups two
+  // consecutive layouts share kept in place; empty for structured programs
+  // and plans over both devices.  `whole`: the remap costs are those of
+  // whole-struct remaps (the executors that remap between two buffers).
+  std::vector<adha_layout *> placed;
+  uint64_t arena = 0;
+  bool whole = false;
   ~adha_plan() {
     for (auto *l : cands) delete l;
+    for (auto *l : placed) delete l;
   }
 };
 
@@ -230,9 +239,18 @@ double analytic_section_us(const SectionDesc &s, const LayoutDesc &l) {
   return kLaunchUs + (double)l.shape.n * analytic_bytes_per_record(s, l) / kBytesPerUs;
 }
 
-double analytic_remap_us(const LayoutDesc &a, const LayoutDesc &b) {
-  if (a.same_map(b)) return 0.0;
-  return kLaunchUs + 2.0 * (double)a.shape.n * a.shape.record_bytes() / kBytesPerUs;
+// Bytes a remap a -> b moves when the groups the layouts share stay in
+// place: 2 * N * (element bytes of the fields whose group changes).
+double moving_bytes(const LayoutDesc &a, const LayoutDesc &b) {
+  double e = 0.0;
+  for (int f : moving_fields(a, b)) e += a.shape.ebytes[f];
+  return 2.0 * (double)a.shape.n * e;
+}
+
+double analytic_remap_us(const LayoutDesc &a, const LayoutDesc &b, bool whole) {
+  if (a.same_groups(b)) return 0.0;
+  const double bytes = whole ? 2.0 * (double)a.shape.n * a.shape.record_bytes() : moving_bytes(a, b);
+  return kLaunchUs + bytes / kBytesPerUs;
 }
 
 // Median time in microseconds of `reps` runs of fn on `stream`, after one warm-up.
@@ -277,11 +295,16 @@ struct DevBuf {
 // Which section times measured_costs takes on the device (the remap figure
 // is always measured).
 enum TimeSections { kTimeAll, kTimeNone, kTimeUntrained };
+// How remap costs are measured: every pair as an in-place remap (the placed
+// executor), one whole-struct figure for every pair (the two-buffer
+// executors), or that figure scaled by the bytes each in-place remap moves.
+enum RemapCosts { kRemapPairs, kRemapWhole, kRemapScaled };
 
 static adha_status measured_costs(Ctx *ctx, const Shape &sh, const std::vector<SectionDesc> &secs,
                                   const std::vector<adha_layout *> &cands, uint32_t reps,
                                   const int32_t *idx_in, uint64_t idx_count, hipStream_t stream,
-                                  std::vector<double> *T, std::vector<double> *R, TimeSections which = kTimeAll) {
+                                  std::vector<double> *T, std::vector<double> *R, TimeSections which = kTimeAll,
+                                  RemapCosts rmode = kRemapPairs) {
   const size_t k = secs.size(), C = cands.size();
   const bool sections = which != kTimeNone;
   uint64_t maxb = 0;
@@ -310,21 +333,56 @@ static adha_status measured_costs(Ctx *ctx, const Shape &sh, const std::vector<S
                        [&] { return section_launch(ctx, secs[s], cands[c]->d, a.p, idx, stream, tab.p); },
                        &(*T)[s * C + c]));
     }
-  // The remap always moves the whole struct: one measured figure, from a
-  // few representative pairs, serves every pair of different layouts.
-  double rsum = 0.0;
-  int rn = 0;
-  for (size_t c = 1; c < C && rn < 4; ++c) {
-    double t = 0.0;
-    ADHA_TRY(time_us(stream, reps, [&] { return remap_one(ctx, cands[0], a.p, cands[c], b.p, stream); }, &t));
-    rsum += t;
-    ++rn;
-  }
-  const double rem = rn ? rsum / rn : 0.0;
   R->assign(C * C, 0.0);
-  for (size_t x = 0; x < C; ++x)
-    for (size_t y = 0; y < C; ++y)
-      if (x != y) (*R)[x * C + y] = rem;
+  if (rmode == kRemapWhole || rmode == kRemapScaled) {
+    // whole-struct remaps (two buffers): one measured figure, from a few
+    // representative pairs, serves every pair of different layouts
+    double rsum = 0.0;
+    int rn = 0;
+    for (size_t c = 1; c < C && rn < 4; ++c) {
+      double t = 0.0;
+      ADHA_TRY(time_us(stream, reps, [&] { return remap_one(ctx, cands[0], a.p, cands[c], b.p, stream); }, &t));
+      rsum += t;
+      ++rn;
+    }
+    const double rem = rn ? rsum / rn : 0.0;
+    // scaled: that figure spread over the bytes each in-place remap moves
+    const double whole_bytes = 2.0 * (double)sh.n * sh.record_bytes();
+    for (size_t x = 0; x < C; ++x)
+      for (size_t y = 0; y < C; ++y) {
+        if (cands[x]->d.same_groups(cands[y]->d)) continue;
+        if (rmode == kRemapWhole) {
+          (*R)[x * C + y] = rem;
+        } else {
+          const double frac = whole_bytes > 0 ? moving_bytes(cands[x]->d, cands[y]->d) / whole_bytes : 0.0;
+          (*R)[x * C + y] = kLaunchUs + std::max(0.0, rem - kLaunchUs) * frac;
+        }
+      }
+  } else {
+    // in-place remaps: every ordered pair timed as the placed executor runs
+    // it (the first layout at its canonical bases, the groups the second
+    // shares with it kept there, the others placed after)
+    DevBuf arena;
+    uint64_t need = 0;
+    std::vector<LayoutDesc> pl2;
+    for (size_t x = 0; x < C; ++x)
+      for (size_t y = 0; y < C; ++y) {
+        if (x == y) continue;
+        uint64_t ab = 0;
+        place_sequence({&cands[x]->d, &cands[y]->d}, &pl2, &ab);
+        need = std::max(need, ab);
+      }
+    if (need) ADHA_TRY(arena.alloc(need));
+    for (size_t x = 0; x < C; ++x)
+      for (size_t y = 0; y < C; ++y) {
+        if (x == y || cands[x]->d.same_groups(cands[y]->d)) continue;
+        uint64_t ab = 0;
+        place_sequence({&cands[x]->d, &cands[y]->d}, &pl2, &ab);
+        double t = 0.0;
+        ADHA_TRY(time_us(stream, reps, [&] { return remap_in_place(ctx, pl2[0], pl2[1], arena.p, stream); }, &t));
+        (*R)[x * C + y] = t;
+      }
+  }
   ADHA_HIP(hipStreamSynchronize(stream));
   return ADHA_OK;
 }
@@ -642,6 +700,24 @@ static adha_status measured_host_costs(Ctx *ctx, adha_plan *pl, uint32_t reps, c
   return ADHA_OK;
 }
 
+// The plan's placed sequence: the start layout at its canonical bases, then
+// each section's layout with the groups the previous one shares kept in
+// place (place_sequence), and the arena they need.
+static adha_status place_plan(adha_plan *pl, const LayoutDesc &start) {
+  for (auto *l : pl->placed) delete l;
+  pl->placed.clear();
+  std::vector<const LayoutDesc *> seq{&start};
+  for (uint32_t c : pl->choice) seq.push_back(&pl->cands[c]->d);
+  std::vector<LayoutDesc> out;
+  place_sequence(seq, &out, &pl->arena);
+  for (auto &L : out) {
+    adha_layout *l = new_layout(std::move(L));
+    if (!l) return fail(ADHA_ERR_OOM, "layout allocation failed");
+    pl->placed.push_back(l);
+  }
+  return ADHA_OK;
+}
+
 }  // namespace adha
 
 using namespace adha;
@@ -784,6 +860,9 @@ adha_status adha_plan_create(adha_ctx *ctx, const adha_program *p, const adha_pl
     pl->cands.push_back(l);
   }
   const size_t k = p->secs.size(), C = pl->cands.size();
+  // structured programs and plans over both devices run with the two-buffer
+  // executors, which remap the whole struct; linear GPU plans run placed
+  pl->whole = !p->tokens.empty() || o->devices == ADHA_DEVICES_GPU_HOST;
   adha_status result = ADHA_OK;
   adha_cost_source src = o->cost;
   hipStream_t st = (hipStream_t)stream;
@@ -806,14 +885,16 @@ adha_status adha_plan_create(adha_ctx *ctx, const adha_program *p, const adha_pl
       std::vector<double> us;
       ADHA_TRY(predict_costs(&ctx->c, feats, base, &us, st));
       pl->T = us;
-      // remap weights: a few measured whole-struct remaps (milliseconds of
-      // device time), the same figure the measured provider uses
       // the network was trained on direct loops and index gathers;
       // reductions and stencils are timed on the device
       bool untrained = false;
       for (const SectionDesc &d : p->secs) untrained |= d.op == ADHA_OP_REDUCE || d.stencil;
+      // remap weights: a few measured whole-struct remaps scaled by the
+      // bytes each pair moves (milliseconds of device time, not the seconds
+      // every pair would take)
       ADHA_TRY(measured_costs(&ctx->c, p->shape, p->secs, pl->cands, std::max<uint32_t>(1, o->reps), idx,
-                              idx_count, st, &pl->T, &pl->R, untrained ? kTimeUntrained : kTimeNone));
+                              idx_count, st, &pl->T, &pl->R, untrained ? kTimeUntrained : kTimeNone,
+                              pl->whole ? kRemapWhole : kRemapScaled));
     }
   }
   if (src == ADHA_COST_ANALYTIC) {
@@ -822,10 +903,11 @@ adha_status adha_plan_create(adha_ctx *ctx, const adha_program *p, const adha_pl
     for (size_t s = 0; s < k; ++s)
       for (size_t c = 0; c < C; ++c) pl->T[s * C + c] = analytic_section_us(p->secs[s], pl->cands[c]->d);
     for (size_t a = 0; a < C; ++a)
-      for (size_t b = 0; b < C; ++b) pl->R[a * C + b] = analytic_remap_us(pl->cands[a]->d, pl->cands[b]->d);
+      for (size_t b = 0; b < C; ++b)
+        pl->R[a * C + b] = analytic_remap_us(pl->cands[a]->d, pl->cands[b]->d, pl->whole);
   } else if (src == ADHA_COST_MEASURED) {
     ADHA_TRY(measured_costs(&ctx->c, p->shape, p->secs, pl->cands, std::max<uint32_t>(1, o->reps), idx,
-                            idx_count, st, &pl->T, &pl->R));
+                            idx_count, st, &pl->T, &pl->R, kTimeAll, pl->whole ? kRemapWhole : kRemapPairs));
   }
   if (o->devices == ADHA_DEVICES_GPU_HOST) {
     pl->hetero = true;
@@ -857,9 +939,46 @@ adha_status adha_plan_create(adha_ctx *ctx, const adha_program *p, const adha_pl
     pl->choice[s2] = nodes[s2] % (uint32_t)C;
     pl->dev[s2] = nodes[s2] >= C ? 1 : 0;
   }
+  if (!pl->whole) {
+    const LayoutDesc aos = layout_aos(p->shape);
+    ADHA_TRY(place_plan(pl.get(), o->init == ADHA_INIT_AOS ? aos : pl->cands[pl->choice[0]]->d));
+  }
   pl->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   *out = pl.release();
   return result;
+}
+
+adha_status adha_plan_with_init(const adha_plan *src, adha_init init, adha_plan **out) {
+  if (!src || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (init != ADHA_INIT_FREE && init != ADHA_INIT_AOS) return fail(ADHA_ERR_INVALID, "init must be FREE or AOS");
+  if (src->hetero || !src->tokens.empty() || src->placed.empty())
+    return fail(ADHA_ERR_UNSUPPORTED, "only linear GPU plans are solved again for another start");
+  const size_t k = src->secs.size(), C = src->cands.size();
+  if (src->T.size() != k * C || src->R.size() != C * C)
+    return fail(ADHA_ERR_STATE, "the plan has no cost tables to solve again");
+  std::unique_ptr<adha_plan> pl(new (std::nothrow) adha_plan);
+  if (!pl) return fail(ADHA_ERR_OOM, "plan allocation failed");
+  pl->shape = src->shape;
+  pl->secs = src->secs;
+  for (auto *l : src->cands) {
+    adha_layout *c = new_layout(l->d);
+    if (!c) return fail(ADHA_ERR_OOM, "layout allocation failed");
+    pl->cands.push_back(c);
+  }
+  pl->T = src->T;
+  pl->R = src->R;
+  pl->whole = false;
+  const LayoutDesc aos = layout_aos(src->shape);
+  std::vector<double> R0(C, 0.0);
+  if (init == ADHA_INIT_AOS)
+    for (size_t c = 0; c < C; ++c)
+      R0[c] = pl->cands[0]->d.same_groups(aos) ? pl->R[0 * C + c] : analytic_remap_us(aos, pl->cands[c]->d, false);
+  ADHA_TRY(pdl_solve((uint32_t)k, (uint32_t)C, pl->T.data(), pl->R.data(), R0.data(), &pl->choice, &pl->cost));
+  pl->dev.assign(k, 0);
+  ADHA_TRY(place_plan(pl.get(), init == ADHA_INIT_AOS ? aos : pl->cands[pl->choice[0]]->d));
+  pl->seconds = src->seconds;
+  *out = pl.release();
+  return ADHA_OK;
 }
 
 adha_status adha_plan_explicit(const adha_program *p, const adha_layout *const *layouts, const int32_t *devices,
@@ -893,6 +1012,8 @@ adha_status adha_plan_explicit(const adha_program *p, const adha_layout *const *
   pl->tokens = p->tokens;
   pl->probs = p->probs;
   pl->join.assign(p->probs.size(), kNoJoin);
+  pl->whole = !p->tokens.empty() || pl->hetero;
+  if (!pl->whole && k) ADHA_TRY(place_plan(pl.get(), pl->cands[pl->choice[0]]->d));
   *out = pl.release();
   return ADHA_OK;
 }
@@ -947,6 +1068,14 @@ adha_status adha_plan_uniform(const adha_program *p, const adha_layout *l, adha_
   pl->join.assign(p->probs.size(), 0);
   pl->T.assign(p->secs.size(), 0.0);
   pl->R.assign(1, 0.0);
+  pl->whole = !p->tokens.empty();
+  if (!pl->whole) {
+    const adha_status ps = place_plan(pl, l->d);
+    if (ps < 0) {
+      delete pl;
+      return ps;
+    }
+  }
   *out = pl;
   return ADHA_OK;
 }
@@ -1047,6 +1176,61 @@ adha_status adha_run(adha_ctx *ctx, const adha_plan *pl, const adha_layout *in_l
   }
   *out_layout = cur;
   *out_in_b = in_b ? 1 : 0;
+  return ADHA_OK;
+}
+
+adha_status adha_plan_arena(const adha_plan *pl, uint64_t *bytes, const adha_layout **start,
+                            const adha_layout **end) {
+  if (!pl) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (pl->placed.empty())
+    return fail(ADHA_ERR_UNSUPPORTED, "structured programs and plans over both devices do not run placed");
+  if (bytes) *bytes = pl->arena;
+  if (start) *start = pl->placed.front();
+  if (end) *end = pl->placed.back();
+  return ADHA_OK;
+}
+
+adha_status adha_plan_placed(const adha_plan *pl, uint32_t i, const adha_layout **out) {
+  if (!pl || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (pl->placed.empty())
+    return fail(ADHA_ERR_UNSUPPORTED, "structured programs and plans over both devices do not run placed");
+  if (i >= pl->placed.size()) return fail(ADHA_ERR_INVALID, "index %u out of range", i);
+  *out = pl->placed[i];
+  return ADHA_OK;
+}
+
+adha_status adha_run_placed(adha_ctx *ctx, const adha_plan *pl, void *arena, uint64_t arena_cap,
+                            const int32_t *idx, uint64_t idx_count, void *stream) {
+  if (!ctx || !pl) return fail(ADHA_ERR_INVALID, "NULL argument");
+  if (pl->placed.empty())
+    return fail(ADHA_ERR_UNSUPPORTED, "structured programs and plans over both devices do not run placed");
+  for (int32_t d : pl->dev)
+    if (d != 0) return fail(ADHA_ERR_INVALID, "the plan maps sections to the host: run it with adha_run_hetero");
+  const uint64_t need = pl->arena;
+  if (need && (!arena || ((uintptr_t)arena & 255u))) return fail(ADHA_ERR_INVALID, "arena is NULL or misaligned");
+  if (arena_cap < need)
+    return fail(ADHA_ERR_INVALID, "the arena holds %llu bytes, the plan needs %llu", (unsigned long long)arena_cap,
+                (unsigned long long)need);
+  // validate everything before the first launch
+  for (size_t s = 0; s < pl->secs.size(); ++s) {
+    adha_section tmp;
+    tmp.d = pl->secs[s];
+    ADHA_TRY(validate_section_run(&tmp, pl->placed[s + 1], arena, arena_cap, idx, idx_count));
+    if (tmp.d.op == ADHA_OP_REDUCE && need) {
+      const uintptr_t o = (uintptr_t)tmp.d.out, no = (uintptr_t)tmp.d.reduce_cells() * 8;
+      if (o < (uintptr_t)arena + need && (uintptr_t)arena < o + no)
+        return fail(ADHA_ERR_INVALID, "a reduction's result table overlaps the arena");
+    }
+  }
+  DeviceGuard g(ctx->c.device);
+  hipStream_t st = (hipStream_t)stream;
+  const adha_layout *cur = pl->placed[0];
+  for (size_t s = 0; s < pl->secs.size(); ++s) {
+    const adha_layout *L = pl->placed[s + 1];
+    if (!cur->d.same_map(L->d)) ADHA_TRY(remap_in_place(&ctx->c, cur->d, L->d, arena, st));
+    ADHA_TRY(section_launch(&ctx->c, pl->secs[s], L->d, arena, idx, st));
+    cur = L;
+  }
   return ADHA_OK;
 }
 

@@ -308,3 +308,93 @@ def test_analytic_plans_over_both_devices():
         opts = A.plan_opts(cost=A.COST_ANALYTIC, init=A.INIT_HOST_AOS)   # host start needs both devices
         h = ctypes.c_void_p()
         A.check(A.lib().adha_plan_create(None, prog.h, ctypes.byref(opts), None, 0, None, ctypes.byref(h)))
+
+
+# ---------------------------------------------------------------- placed layouts
+def test_placed_layouts_match_oracle_and_reject_bad_bases():
+    rng = random.Random(17)
+    for trial in range(25):
+        F = rng.randint(1, 9)
+        eb = [rng.choice([1, 2, 4, 8]) for _ in range(F)]
+        n = rng.choice([1, 63, 64, 1000])
+        st = A.Struct(n, [A.RAW] * F, eb)
+        gof, tiles = _rand_layout(rng, st, eb)
+        L = A.Layout.create(st, gof, tiles)
+        O = OLayout(n, eb, gof, tiles)
+        # the groups in shuffled order, each at a 256-aligned slot with a gap
+        order = list(range(len(O.groups)))
+        rng.shuffle(order)
+        at, bases = 256 * rng.randint(0, 3), [0] * len(O.groups)
+        for g in order:
+            bases[g] = at
+            at += -(-O.B[g] // 256) * 256 + 256 * rng.randint(0, 2)
+        P, OP_ = L.place(bases), O.placed(bases)
+        assert P.bases() == bases and P.nbytes == OP_.nbytes
+        for f in range(F):
+            for r in {0, n - 1, n // 2}:
+                assert P.addr(r, f) == OP_.addr(r, f)
+        assert not P.equals(L) or bases == O.base
+    st = A.Struct(1000, [A.F32] * 3)
+    L = A.Layout.soa(st)
+    for bad in ([0, 4096, 4100], [0, 4096], [0, 0, 8192], [0, 3840, 8192]):   # misaligned, count, overlaps
+        with pytest.raises(A.AdhaError):
+            L.place(bad)
+    assert L.place([8192, 0, 4096]).nbytes == 8192 + 4096
+
+
+def test_pdl_prefers_the_cheaper_remap_when_sections_cost_the_same():
+    """Two candidates that price every section alike and differ only in what
+    a remap into them moves: the shortest path takes the one that keeps more
+    groups in place, as brute force over every assignment does."""
+    n, eb = 1 << 16, [4] * 6
+    L0 = OLayout(n, eb, [0, 0, 0, 1, 2, 3], [1, 1, 1, 1])      # {0,1,2} interleaved
+    L1 = OLayout(n, eb, [0, 0, 0, 1, 1, 2], [1, 1, 1])         # keeps {0,1,2}, joins {3,4}
+    L2 = OLayout(n, eb, [0, 1, 1, 2, 2, 3], [1, 1, 1, 1])      # breaks {0,1,2} up
+    cands = [L0, L1, L2]
+    R = [[OC.remap_us(a, b) for b in cands] for a in cands]
+    assert R[0][1] < R[0][2]
+    T = [[1.0, 50.0, 50.0], [90.0, 10.0, 10.0]]
+    cost, path = OP.pdl_dp(T, R)
+    bf_cost, bf_path = OP.pdl_bruteforce(T, R)
+    assert path == bf_path == [0, 1] and cost == pytest.approx(bf_cost)
+    lib_path = (ctypes.c_uint32 * 2)()
+    c = ctypes.c_double()
+    flat = lambda m: (ctypes.c_double * (len(m) * len(m[0])))(*[v for row in m for v in row])
+    A.check(A.lib().adha_pdl_solve(2, 3, flat(T), flat(R), None, lib_path, ctypes.byref(c)))
+    assert list(lib_path) == [0, 1] and c.value == pytest.approx(cost)
+
+
+def test_analytic_plan_placement_keeps_shared_groups_in_place():
+    """The placed sequence of analytic plans of random programs: a group two
+    consecutive layouts share keeps its base, a new group never overlaps a
+    group of the layout before it, everything fits the arena, and the
+    remap cost of every pair is that of its moving fields."""
+    spec = synth.config3_struct(1 << 16)
+    st = A.Struct.from_spec(spec)
+    for seed in (3, 11, 12, 13):
+        secs = synth.random_program(seed, spec.n_fields)
+        prog = A.Program(st, [A.Section.from_spec(st, s) for s in secs])
+        opts = A.plan_opts(cost=A.COST_ANALYTIC, cap_bytes=64)
+        h = ctypes.c_void_p()
+        A.check(A.lib().adha_plan_create(None, prog.h, ctypes.byref(opts), None, 0, None, ctypes.byref(h)))
+        pl = A.Plan(h, len(secs))
+        arena, start, end = A.plan_arena(pl)
+        placed = [A.plan_placed(pl, i) for i in range(len(secs) + 1)]
+        assert start.equals(placed[0]) and end.equals(placed[-1])
+        assert start.equals(pl.candidate(pl.choices()[0]))          # canonical, at offset 0
+        for i in range(len(secs) + 1):
+            gof, tiles = placed[i].groups(spec.n_fields)
+            O = OLayout(spec.n, spec.elem_bytes, gof, tiles).placed(placed[i].bases())
+            assert O.nbytes <= arena
+            if i == 0:
+                prev = O
+                continue
+            for g, grp in enumerate(O.groups):
+                if grp in prev.groups:
+                    assert O.base[g] == prev.base[prev.groups.index(grp)]
+                else:
+                    a, b = O.region(g)
+                    for h2 in range(len(prev.groups)):
+                        c2, d2 = prev.region(h2)
+                        assert b <= c2 or d2 <= a
+            prev = O

@@ -9,6 +9,8 @@ independent within a section, and a gather never writes a field it reads.
 The plans are the one the benchmark builds and times (the full catalogue
 with measured costs, so remaps happen between runs) and the analytic-cost
 plan; the all-SoA and all-AoS uniform plans are checked too.
+Every plan runs placed in one arena (adha_run_placed), the executor the
+benchmark times: between sections only the groups that change are moved.
 Device results are remapped back to the packed record image on the device
 and compared byte for byte; a floating-point field may differ by at most
 1 ulp."""
@@ -80,9 +82,6 @@ def test_config3_full_size_plans_match_oracle(ctx):
         assert bad == 0
     del idx_h
     La = A.Layout.aos(st)
-    cap = max(La.nbytes, A.Layout.soa(st).nbytes) + (1 << 26)
-    buf_a = torch.empty(cap, dtype=torch.uint8, device="cuda")
-    buf_b = torch.empty(cap, dtype=torch.uint8, device="cuda")
     back = torch.empty(La.nbytes, dtype=torch.uint8, device="cuda")
     say("program full: planning with measured costs (the benchmark's plan)")
     plans = [("measured", A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_MEASURED, catalogue=A.CAT_FULL,
@@ -91,22 +90,18 @@ def test_config3_full_size_plans_match_oracle(ctx):
                                                               cap_bytes=64))),
              ("all-SoA", A.Plan.uniform(prog, A.Layout.soa(st))),
              ("all-AoS", A.Plan.uniform(prog, La))]
+    arena = torch.empty(max(A.plan_arena(p)[0] for _, p in plans), dtype=torch.uint8, device="cuda")
     for name, plan in plans:
-        say("program full: run", name, plan.choices())
-        buf_a[: La.nbytes].copy_(src)
-        out_h, in_b = A.run(ctx, plan, La, buf_a, buf_b, idx)
+        arena_bytes, start, end = A.plan_arena(plan)
+        say("program full: run", name, plan.choices(), "placed in", arena_bytes, "bytes")
+        # the data starts in the plan's start layout at the arena's start
+        A.remap(ctx, La, src, start, arena)
+        A.run_placed(ctx, plan, arena, idx)
         ctx.check()
-        # the data ends in one of the plan's layouts, or stays in the input
-        # layout when the plan never leaves it
-        out_l = [L for L in [La] + [plan.candidate(c) for c in range(plan.n_candidates)] if L.h.value == out_h]
-        assert len(out_l) >= 1
-        res = buf_b if in_b else buf_a
-        if out_l[0].equals(La):
-            got = res[: La.nbytes].cpu().numpy()
-        else:
-            A.remap(ctx, out_l[0], res, La, back)
-            ctx.check()
-            got = back.cpu().numpy()
+        # read the result through the end layout, back into the record image
+        A.remap(ctx, end, arena, La, back)
+        ctx.check()
+        got = back.cpu().numpy()
         if np.array_equal(got, want):
             continue
         g2, w2 = got.reshape(N, -1), want.reshape(N, -1)

@@ -210,3 +210,92 @@ def test_config2_full_size_to_aos_fresh_input(ctx, source):
     del got
     packed = fill_aos_device(spec, 2).cpu().numpy()
     assert np.array_equal(packed, want)
+
+
+# ---------------------------------------------------------------- in-place remaps
+def _placed_after(L, Lb, n_extra=0):
+    """Lb with the groups it shares with L (same fields and tile) at L's bases
+    and its other groups packed after the end of L."""
+    at = L.nbytes + 256 * n_extra
+    bases = []
+    for g, grp in enumerate(Lb.groups):
+        if grp in L.groups:
+            bases.append(L.base[L.groups.index(grp)])
+        else:
+            bases.append(at)
+            at += -(-Lb.B[g] // 256) * 256
+    return Lb.placed(bases)
+
+
+def test_in_place_remap_random_pairs_match_oracle(ctx):
+    """Random pairs of layouts (dword and byte fields, several tiles, ragged
+    N): the in-place remap moves only the destination's new groups; the
+    whole buffer, untouched bytes included, equals the oracle's."""
+    rng = random.Random(31)
+    for trial in range(40):
+        F = rng.randint(2, 12)
+        byte_mode = trial % 4 == 3
+        eb = [rng.choice([1, 2, 4, 8] if byte_mode else [4, 8]) for _ in range(F)]
+        n = rng.choice([1, 63, 64, 65, 513, 4097, 30011])
+        st = A.Struct(n, [A.RAW] * F, eb)
+        OA, OB = _rand_layout(rng, n, eb), _rand_layout(rng, n, eb)
+        if trial % 3 == 0:      # make them share a group
+            OB = OLayout(n, eb, [OA.group_of[f] for f in range(F)], [t for _, t in OA.groups])
+            g = rng.randrange(len(OB.groups))
+            gof = [OA.group_of[f] if OA.group_of[f] != g else len(OA.groups) for f in range(F)]
+            used = {x: i for i, x in enumerate(sorted(set(gof)))}
+            OB = OLayout(n, eb, [used[x] for x in gof], [1] * len(used))
+        P = _placed_after(OA, OB, n_extra=rng.randint(0, 2))
+        cols = [synth.field_values(150 + trial, f, n, synth.RAW, e) for f, e in enumerate(eb)]
+        buf_h = np.full(P.nbytes + 512, 0xA5, np.uint8)
+        buf_h[: OA.nbytes] = oracle.pack(OA, cols)
+        want = oracle.remap_in_place(OA, P, buf_h)
+        dev = dev_bytes(buf_h)
+        LA = mirror(st, OA)
+        LP = mirror(st, OB).place(P.base)
+        say("in place", trial, OA, "->", P.base, "n", n)
+        A.remap_in_place(ctx, LA, LP, dev)
+        ctx.check()
+        assert first_diff(host(dev), want) is None, (trial, first_diff(host(dev), want))
+
+
+def test_in_place_remap_rejects_overlapping_regions(ctx):
+    st = A.Struct(1000, [A.F32] * 4)
+    La = A.Layout.aos(st)
+    Ls = A.Layout.soa(st)
+    buf = torch.zeros(1 << 16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(A.AdhaError):          # SoA at offset 0 overlaps the AoS record array
+        A.remap_in_place(ctx, La, Ls, buf)
+    ok = Ls.place([16128 + 4096 * i for i in range(4)])
+    A.remap_in_place(ctx, La, ok, buf)
+    with pytest.raises(A.AdhaError):          # the buffer is too small for the destination
+        A.remap_in_place(ctx, La, ok, buf[:16384])
+    ctx.check()
+
+
+@pytest.mark.timeout(600)
+def test_config2_full_size_in_place_partial_remap(ctx):
+    """2^26 records in SoA; the target groups fields 0-3 in 64-record tiles
+    and keeps fields 4-15 as they are: only fields 0-3 move (2 GiB read and
+    written instead of 8 GiB), into space after the SoA arrays.  The whole
+    arena against the oracle's in-place remap."""
+    n, spec, st, OA, OS, OT = _config2_full()
+    eb = spec.elem_bytes
+    OB = OLayout(n, eb, [0, 0, 0, 0] + list(range(1, 13)), [64] + [1] * 12)
+    P = _placed_after(OS, OB)
+    assert P.base[1:] == OS.base[4:]
+    say("config2 in place: generating", n, "records in SoA")
+    src = _soa_device(spec, 2, OS)
+    arena = dev_empty(P.nbytes, fill=0x77)
+    arena[: OS.nbytes].copy_(src)
+    before = np.full(P.nbytes, 0x77, np.uint8)
+    before[: OS.nbytes] = src.cpu().numpy()
+    del src
+    LS = mirror(st, OS)
+    LP = mirror(st, OB).place(P.base)
+    A.remap_in_place(ctx, LS, LP, arena)
+    ctx.check()
+    got = arena.cpu().numpy()
+    say("config2 in place: oracle")
+    want = oracle.remap_in_place(OS, P, before)
+    assert first_diff(got, want) is None, first_diff(got, want)
