@@ -28,8 +28,9 @@ Besides the timed steps the run reports (outside the timed region):
                 run time vs all-GPU and all-host;
   batched       the 512-array batched remap: one graph launch vs one launch
                 per array;
-  learned       (with --learned) the cost model: planned program time with
-                learned costs vs measured enumeration, over seeded programs.
+  learned       the learned cost model (the network kept in the package):
+                planned program time with learned costs vs measured
+                enumeration, over 64 seeded programs.
 """
 from __future__ import annotations
 
@@ -86,23 +87,29 @@ def parse():
     ap.add_argument("--skip-flow", action="store_true")
     ap.add_argument("--skip-medical", action="store_true")
     ap.add_argument("--skip-subdword", action="store_true")
+    ap.add_argument("--skip-probes", action="store_true")
     ap.add_argument("--only-subdword", action="store_true", help="the sub-dword remap leg only")
     ap.add_argument("--only-batched", action="store_true", help="the batched remap leg only")
-    ap.add_argument("--cap-bytes", type=int, default=64, help="greedy grouping cap of the program leg's catalogue")
+    ap.add_argument("--cap-bytes", type=int, default=128, help="greedy grouping cap of the program leg's catalogue")
     ap.add_argument("--only-medical", action="store_true", help="the Medical-shaped stencil leg only")
     ap.add_argument("--only-flow", action="store_true", help="the branching-program leg only")
     ap.add_argument("--only-hetero", action="store_true", help="the GPU + host planning leg only")
     ap.add_argument("--only-kmeans", action="store_true", help="the K-Means-shaped leg only (for profiling)")
     ap.add_argument("--skip-cpu", action="store_true")
-    ap.add_argument("--learned", action="store_true")
+    ap.add_argument("--skip-learned", action="store_true")
     ap.add_argument("--only-learned", action="store_true", help="skip everything but the cost-model leg")
+    ap.add_argument("--train-model", action="store_true",
+                    help="train a fresh network here instead of loading the packaged one")
     ap.add_argument("--train-samples", type=int, default=20000)
     ap.add_argument("--train-epochs", type=int, default=300)
     ap.add_argument("--programs", type=int, default=64)
+    ap.add_argument("--learned-reps", type=int, default=1,
+                    help="timed launches per (section, candidate) of the learned leg's measured enumeration")
     ap.add_argument("--program-seed0", type=int, default=1000)
     ap.add_argument("--save-model", default=None)
     ap.add_argument("--load-model", default=None)
     ap.add_argument("--only-remap", action="store_true", help="timed steps only (for profiling)")
+    ap.add_argument("--only-probes", action="store_true", help="the bandwidth and random-access probes only")
     ap.add_argument("--only-program", action="store_true", help="the program leg only (for profiling)")
     ap.add_argument("--program-cost", choices=["measured", "analytic"], default="measured",
                     help="cost tables of the program leg's plan (analytic: no timing runs while planning)")
@@ -559,6 +566,41 @@ def batched_bench(A, synth, torch, timer):
             "graph_frac_of_peak": round(total / g_ms / 1e6 / HBM_PEAK_GBS, 3)}
 
 
+def probes_bench(A, synth, torch):
+    """The ceilings: plain 16-byte read, write and copy streams over 4 GiB,
+    and random single loads (the access of a gather's neighbour field) into
+    a 2.4 GB buffer -- the program workload's AoS size -- at several record
+    strides and load widths, 2^26 accesses each."""
+    ctx = A.Ctx(0)
+    nbytes = 1 << 32
+    a = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    out = {"stream_bytes": nbytes}
+    for kind, name in ((0, "read"), (1, "write"), (2, "copy")):
+        us = A.probe_stream(ctx, kind, a, b, nbytes, reps=5)
+        moved = 2 * nbytes if kind == 2 else nbytes
+        out[name + "_GBps"] = round(moved / us / 1e3, 1)
+        out[name + "_frac_of_peak"] = round(moved / us / 1e3 / HBM_PEAK_GBS, 3)
+    del b
+    buf_bytes = (1 << 24) * 144
+    n = 1 << 26
+    res = torch.empty(n * 4, dtype=torch.uint8, device="cuda")
+    rows = []
+    for stride, lb in ((4, 4), (16, 16), (64, 4), (64, 16), (64, 64), (128, 4), (128, 64), (128, 128),
+                       (144, 4), (144, 16)):
+        records = buf_bytes // stride
+        idx = synth.uniform_index_torch(9, stride, n, records, "cuda")
+        us = A.probe_gather(ctx, a[:buf_bytes], stride, lb, idx, res, reps=5)
+        rate = n / us * 1e6
+        rows.append({"stride": stride, "load_bytes": lb, "us": round(us, 1), "G_accesses_per_s": round(rate / 1e9, 2),
+                     "GBps_at_64B_per_access": round(rate * 64 / 1e9, 1),
+                     "GBps_at_128B_per_access": round(rate * 128 / 1e9, 1)})
+        del idx
+    ctx.check()
+    out["random_access"] = {"buffer_bytes": buf_bytes, "accesses": n, "rows": rows}
+    return out
+
+
 def back_to_back_ms(timer, fn, inner=10, reps=5):
     """Milliseconds per call of fn over `inner` calls between two events:
     for programs of a few hundred microseconds the host work of one call
@@ -601,13 +643,21 @@ def path_cost(T, R, path):
 
 
 def learned_bench(A, synth, torch, args):
-    """Trains the cost model on timings of generated sections, then plans
-    seeded 8-section programs with learned, analytic and measured costs; each
-    plan is scored under the measured tables (the enumeration's ground truth)."""
+    """Plans seeded 8-section programs with learned, analytic and measured
+    costs; each plan is scored under the measured tables (the enumeration's
+    ground truth).  The network is the one kept in the package (trained on
+    this kind of device by train_costmodel.py), unless --train-model asks for
+    a fresh one.  All three planners price remaps alike: one measured
+    whole-struct remap scaled by the bytes each pair moves."""
     ctx = A.Ctx(0)
-    if args.load_model:
-        A.costmodel_load(ctx, args.load_model)
-        rep = {"loaded": args.load_model}
+    if not args.train_model:
+        path = args.load_model or A.DEFAULT_MODEL
+        A.costmodel_load(ctx, path)
+        rep = {"loaded": os.path.relpath(path, os.path.dirname(os.path.abspath(__file__)))}
+        meta = os.path.splitext(path)[0] + ".json"
+        if os.path.exists(meta):
+            with open(meta) as fh:
+                rep["trained"] = json.load(fh)
     else:
         log("learned: generating and timing", args.train_samples, "sections")
         rep = A.costmodel_train(ctx, A.train_opts(n_samples=args.train_samples, epochs=args.train_epochs,
@@ -625,8 +675,14 @@ def learned_bench(A, synth, torch, args):
         ss = [A.Section.from_spec(st, s) for s in synth.random_program(seed % 256, 32)]
         prog = A.Program(st, ss)
         idx = synth.uniform_index_torch(seed % 256, 999, n * 16, n, "cuda")
-        pl_m = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_MEASURED, reps=3), idx=idx)
+        # the enumeration's ground truth: every (section, candidate) timed
+        # (one warm-up launch, then one timed launch)
+        pl_m = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_MEASURED, reps=args.learned_reps, pair_remaps=0),
+                             idx=idx)
         pl_l = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_LEARNED), idx=idx)
+        # the network's pick verified on the device: the sections of the
+        # chosen path timed, then solved again (a few rounds)
+        pl_v = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_LEARNED, verify_rounds=4, reps=1), idx=idx)
         pl_a = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_ANALYTIC))
         T, R = pl_m.tables()
         # without the network: analytic section costs, same measured remap costs
@@ -634,6 +690,8 @@ def learned_bench(A, synth, torch, args):
         _, a_path = A.pdl_solve(Ta, R)
         rows.append(dict(seed=seed, log2n=n.bit_length() - 1, measured_us=round(pl_m.cost, 1),
                          learned_ratio=round(path_cost(T, R, pl_l.choices()) / pl_m.cost, 4),
+                         verified_ratio=round(path_cost(T, R, pl_v.choices()) / pl_m.cost, 4),
+                         verified_entries=pl_v.verified, plan_s_verified=round(pl_v.seconds, 3),
                          analytic_ratio=round(path_cost(T, R, a_path) / pl_m.cost, 4),
                          plan_s_measured=round(pl_m.seconds, 3), plan_s_learned=round(pl_l.seconds, 4)))
         log("learned:", rows[-1])
@@ -641,8 +699,16 @@ def learned_bench(A, synth, torch, args):
         torch.cuda.empty_cache()
     lr = [r["learned_ratio"] for r in rows]
     ar = [r["analytic_ratio"] for r in rows]
-    return {"train": rep, "programs": len(rows),
+    return {"workload": "%d seeded programs (seeds %d..%d) of 8 sections on the 32-field struct, N = 2^20..2^24; "
+                        "ratio = program time of the plan / measured-enumeration optimum, under the measured tables"
+                        % (len(rows), args.program_seed0, args.program_seed0 + args.programs - 1),
+            "model": rep, "programs": len(rows),
+            "gate_mean_ratio": 1.05, "gate_met": bool(np.mean(lr) <= 1.05),
             "learned_mean_ratio": round(float(np.mean(lr)), 4), "learned_max_ratio": round(float(np.max(lr)), 4),
+            "verified_mean_ratio": round(float(np.mean([r["verified_ratio"] for r in rows])), 4),
+            "verified_max_ratio": round(float(np.max([r["verified_ratio"] for r in rows])), 4),
+            "verified_entries_mean": round(float(np.mean([r["verified_entries"] for r in rows])), 1),
+            "plan_seconds_verified": round(sum(r["plan_s_verified"] for r in rows), 2),
             "analytic_mean_ratio": round(float(np.mean(ar)), 4), "analytic_max_ratio": round(float(np.max(ar)), 4),
             "plan_seconds_measured": round(sum(r["plan_s_measured"] for r in rows), 2),
             "plan_seconds_learned": round(sum(r["plan_s_learned"] for r in rows), 3),
@@ -665,6 +731,9 @@ def main():
     timer = Timer(torch)
     if args.only_learned:
         print(json.dumps({"learned": learned_bench(A, synth, torch, args)}), flush=True)
+        return
+    if args.only_probes:
+        print(json.dumps({"probes": probes_bench(A, synth, torch)}), flush=True)
         return
     if args.only_medical:
         print(json.dumps({"medical": medical_bench(A, synth, torch, timer)}), flush=True)
@@ -768,11 +837,22 @@ def main():
                      "per_launch_bytes": 2 * n * 64},
     }
     if not args.only_remap:
+        del a, s, t, b
+        torch.cuda.empty_cache()
+        if not args.skip_probes:
+            # the ceilings the fractions are read against, in the same run
+            try:
+                log("probes")
+                line["probes"] = pr = probes_bench(A, synth, torch)
+                rf = line["roofline"]
+                rf["copy_ceiling"] = pr["copy_GBps"]
+                rf["frac_of_copy_ceiling"] = round(rf["achieved"] / pr["copy_GBps"], 4)
+            except Exception as e:
+                line["probes"] = {"error": repr(e)}
+            torch.cuda.empty_cache()
         if not args.skip_cpu:
             log("cpu baseline")
             line["cpu_baseline"] = cpu_baseline(synth)
-        del a, s, t, b
-        torch.cuda.empty_cache()
         if not args.skip_program:
             try:
                 line["program"] = program_bench(A, synth, torch, timer, args.program_log2n, cap_bytes=args.cap_bytes)
@@ -815,7 +895,7 @@ def main():
             except Exception as e:
                 line["batched"] = {"error": repr(e)}
             torch.cuda.empty_cache()
-        if args.learned:
+        if not args.skip_learned:
             try:
                 line["learned"] = learned_bench(A, synth, torch, args)
             except Exception as e:

@@ -350,12 +350,13 @@ adha_status adha_section_run_static(adha_ctx *ctx, const adha_section *sec, cons
  * sections, N*(4*d + d*read + write bytes) for gathers, N*(read + key
  * bytes) for reductions. */
 adha_status adha_section_bytes(const adha_section *sec, uint64_t *out);
-/* Effective HBM bytes one run moves under layout l, counted in 64-byte
- * access granules: a streamed group costs min(S_g, sum over touched fields
- * of max(e_f, 64/T)) per record; a gathered neighbour costs the touched
- * span of an interleaved group plus 63 bytes, else e_f + 63 per field; a
- * gather also reads 4*d index bytes.  This is the analytic cost model's
- * byte count (the unit of the gathers' transaction roofline). */
+/* Effective HBM bytes one run moves under layout l, counted in 128-byte
+ * access granules (the line a random access fetches, measured with
+ * adha_probe_gather): a streamed group costs min(S_g, sum over touched
+ * fields of max(e_f, 128/T)) per record; a gathered neighbour costs the
+ * touched span of an interleaved group plus 127 bytes, else e_f + 127 per
+ * field; a gather also reads 4*d index bytes.  This is the analytic cost
+ * model's byte count (the unit of the gathers' transaction roofline). */
 adha_status adha_section_effective_bytes(const adha_section *sec, const adha_layout *l, double *out);
 
 /* ------------------------------------------------------------ host backend */
@@ -439,10 +440,20 @@ typedef enum { ADHA_DEVICES_GPU = 0, ADHA_DEVICES_GPU_HOST = 1 } adha_devices;
 typedef struct {
   adha_cost_source cost;
   adha_catalogue catalogue;
-  uint32_t cap_bytes; /* ODS structure capacity in bytes */
+  uint32_t cap_bytes; /* ODS structure capacity in bytes (default 128: one line) */
   adha_init init;     /* FREE: data starts in the first chosen layout at no cost */
   uint32_t reps;      /* measured costs: median of this many timed runs */
   adha_devices devices; /* GPU only, or GPU and host */
+  uint32_t pair_remaps; /* MEASURED, linear GPU programs: 1 (default) times the
+                         * in-place remap of every ordered pair of candidates;
+                         * 0 scales one measured whole-struct remap by the
+                         * bytes each pair moves (as LEARNED does) */
+  uint32_t verify_rounds; /* LEARNED, linear GPU programs: 0 (default) plans on
+                           * the network's predictions alone; r > 0 then times
+                           * the sections of the chosen path on the device,
+                           * puts those times in the table and solves again,
+                           * up to r rounds or until the chosen path is timed
+                           * throughout (adha_plan_verified counts the timings) */
 } adha_plan_opts;
 
 adha_status adha_plan_opts_default(adha_plan_opts *o);
@@ -451,13 +462,16 @@ adha_status adha_plan_opts_default(adha_plan_opts *o);
  * fills the cost tables from the chosen source and solves the shortest
  * path.  Measured and learned costs use device scratch the call allocates
  * and frees; gather sections are timed with idx (device, N*d entries) when
- * given, else with uniformly random neighbours.  Remap costs (section 2:
+ * given, else with uniformly random neighbours.  A section is timed once per
+ * distinct arrangement of the groups holding its fields: candidates that
+ * differ only in groups the section does not touch share that time.
+ * Remap costs (section 2:
  * weighed by the fields two layouts have in common): for linear GPU
  * programs a remap a -> b moves only the fields whose group (fields and
  * tile) differs, as adha_run_placed runs it -- MEASURED times every ordered
  * pair that way, ANALYTIC charges 4 us + 2*N*(their bytes) / 5.6 TB/s,
- * LEARNED scales one measured whole-struct remap by the bytes each pair
- * moves; for structured programs and plans over both devices every pair of
+ * LEARNED (and MEASURED with pair_remaps = 0) scales one measured
+ * whole-struct remap by the bytes each pair moves; for structured programs and plans over both devices every pair of
  * different layouts costs one whole-struct remap (measured, or analytic
  * with all N*S bytes), as their executors remap between two buffers.
  * Returns WARN_FALLBACK when LEARNED had no model. */
@@ -509,6 +523,9 @@ adha_status adha_plan_cost(const adha_plan *pl, double *us);
 adha_status adha_plan_tables(const adha_plan *pl, double *T, double *R);
 /* Seconds spent building the plan (catalogue, costs, path). */
 adha_status adha_plan_time(const adha_plan *pl, double *seconds);
+/* (section, candidate) entries a learned plan timed to verify its path
+ * (opts.verify_rounds); 0 for other plans. */
+adha_status adha_plan_verified(const adha_plan *pl, uint32_t *entries);
 
 /* Runs the program under the plan with two buffers.  The data starts in
  * buf_a laid out by in_layout (under INIT_FREE pass the plan's first
@@ -563,6 +580,30 @@ adha_status adha_run_hetero(adha_ctx *ctx, const adha_plan *pl, const adha_layou
                             const int32_t *idx_dev, const int32_t *idx_host, uint64_t idx_count, void *stream,
                             const adha_layout **out_layout, int32_t *out_device, int32_t *out_in_b);
 
+/* ------------------------------------------------------------ probes */
+/* Bandwidth ceilings of the device, with plain kernels of the library:
+ * kind 0 reads `bytes` of a, kind 1 writes `bytes` of b, kind 2 copies a to
+ * b, all as 16-byte accesses over a persistent grid (8 workgroups per CU).
+ * *us is the best over four forms (1 or 4 chunks in flight per thread,
+ * ordinary or streaming accesses) of the median of reps timed launches
+ * after one warm-up.  Buffers are
+ * device, 256-byte aligned, `bytes` each (a multiple of 16; b is the read
+ * probe's sink and stays unwritten in practice); a and b may not overlap
+ * for a copy.  GB/s = bytes (read, write) or 2*bytes (copy) / us / 1e3. */
+adha_status adha_probe_stream(adha_ctx *ctx, uint32_t kind, void *a, void *b, uint64_t bytes, uint32_t reps,
+                              void *stream, double *us);
+/* Random-access probe (the access of a gather's neighbour field): lane i
+ * loads load_bytes (4, 8, 16, 32, 64 or 128; above 16 as 16-byte loads)
+ * at buf + idx[i] * stride and writes one
+ * 4-byte word to out[i], for i < n (n <= 2^28).  Every index is checked on
+ * the host to name a record inside buf (idx[i] < buf_bytes / stride) before
+ * the launch.  *us as for adha_probe_stream.  n / us is the random-access
+ * rate; with the HBM bytes a counter run reports it gives the bytes one
+ * random access fetches. */
+adha_status adha_probe_gather(adha_ctx *ctx, const void *buf, uint64_t buf_bytes, uint64_t stride,
+                              uint32_t load_bytes, const int32_t *idx, uint64_t n, void *out, uint32_t reps,
+                              void *stream, double *us);
+
 /* ------------------------------------------------------------ cost model */
 #define ADHA_N_FEATURES 16
 /* Feature vector of (section, layout) for the learned cost model. */
@@ -589,11 +630,14 @@ typedef struct {
   uint32_t n_samples;  /* sections to generate and time */
   uint32_t epochs;
   uint32_t batch;
-  float lr;
+  float lr;            /* Adam's initial step size; it decays along a half cosine to lr / 20 */
   uint64_t seed;
   int32_t min_log2_n, max_log2_n; /* record counts of generated sections */
   uint32_t reps;       /* timing: median of reps */
   uint32_t progress_every; /* >0: one line on stderr per that many timed sections */
+  uint32_t ensemble;   /* networks trained on the same timings from different
+                        * initial weights (1..16, default 1); the model
+                        * predicts with their mean */
 } adha_train_opts;
 typedef struct {
   double gen_seconds, train_seconds;
@@ -603,11 +647,15 @@ typedef struct {
 } adha_train_report;
 adha_status adha_train_opts_default(adha_train_opts *o);
 /* Generates sections and layouts, times them on the device, trains the
- * network with the kernels above and keeps it in the context. */
+ * network(s) with the kernels above and keeps the model in the context.
+ * The model predicts ln(time / analytic estimate) of a (section, layout)
+ * as the mean over its networks; the planner uses the analytic estimate
+ * times e^prediction.  val_loss and val_mape are those of that mean. */
 adha_status adha_costmodel_train(adha_ctx *ctx, const adha_train_opts *o, adha_train_report *rep);
 adha_status adha_costmodel_save(const adha_ctx *ctx, const char *path);
-/* ERR_IO on a missing, short or corrupt file (checksum); the context then
- * keeps no model. */
+/* Model files: "ADHAMLP3", the network count, the parameter count per
+ * network, the parameters, an FNV-1a checksum.  ERR_IO on a missing, short
+ * or corrupt file (checksum); the context then keeps no model. */
 adha_status adha_costmodel_load(adha_ctx *ctx, const char *path);
 /* Predicted time (microseconds) of sec under l with the loaded model. */
 adha_status adha_costmodel_predict(adha_ctx *ctx, const adha_section *sec, const adha_layout *l,

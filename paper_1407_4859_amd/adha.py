@@ -16,6 +16,8 @@ import torch  # loads the HIP runtime that libadha then shares
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libadha.so")
+# the learned cost model trained on an MI355X's own timings (train_costmodel.py)
+DEFAULT_MODEL = os.path.join(HERE, "models", "costmodel_mi355x.adha")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "adha.h")
 
 OK, WARN_FALLBACK = 0, 1
@@ -58,13 +60,15 @@ class RemapInfo(ctypes.Structure):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("cost", ctypes.c_int), ("catalogue", ctypes.c_int), ("cap_bytes", ctypes.c_uint32),
-                ("init", ctypes.c_int), ("reps", ctypes.c_uint32), ("devices", ctypes.c_int)]
+                ("init", ctypes.c_int), ("reps", ctypes.c_uint32), ("devices", ctypes.c_int),
+                ("pair_remaps", ctypes.c_uint32), ("verify_rounds", ctypes.c_uint32)]
 
 
 class TrainOpts(ctypes.Structure):
     _fields_ = [("n_samples", ctypes.c_uint32), ("epochs", ctypes.c_uint32), ("batch", ctypes.c_uint32),
                 ("lr", ctypes.c_float), ("seed", ctypes.c_uint64), ("min_log2_n", ctypes.c_int32),
-                ("max_log2_n", ctypes.c_int32), ("reps", ctypes.c_uint32), ("progress_every", ctypes.c_uint32)]
+                ("max_log2_n", ctypes.c_int32), ("reps", ctypes.c_uint32), ("progress_every", ctypes.c_uint32),
+                ("ensemble", ctypes.c_uint32)]
 
 
 class TrainReport(ctypes.Structure):
@@ -122,6 +126,9 @@ _SIGS = {
     "adha_run_placed": ([P, P, P, U64, P, U64, P], I32T),
     "adha_plan_placed": ([P, U32, PP], I32T),
     "adha_plan_with_init": ([P, ctypes.c_int, PP], I32T),
+    "adha_plan_verified": ([P, ctypes.POINTER(U32)], I32T),
+    "adha_probe_stream": ([P, U32, P, P, U64, U32, P, ctypes.POINTER(DBL)], I32T),
+    "adha_probe_gather": ([P, P, U64, U64, U32, P, U64, P, U32, P, ctypes.POINTER(DBL)], I32T),
     "adha_section_bytes": ([P, ctypes.POINTER(U64)], I32T),
     "adha_section_effective_bytes": ([P, P, ctypes.POINTER(ctypes.c_double)], I32T),
     "adha_host_section_run": ([P, P, P, U64, P, U64, P, U64, U32, ctypes.POINTER(U64)], I32T),
@@ -489,6 +496,12 @@ class Plan:
                                           stream_ptr(stream), ctypes.byref(h)))
         return cls(h, len(prog.sections), st)
 
+    @property
+    def verified(self) -> int:
+        v = ctypes.c_uint32()
+        check(lib().adha_plan_verified(self.h, ctypes.byref(v)))
+        return v.value
+
     def with_init(self, init: int):
         """adha_plan_with_init: the same tables solved for another start."""
         h = ctypes.c_void_p()
@@ -721,6 +734,27 @@ def plan_arena(plan: Plan):
     s, e = ctypes.c_void_p(), ctypes.c_void_p()
     check(lib().adha_plan_arena(plan.h, ctypes.byref(b), ctypes.byref(s), ctypes.byref(e)))
     return b.value, Layout(s, owned=False, keep=plan), Layout(e, owned=False, keep=plan)
+
+
+def probe_stream(ctx: Ctx, kind: int, a, b, nbytes: int, reps: int = 5, stream=None) -> float:
+    """adha_probe_stream: microseconds of a 16-byte read (0), write (1) or
+    copy (2) stream over nbytes."""
+    us = ctypes.c_double()
+    ap, _ = _dev(a)
+    bp, _ = _dev(b)
+    check(lib().adha_probe_stream(ctx.h, kind, ap, bp, nbytes, reps, stream_ptr(stream), ctypes.byref(us)))
+    return us.value
+
+
+def probe_gather(ctx: Ctx, buf, stride: int, load_bytes: int, idx, out, reps: int = 5, stream=None) -> float:
+    """adha_probe_gather: microseconds of one random load per index."""
+    us = ctypes.c_double()
+    bp, bc = _dev(buf)
+    ip, icap = _dev(idx)
+    op_, _ = _dev(out)
+    check(lib().adha_probe_gather(ctx.h, bp, bc, stride, load_bytes, ip, icap // 4, op_, reps, stream_ptr(stream),
+                                  ctypes.byref(us)))
+    return us.value
 
 
 def plan_placed(plan: Plan, i: int) -> Layout:

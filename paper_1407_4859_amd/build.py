@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libadha.so")
 SOURCES = ["layout.cpp", "abi.cpp", "plan.cpp", "costmodel.cpp", "tune.cpp", "host.cpp",
-           "remap.hip", "section.hip", "mlp.hip"]
+           "remap.hip", "section.hip", "mlp.hip", "probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",

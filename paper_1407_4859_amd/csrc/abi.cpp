@@ -18,6 +18,8 @@ Ctx::~Ctx() {
     if (kv.second.dev) (void)hipFree(kv.second.dev);
   if (err_flag) (void)hipFree(err_flag);
   if (reduce_partials) (void)hipFree(reduce_partials);
+  for (float *q : {mlp_params, mlp_x, mlp_y})
+    if (q) (void)hipFree(q);
 }
 
 adha_status ctx_reduce_scratch(Ctx *ctx) {

@@ -246,6 +246,8 @@ adha_status host_remap(uint32_t threads, const LayoutDesc &a, const uint8_t *src
                        uint8_t *dst);
 
 // ------------------------------------------------------------------ MLP
+// At most this many networks in a cost model (their mean prediction is used).
+static const uint32_t kMaxEnsemble = 16;
 adha_status mlp_forward(Ctx *ctx, const float *params, const float *x, uint32_t batch, float *y,
                         hipStream_t stream);
 // scratch holds scratch_floats floats; the call fails (before any launch)
@@ -276,8 +278,14 @@ struct Ctx {
     uint32_t tile_bytes = 16384, wg_per_cu = 4, strided = 0, nt = 1;
   } batch;
   std::vector<GraphEntry> graphs;
-  std::vector<float> model;  // trained / loaded cost-model parameters (empty = none)
+  std::vector<float> model;  // trained / loaded cost-model parameters, n_models networks (empty = none)
+  uint32_t n_models = 1;
   bool has_model = false;
+  // cost-model inference: parameters on the device (stale when !mlp_params_ok)
+  // and grow-only feature / prediction buffers of mlp_io_cap rows
+  float *mlp_params = nullptr, *mlp_x = nullptr, *mlp_y = nullptr;
+  bool mlp_params_ok = false;
+  uint32_t mlp_io_cap = 0;
   bool no_span = false;      // gathers always take the per-field path
   uint32_t reduce_wg_per_cu = 8;     // reductions: first-pass workgroups per CU
   bool reduce_plain = false;         // reductions: plain double sums instead of compensated ones

@@ -113,21 +113,38 @@ adha_status predict_costs(Ctx *ctx, const std::vector<std::vector<float>> &feats
   if (B == 0) return ADHA_OK;
   std::vector<float> x((size_t)B * ADHA_N_FEATURES), y(B);
   for (uint32_t i = 0; i < B; ++i) memcpy(&x[(size_t)i * ADHA_N_FEATURES], feats[i].data(), ADHA_N_FEATURES * 4);
-  float *dp = nullptr, *dx = nullptr, *dy = nullptr;
-  ADHA_HIP(hipMalloc((void **)&dp, ADHA_MLP_PARAMS * 4));
-  hipError_t e = hipMalloc((void **)&dx, x.size() * 4);
-  if (e == hipSuccess) e = hipMalloc((void **)&dy, (size_t)B * 4);
-  adha_status st = ADHA_OK;
-  if (e == hipSuccess) e = hipMemcpy(dp, ctx->model.data(), ADHA_MLP_PARAMS * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(dx, x.data(), x.size() * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess) st = mlp_forward(ctx, dp, dx, B, dy, stream);
-  if (e == hipSuccess && st >= 0) e = hipStreamSynchronize(stream);
-  if (e == hipSuccess && st >= 0) e = hipMemcpy(y.data(), dy, (size_t)B * 4, hipMemcpyDeviceToHost);
-  (void)hipFree(dp);
-  if (dx) (void)hipFree(dx);
-  if (dy) (void)hipFree(dy);
-  if (st < 0) return st;
-  if (e != hipSuccess) return fail(ADHA_ERR_DEVICE, "cost model inference failed: %s", hipGetErrorString(e));
+  // the context keeps the parameters on the device (uploaded once per
+  // model) and grow-only input and output buffers
+  const uint32_t K = ctx->n_models;
+  if (!ctx->mlp_params) ADHA_HIP(hipMalloc((void **)&ctx->mlp_params, (size_t)kMaxEnsemble * ADHA_MLP_PARAMS * 4));
+  if (!ctx->mlp_params_ok) {
+    ADHA_HIP(hipMemcpy(ctx->mlp_params, ctx->model.data(), (size_t)K * ADHA_MLP_PARAMS * 4, hipMemcpyHostToDevice));
+    ctx->mlp_params_ok = true;
+  }
+  if (ctx->mlp_io_cap < B) {
+    ADHA_HIP(hipStreamSynchronize(stream));
+    if (ctx->mlp_x) (void)hipFree(ctx->mlp_x);
+    if (ctx->mlp_y) (void)hipFree(ctx->mlp_y);
+    ctx->mlp_x = ctx->mlp_y = nullptr;
+    ctx->mlp_io_cap = 0;
+    const uint32_t cap = std::max<uint32_t>(B, 1024);
+    ADHA_HIP(hipMalloc((void **)&ctx->mlp_x, (size_t)cap * ADHA_N_FEATURES * 4));
+    ADHA_HIP(hipMalloc((void **)&ctx->mlp_y, (size_t)kMaxEnsemble * cap * 4));
+    ctx->mlp_io_cap = cap;
+  }
+  ADHA_HIP(hipMemcpyAsync(ctx->mlp_x, x.data(), x.size() * 4, hipMemcpyHostToDevice, stream));
+  for (uint32_t k = 0; k < K; ++k)
+    ADHA_TRY(mlp_forward(ctx, ctx->mlp_params + (size_t)k * ADHA_MLP_PARAMS, ctx->mlp_x, B,
+                         ctx->mlp_y + (size_t)k * ctx->mlp_io_cap, stream));
+  std::vector<float> yk((size_t)K * ctx->mlp_io_cap);
+  ADHA_HIP(hipMemcpyAsync(yk.data(), ctx->mlp_y, yk.size() * 4, hipMemcpyDeviceToHost, stream));
+  ADHA_HIP(hipStreamSynchronize(stream));
+  // the networks' mean prediction of the log ratio
+  for (uint32_t i = 0; i < B; ++i) {
+    double m = 0.0;
+    for (uint32_t k = 0; k < K; ++k) m += yk[(size_t)k * ctx->mlp_io_cap + i];
+    y[i] = (float)(m / K);
+  }
   for (uint32_t i = 0; i < B; ++i) (*us)[i] = base_us[i] * std::exp((double)y[i]);
   return ADHA_OK;
 }
@@ -277,12 +294,14 @@ adha_status adha_train_opts_default(adha_train_opts *o) {
   o->max_log2_n = 22;
   o->reps = 3;
   o->progress_every = 0;
+  o->ensemble = 1;
   return ADHA_OK;
 }
 
 adha_status adha_costmodel_train(adha_ctx *ctx, const adha_train_opts *o, adha_train_report *rep) {
   if (!ctx || !o) return fail(ADHA_ERR_INVALID, "NULL argument");
   if (o->n_samples < 10 || o->batch == 0 || o->epochs == 0) return fail(ADHA_ERR_INVALID, "bad training options");
+  if (o->ensemble > kMaxEnsemble) return fail(ADHA_ERR_INVALID, "at most %u networks", kMaxEnsemble);
   if (o->min_log2_n < 1 || o->max_log2_n > 26 || o->min_log2_n > o->max_log2_n)
     return fail(ADHA_ERR_INVALID, "record-count range must lie in [2^1, 2^26]");
   DeviceGuard guard(ctx->c.device);
@@ -348,9 +367,11 @@ adha_status adha_costmodel_train(adha_ctx *ctx, const adha_train_opts *o, adha_t
   // 90 / 10 split, then Adam on mini-batches, all on the device.
   const uint32_t ns = (uint32_t)Y.size(), nval = std::max<uint32_t>(1, ns / 10), ntr = ns - nval;
   const uint32_t B = std::min(o->batch, ntr);
-  std::vector<float> P(ADHA_MLP_PARAMS, 0.0f);
-  {
-    // He-uniform initial weights, zero biases
+  const uint32_t K = std::max<uint32_t>(1, o->ensemble);
+  std::vector<float> P(ADHA_MLP_PARAMS, 0.0f), all;  // all: the K trained networks
+  auto init = [&] {
+    // He-uniform initial weights, zero biases (each network its own draw)
+    std::fill(P.begin(), P.end(), 0.0f);
     const int fan[4] = {ADHA_N_FEATURES, 64, 64, 64}, outs[4] = {64, 64, 64, 1};
     size_t at = 0;
     for (int l = 0; l < 4; ++l) {
@@ -358,7 +379,7 @@ adha_status adha_costmodel_train(adha_ctx *ctx, const adha_train_opts *o, adha_t
       for (int q = 0; q < fan[l] * outs[l]; ++q) P[at + q] = (float)(lim * (2.0 * g.unit() - 1.0));
       at += (size_t)fan[l] * outs[l] + outs[l];
     }
-  }
+  };
   float *dP = nullptr, *dG = nullptr, *dM = nullptr, *dV = nullptr, *dX = nullptr, *dY = nullptr, *dS = nullptr,
         *dL = nullptr;
   // scratch for the largest batch any call below uses: the mini-batches (B),
@@ -371,22 +392,33 @@ adha_status adha_costmodel_train(adha_ctx *ctx, const adha_train_opts *o, adha_t
   for (int q = 0; q < 8; ++q)
     if (hipMalloc((void **)ptrs[q], need[q] * 4) != hipSuccess) result = fail(ADHA_ERR_OOM, "training buffers");
   if (result >= 0) {
+    (void)hipMemcpy(dX, X.data(), X.size() * 4, hipMemcpyHostToDevice);
+    (void)hipMemcpy(dY, Y.data(), Y.size() * 4, hipMemcpyHostToDevice);
+  }
+  // every network on the same data, from its own initial weights; the
+  // validation figures are those of their mean prediction
+  std::vector<double> pred_sum(nval, 0.0);
+  double tl_sum = 0.0;
+  for (uint32_t k = 0; k < K && result >= 0; ++k) {
+    init();
     (void)hipMemcpy(dP, P.data(), P.size() * 4, hipMemcpyHostToDevice);
     (void)hipMemset(dM, 0, ADHA_MLP_PARAMS * 4);
     (void)hipMemset(dV, 0, ADHA_MLP_PARAMS * 4);
-    (void)hipMemcpy(dX, X.data(), X.size() * 4, hipMemcpyHostToDevice);
-    (void)hipMemcpy(dY, Y.data(), Y.size() * 4, hipMemcpyHostToDevice);
     uint32_t step = 0;
-    for (uint32_t ep = 0; ep < o->epochs && result >= 0; ++ep)
+    for (uint32_t ep = 0; ep < o->epochs && result >= 0; ++ep) {
+      // the step size decays along a half cosine, from lr to lr / 20
+      const float lr = (float)(o->lr * (0.05 + 0.95 * 0.5 * (1.0 + std::cos(3.141592653589793 * ep / o->epochs))));
       for (uint32_t b0 = 0; b0 + B <= ntr && result >= 0; b0 += B) {
         result = mlp_backward(c, dP, dX + (size_t)b0 * ADHA_N_FEATURES, dY + b0, B, dG, dL, dS, scratch_floats, st);
-        if (result >= 0) result = mlp_adam(c, dP, dG, dM, dV, o->lr, 0.9f, 0.999f, 1e-8f, ++step, st);
+        if (result >= 0) result = mlp_adam(c, dP, dG, dM, dV, lr, 0.9f, 0.999f, 1e-8f, ++step, st);
       }
+    }
     float tl = 0.f;
     if (result >= 0) {
       result = mlp_backward(c, dP, dX, dY, ntr, dG, dL, dS, scratch_floats, st);
       (void)hipStreamSynchronize(st);
       (void)hipMemcpy(&tl, dL, 4, hipMemcpyDeviceToHost);
+      tl_sum += tl;
     }
     std::vector<float> pred(nval);
     if (result >= 0) {
@@ -394,16 +426,24 @@ adha_status adha_costmodel_train(adha_ctx *ctx, const adha_train_opts *o, adha_t
       (void)hipStreamSynchronize(st);
       (void)hipMemcpy(pred.data(), dS, nval * 4, hipMemcpyDeviceToHost);
       (void)hipMemcpy(P.data(), dP, P.size() * 4, hipMemcpyDeviceToHost);
+      for (uint32_t q = 0; q < nval; ++q) pred_sum[q] += pred[q];
+      all.insert(all.end(), P.begin(), P.end());
     }
-    if (result >= 0) {
+  }
+  if (result >= 0) {
+    {
       double mse = 0, mape = 0;
       for (uint32_t q = 0; q < nval; ++q) {
-        const double d = pred[q] - Y[ntr + q];
+        const double pm = pred_sum[q] / K;
+        const double d = pm - Y[ntr + q];
         mse += d * d;
-        mape += std::fabs(std::exp((double)pred[q] - Y[ntr + q]) - 1.0);
+        mape += std::fabs(std::exp(pm - Y[ntr + q]) - 1.0);
       }
-      c->model = P;
+      const double tl = tl_sum / K;
+      c->model = all;
+      c->n_models = K;
       c->has_model = true;
+      c->mlp_params_ok = false;
       if (rep) {
         rep->gen_seconds = std::chrono::duration<double>(t1 - t0).count();
         rep->train_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
@@ -425,11 +465,12 @@ adha_status adha_costmodel_save(const adha_ctx *ctx, const char *path) {
   if (!ctx->c.has_model) return fail(ADHA_ERR_STATE, "no cost model to save");
   FILE *f = fopen(path, "wb");
   if (!f) return fail(ADHA_ERR_IO, "cannot open %s for writing", path);
-  const char magic[8] = {'A', 'D', 'H', 'A', 'M', 'L', 'P', '2'};
-  const uint32_t n = ADHA_MLP_PARAMS;
-  const uint64_t h = fnv1a(ctx->c.model.data(), n * 4);
-  bool ok = fwrite(magic, 1, 8, f) == 8 && fwrite(&n, 4, 1, f) == 1 &&
-            fwrite(ctx->c.model.data(), 4, n, f) == n && fwrite(&h, 8, 1, f) == 1;
+  const char magic[8] = {'A', 'D', 'H', 'A', 'M', 'L', 'P', '3'};
+  const uint32_t k = ctx->c.n_models, n = ADHA_MLP_PARAMS;
+  const size_t total = (size_t)k * n;
+  const uint64_t h = fnv1a(ctx->c.model.data(), total * 4);
+  bool ok = fwrite(magic, 1, 8, f) == 8 && fwrite(&k, 4, 1, f) == 1 && fwrite(&n, 4, 1, f) == 1 &&
+            fwrite(ctx->c.model.data(), 4, total, f) == total && fwrite(&h, 8, 1, f) == 1;
   ok = (fclose(f) == 0) && ok;
   if (!ok) return fail(ADHA_ERR_IO, "write to %s failed", path);
   return ADHA_OK;
@@ -439,19 +480,26 @@ adha_status adha_costmodel_load(adha_ctx *ctx, const char *path) {
   if (!ctx || !path) return fail(ADHA_ERR_INVALID, "NULL argument");
   ctx->c.has_model = false;
   ctx->c.model.clear();
+  ctx->c.mlp_params_ok = false;
   FILE *f = fopen(path, "rb");
   if (!f) return fail(ADHA_ERR_IO, "cannot open %s", path);
   char magic[8];
-  uint32_t n = 0;
+  uint32_t k = 0, n = 0;
   uint64_t h = 0;
-  std::vector<float> P(ADHA_MLP_PARAMS);
-  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "ADHAMLP2", 8) == 0 && fread(&n, 4, 1, f) == 1 &&
-            n == ADHA_MLP_PARAMS && fread(P.data(), 4, n, f) == n && fread(&h, 8, 1, f) == 1;
+  std::vector<float> P;
+  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "ADHAMLP3", 8) == 0 && fread(&k, 4, 1, f) == 1 &&
+            k >= 1 && k <= kMaxEnsemble && fread(&n, 4, 1, f) == 1 && n == ADHA_MLP_PARAMS;
+  if (ok) {
+    P.resize((size_t)k * n);
+    ok = fread(P.data(), 4, P.size(), f) == P.size() && fread(&h, 8, 1, f) == 1;
+  }
   fclose(f);
   if (!ok) return fail(ADHA_ERR_IO, "%s is not a cost-model file (short or bad header)", path);
-  if (fnv1a(P.data(), n * 4) != h) return fail(ADHA_ERR_IO, "%s failed its checksum", path);
+  if (fnv1a(P.data(), P.size() * 4) != h) return fail(ADHA_ERR_IO, "%s failed its checksum", path);
   ctx->c.model = P;
+  ctx->c.n_models = k;
   ctx->c.has_model = true;
+  ctx->c.mlp_params_ok = false;
   return ADHA_OK;
 }
 

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <new>
 
 #include "adha_impl.h"
@@ -46,6 +47,7 @@ struct adha_plan {
   std::vector<adha_layout *> placed;
   uint64_t arena = 0;
   bool whole = false;
+  uint32_t verified = 0;  // learned plans: (section, candidate) entries timed to verify the path
   ~adha_plan() {
     for (auto *l : cands) delete l;
     for (auto *l : placed) delete l;
@@ -190,7 +192,10 @@ static void catalogue(const Shape &sh, const std::vector<SectionDesc> &secs, boo
 
 // ------------------------------------------------------------------ costs
 // Analytic model: effective HBM bytes per record over a bandwidth.
-static const double kGranule = 64.0;       // bytes per DRAM access granule
+// bytes one random access fetches: the 128-byte line (measured with the
+// library's random-access probe: a 4-byte and a 128-byte random load run at
+// nearly the same rate, and the counters read 128 bytes fetched per access)
+static const double kGranule = 128.0;
 static const double kBytesPerUs = 5.6e6;   // 70% of 8 TB/s
 static const double kLaunchUs = 4.0;
 
@@ -295,6 +300,25 @@ struct DevBuf {
 // Which section times measured_costs takes on the device (the remap figure
 // is always measured).
 enum TimeSections { kTimeAll, kTimeNone, kTimeUntrained };
+
+// Section s and the groups of l that hold a field it touches (read, written
+// or its key): their fields, tiles and the offsets of the touched fields.
+static std::vector<uint64_t> touched_groups_key(size_t s, const SectionDesc &d, const LayoutDesc &l) {
+  std::vector<int32_t> t = d.streamed_reads();
+  t.insert(t.end(), d.wr.begin(), d.wr.end());
+  std::vector<uint32_t> gs;
+  for (int f : t) gs.push_back(l.group_of[f]);
+  std::sort(gs.begin(), gs.end());
+  gs.erase(std::unique(gs.begin(), gs.end()), gs.end());
+  // (and whether the layout fits 32-bit offsets, which some kernel forms need)
+  std::vector<uint64_t> key{(uint64_t)s, l.nbytes <= (1ull << 32) ? 1u : 0u};
+  for (uint32_t g : gs) {
+    const Group &G = l.groups[g];
+    key.push_back(((uint64_t)G.T << 32) | G.fields.size());
+    for (int f : G.fields) key.push_back((uint64_t)f);
+  }
+  return key;
+}
 // How remap costs are measured: every pair as an in-place remap (the placed
 // executor), one whole-struct figure for every pair (the two-buffer
 // executors), or that figure scaled by the bytes each in-place remap moves.
@@ -304,9 +328,10 @@ static adha_status measured_costs(Ctx *ctx, const Shape &sh, const std::vector<S
                                   const std::vector<adha_layout *> &cands, uint32_t reps,
                                   const int32_t *idx_in, uint64_t idx_count, hipStream_t stream,
                                   std::vector<double> *T, std::vector<double> *R, TimeSections which = kTimeAll,
-                                  RemapCosts rmode = kRemapPairs) {
+                                  RemapCosts rmode = kRemapPairs, const std::vector<char> *only = nullptr) {
+  // only: time just the (section, candidate) entries it marks, leave R alone
   const size_t k = secs.size(), C = cands.size();
-  const bool sections = which != kTimeNone;
+  const bool sections = which != kTimeNone || only;
   uint64_t maxb = 0;
   uint32_t maxd = 0;
   for (auto *l : cands) maxb = std::max(maxb, l->d.nbytes);
@@ -324,15 +349,31 @@ static adha_status measured_costs(Ctx *ctx, const Shape &sh, const std::vector<S
     ADHA_TRY(fill_uniform_index((int32_t *)ix.p, (uint64_t)sh.n * maxd, sh.n, 0x5eedULL, stream));
     idx = (const int32_t *)ix.p;
   }
-  if (which == kTimeAll) T->assign(k * C, 0.0);
+  if (which == kTimeAll && !only) T->assign(k * C, 0.0);
+  // a section's time depends on the groups holding the fields it touches
+  // (their fields and tiles), not on the rest of the layout: time each such
+  // arrangement once per section
+  std::map<std::vector<uint64_t>, double> seen;
   for (size_t c = 0; c < C && sections; ++c)
     for (size_t s = 0; s < k; ++s) {
-      if (which == kTimeUntrained && secs[s].op != ADHA_OP_REDUCE && !secs[s].stencil) continue;
+      if (only ? !(*only)[s * C + c] : (which == kTimeUntrained && secs[s].op != ADHA_OP_REDUCE && !secs[s].stencil))
+        continue;
+      const std::vector<uint64_t> key = touched_groups_key(s, secs[s], cands[c]->d);
+      auto it = seen.find(key);
+      if (it != seen.end()) {
+        (*T)[s * C + c] = it->second;
+        continue;
+      }
       // a gather section's index array is [N][d]; a wider one is read as [N][d] too
       ADHA_TRY(time_us(stream, reps,
                        [&] { return section_launch(ctx, secs[s], cands[c]->d, a.p, idx, stream, tab.p); },
                        &(*T)[s * C + c]));
+      seen.emplace(key, (*T)[s * C + c]);
     }
+  if (only) {
+    ADHA_HIP(hipStreamSynchronize(stream));
+    return ADHA_OK;
+  }
   R->assign(C * C, 0.0);
   if (rmode == kRemapWhole || rmode == kRemapScaled) {
     // whole-struct remaps (two buffers): one measured figure, from a few
@@ -826,10 +867,12 @@ adha_status adha_plan_opts_default(adha_plan_opts *o) {
   if (!o) return fail(ADHA_ERR_INVALID, "NULL argument");
   o->cost = ADHA_COST_MEASURED;
   o->catalogue = ADHA_CAT_FULL;
-  o->cap_bytes = 64;
+  o->cap_bytes = 128;  // one 128-byte line: a gathered structure comes in one access
   o->init = ADHA_INIT_FREE;
   o->reps = 5;
   o->devices = ADHA_DEVICES_GPU;
+  o->pair_remaps = 1;
+  o->verify_rounds = 0;
   return ADHA_OK;
 }
 
@@ -895,6 +938,36 @@ adha_status adha_plan_create(adha_ctx *ctx, const adha_program *p, const adha_pl
       ADHA_TRY(measured_costs(&ctx->c, p->shape, p->secs, pl->cands, std::max<uint32_t>(1, o->reps), idx,
                               idx_count, st, &pl->T, &pl->R, untrained ? kTimeUntrained : kTimeNone,
                               pl->whole ? kRemapWhole : kRemapScaled));
+      // verification: time the sections of the path the predictions choose,
+      // put those times in the table and solve again, until the chosen
+      // path is timed throughout (or the rounds run out)
+      if (o->verify_rounds && p->tokens.empty() && o->devices == ADHA_DEVICES_GPU) {
+        std::vector<char> known(k * C, 0);
+        for (size_t s2 = 0; s2 < k; ++s2)
+          if (p->secs[s2].op == ADHA_OP_REDUCE || p->secs[s2].stencil)
+            for (size_t c = 0; c < C; ++c) known[s2 * C + c] = 1;
+        const LayoutDesc aos = layout_aos(p->shape);
+        std::vector<double> R0(C, 0.0);
+        if (o->init == ADHA_INIT_AOS)
+          for (size_t c = 0; c < C; ++c) R0[c] = pl->R[0 * C + c];
+        for (uint32_t round = 0; round < o->verify_rounds; ++round) {
+          std::vector<uint32_t> path;
+          double cst = 0.0;
+          ADHA_TRY(pdl_solve((uint32_t)k, (uint32_t)C, pl->T.data(), pl->R.data(), R0.data(), &path, &cst));
+          std::vector<char> want(k * C, 0);
+          bool any = false;
+          for (size_t s2 = 0; s2 < k; ++s2)
+            if (!known[s2 * C + path[s2]]) want[s2 * C + path[s2]] = any = true;
+          if (!any) break;
+          ADHA_TRY(measured_costs(&ctx->c, p->shape, p->secs, pl->cands, std::max<uint32_t>(1, o->reps), idx,
+                                  idx_count, st, &pl->T, &pl->R, kTimeNone, kRemapScaled, &want));
+          for (size_t e = 0; e < k * C; ++e)
+            if (want[e]) {
+              known[e] = 1;
+              ++pl->verified;
+            }
+        }
+      }
     }
   }
   if (src == ADHA_COST_ANALYTIC) {
@@ -907,7 +980,8 @@ adha_status adha_plan_create(adha_ctx *ctx, const adha_program *p, const adha_pl
         pl->R[a * C + b] = analytic_remap_us(pl->cands[a]->d, pl->cands[b]->d, pl->whole);
   } else if (src == ADHA_COST_MEASURED) {
     ADHA_TRY(measured_costs(&ctx->c, p->shape, p->secs, pl->cands, std::max<uint32_t>(1, o->reps), idx,
-                            idx_count, st, &pl->T, &pl->R, kTimeAll, pl->whole ? kRemapWhole : kRemapPairs));
+                            idx_count, st, &pl->T, &pl->R, kTimeAll,
+                            pl->whole ? kRemapWhole : (o->pair_remaps ? kRemapPairs : kRemapScaled)));
   }
   if (o->devices == ADHA_DEVICES_GPU_HOST) {
     pl->hetero = true;
@@ -1121,6 +1195,12 @@ adha_status adha_plan_tables(const adha_plan *pl, double *T, double *R) {
 adha_status adha_plan_time(const adha_plan *pl, double *seconds) {
   if (!pl || !seconds) return fail(ADHA_ERR_INVALID, "NULL argument");
   *seconds = pl->seconds;
+  return ADHA_OK;
+}
+
+adha_status adha_plan_verified(const adha_plan *pl, uint32_t *entries) {
+  if (!pl || !entries) return fail(ADHA_ERR_INVALID, "NULL argument");
+  *entries = pl->verified;
   return ADHA_OK;
 }
 

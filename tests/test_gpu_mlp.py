@@ -93,23 +93,6 @@ def test_adam_step_matches_oracle(ctx):
     assert _rel(dv.cpu().numpy(), opt.v[0]) <= 1e-6
 
 
-def test_features_match_oracle_definition():
-    from oracle.costmodel import features as ofeat  # noqa: F401
-    spec = synth.config3_struct(1 << 18)
-    st = A.Struct.from_spec(spec)
-    secs = synth.random_program(7, spec.n_fields)
-    prog_secs = [A.Section.from_spec(st, s) for s in secs]
-    osecs = [(s.read, s.write, s.degree) for s in secs]
-    cat = OP.catalogue(osecs, spec.n, spec.elem_bytes, 64)
-    for s, sec in zip(secs, prog_secs):
-        for O in cat[:12]:
-            gof = [O.group_of[f] for f in range(spec.n_fields)]
-            lay = A.Layout.create(st, gof, [t for _, t in O.groups])
-            got = np.array(sec.features(lay), np.float32)
-            want = np.array(ofeat(s.read, s.write, s.degree, O, spec), np.float32)
-            assert np.array_equal(got, want), (s, O, got, want)
-
-
 def test_train_save_load_predict_and_fallback(ctx):
     rep = A.costmodel_train(ctx, A.train_opts(n_samples=400, epochs=60, min_log2_n=12, max_log2_n=16, reps=2))
     say("train report", rep)
