@@ -32,7 +32,7 @@ _SRC = os.path.join(_HERE, "adha_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-F32, F64, I32, RAW = 0, 1, 2, 3
+F32, F64, I32, RAW, U32, U8, U16, I16 = 0, 1, 2, 3, 4, 5, 6, 7
 OP_GEN, OP_MULADD3, OP_SUB2, OP_SUM = 0, 1, 2, 3
 
 

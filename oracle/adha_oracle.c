@@ -16,7 +16,7 @@
 #include <stdint.h>
 #include <string.h>
 
-enum { ORC_F32 = 0, ORC_F64 = 1, ORC_I32 = 2, ORC_RAW = 3 };
+enum { ORC_F32 = 0, ORC_F64 = 1, ORC_I32 = 2, ORC_RAW = 3, ORC_U32 = 4, ORC_U8 = 5, ORC_U16 = 6, ORC_I16 = 7 };
 enum { ORC_GEN = 0, ORC_MULADD3 = 1, ORC_SUB2 = 2, ORC_SUM = 3 };
 
 #define ORC_MAX_TERMS 1024
@@ -65,24 +65,44 @@ static orc_term orc_load(const uint8_t *buf, const uint64_t *row, int32_t dt, ui
     return t;
 }
 
+/*
+ * Integer element types: I32 and I16 are two's complement, U32, U16 and U8
+ * unsigned; t.bits holds the element's bytes zero-extended.  As a number an
+ * integer term is its mathematical value; converting it to a floating-point
+ * type rounds to nearest even (exact below 2^24 for float, always for
+ * double).  As 32 bits (the integer fold) it is that value modulo 2^32, so
+ * I16 is sign-extended and the unsigned types zero-extended.
+ */
+static int64_t orc_int_value(orc_term t)
+{
+    switch (t.dt) {
+    case ORC_I32: return (int32_t)(uint32_t)t.bits;
+    case ORC_I16: return (int16_t)(uint16_t)t.bits;
+    case ORC_U32: return (uint32_t)t.bits;
+    case ORC_U16: return (uint16_t)t.bits;
+    default: return (uint8_t)t.bits;
+    }
+}
+
 static float orc_to_f32(orc_term t)
 {
     if (t.dt == ORC_F32) { float v; uint32_t b = (uint32_t)t.bits; memcpy(&v, &b, 4); return v; }
-    if (t.dt == ORC_I32) return (float)(int32_t)(uint32_t)t.bits;
-    { double v; memcpy(&v, &t.bits, 8); return (float)v; }
+    if (t.dt == ORC_F64) { double v; memcpy(&v, &t.bits, 8); return (float)v; }
+    return (float)orc_int_value(t);
 }
 
 static double orc_to_f64(orc_term t)
 {
     if (t.dt == ORC_F32) { float v; uint32_t b = (uint32_t)t.bits; memcpy(&v, &b, 4); return (double)v; }
-    if (t.dt == ORC_I32) return (double)(int32_t)(uint32_t)t.bits;
-    { double v; memcpy(&v, &t.bits, 8); return v; }
+    if (t.dt == ORC_F64) { double v; memcpy(&v, &t.bits, 8); return v; }
+    return (double)orc_int_value(t);
 }
 
 static uint32_t orc_bits32(orc_term t)
 {
     if (t.dt == ORC_F64) return (uint32_t)t.bits ^ (uint32_t)(t.bits >> 32);
-    return (uint32_t)t.bits;
+    if (t.dt == ORC_F32) return (uint32_t)t.bits;
+    return (uint32_t)(uint64_t)orc_int_value(t);
 }
 
 /*
@@ -94,8 +114,10 @@ static uint32_t orc_bits32(orc_term t)
  * write field w_k (ascending id) is written at i:
  *   GEN, fp w:  acc = 0; per term v = convert(t) to w's type;
  *               k = 0: acc = acc + v;  k = 1: acc = acc*0.5 + v
- *   GEN, i32 w: acc = 0 (mod 2^32); per term u = its 32 bits (fp64: low ^ high);
- *               k = 0: acc = acc + u;  k = 1: acc = (acc ^ u) * 16777619
+ *   GEN, integer w: acc = 0 (mod 2^32); per term u = its 32 bits (fp64: low ^
+ *               high; an integer term's value modulo 2^32);
+ *               k = 0: acc = acc + u;  k = 1: acc = (acc ^ u) * 16777619;
+ *               stored as the low bytes of acc that fit w
  *   MULADD3: w = a*b + c;  SUB2: w = a - b;  SUM: w = ((t0 + t1) + ...)
  * with a, b, c the three read fields in ascending id, each converted to w's
  * type first.  Returns the number of gather indices outside [0, n).
@@ -158,14 +180,17 @@ int64_t orc_section(int32_t op, int64_t n, const uint64_t *desc, const int32_t *
                     }
                 }
                 memcpy(dst, &acc, 8);
-            } else if (wdt == ORC_I32) {
+            } else {
+                /* an integer write field: the fold modulo 2^32, stored as its
+                   low e bytes (the value modulo 2^(8e)) */
                 uint32_t acc = 0;
                 for (int32_t q = 0; q < nt; ++q) {
                     uint32_t u = orc_bits32(terms[q]);
                     if (k == 1) acc = (acc ^ u) * 16777619u;
                     else acc = acc + u;
                 }
-                memcpy(dst, &acc, 4);
+                uint8_t le[4] = {(uint8_t)acc, (uint8_t)(acc >> 8), (uint8_t)(acc >> 16), (uint8_t)(acc >> 24)};
+                memcpy(dst, le, (size_t)desc[5 * w + 4]);
             }
         }
     }

@@ -9,7 +9,7 @@ record has key 0 when there is no key field),
   table[k][j] = the exact sum of read field j (ascending id) over those
                 records -- rounded once to a double for F32 and F64 fields
                 (math.fsum rounds the exact sum correctly), an exact Python
-                integer for I32 fields;
+                integer for integer fields (I32, U32, U16, U8, I16);
   table[k][n_read] = the number of those records.
 
 Records whose key is outside [0, K) are left out and counted as bad.  The
@@ -24,7 +24,8 @@ import numpy as np
 
 from .layout import Layout
 
-F32, F64, I32 = 0, 1, 2
+F32, F64, I32, U32, U8, U16, I16 = 0, 1, 2, 4, 5, 6, 7
+INTEGER = {I32: np.int32, U32: np.uint32, U8: np.uint8, U16: np.uint16, I16: np.int16}
 
 
 def field_values(layout: Layout, buf: np.ndarray, dtype: int, f: int) -> np.ndarray:
@@ -38,8 +39,8 @@ def field_values(layout: Layout, buf: np.ndarray, dtype: int, f: int) -> np.ndar
         return raw.view(np.float32).reshape(-1)
     if dtype == F64:
         return raw.view(np.float64).reshape(-1)
-    if dtype == I32:
-        return raw.view(np.int32).reshape(-1)
+    if dtype in INTEGER:
+        return raw.view(INTEGER[dtype]).reshape(-1)
     raise ValueError(f"field {f} has no numeric type")
 
 
@@ -59,8 +60,8 @@ def reduce(layout: Layout, dtypes, read, key: int, n_keys: int, buf: np.ndarray)
         row = []
         for f, v in zip(read, cols):
             picked = v[sel]
-            if dtypes[f] == I32:
-                # int64 holds any sum of fewer than 2^32 int32 values exactly
+            if dtypes[f] in INTEGER:
+                # int64 holds any sum of fewer than 2^31 such values exactly
                 row.append(int(picked.astype(np.int64).sum()))
             else:
                 row.append(math.fsum(picked.astype(np.float64).tolist()))
@@ -77,7 +78,7 @@ def table_cells(table, dtypes, read) -> np.ndarray:
     out = []
     for row in table:
         for j, v in enumerate(row):
-            if j < len(read) and dtypes[read[j]] != I32:
+            if j < len(read) and dtypes[read[j]] not in INTEGER:
                 out.append(np.array([v], np.float64).view(np.uint64)[0])
             else:
                 out.append(np.uint64(v % (1 << 64)))

@@ -29,8 +29,8 @@ M2 = 0x94D049BB133111EB
 MASK64 = (1 << 64) - 1
 
 # dtype codes (same numbering as the C-ABI's adha_dtype)
-F32, F64, I32, RAW = 0, 1, 2, 3
-DT_NAMES = {F32: "f32", F64: "f64", I32: "i32", RAW: "raw"}
+F32, F64, I32, RAW, U32, U8, U16, I16 = 0, 1, 2, 3, 4, 5, 6, 7
+DT_NAMES = {F32: "f32", F64: "f64", I32: "i32", RAW: "raw", U32: "u32", U8: "u8", U16: "u16", I16: "i16"}
 
 
 def _key(seed: int, stream: int) -> int:
@@ -71,6 +71,14 @@ def decode(z: np.ndarray, dtype: int, elem_bytes: int = 4) -> np.ndarray:
         v = (z >> np.uint64(11)).astype(np.float64) * 2.0 ** -52 - 1.0
     elif dtype == I32:
         v = (z >> np.uint64(33)).astype(np.int32)
+    elif dtype == U32:
+        v = (z >> np.uint64(32)).astype(np.uint32)
+    elif dtype == U16:
+        v = (z >> np.uint64(48)).astype(np.uint16)
+    elif dtype == I16:
+        v = (z >> np.uint64(48)).astype(np.uint16).view(np.int16)
+    elif dtype == U8:
+        v = (z >> np.uint64(56)).astype(np.uint8)
     elif dtype == RAW:
         if elem_bytes == 8:
             v = z.copy()
@@ -172,6 +180,12 @@ def decode_torch(z, dtype: int, elem_bytes: int = 4):
         v = _t_srl(z, 11).to(torch.float64) * 2.0 ** -52 - 1.0
     elif dtype == I32:
         v = _t_srl(z, 33).to(torch.int32)
+    elif dtype == U32:
+        v = _t_srl(z, 32).to(torch.int64).to(torch.int32)       # the low 32 bits of z >> 32
+    elif dtype in (U16, I16):
+        v = _t_srl(z, 48).to(torch.int16)
+    elif dtype == U8:
+        v = _t_srl(z, 56).to(torch.uint8)
     elif dtype == RAW:
         if elem_bytes == 8:
             v = z

@@ -180,3 +180,99 @@ def test_direct_section_reads_before_writing():
     a, b = _as(cols[0], F32), _as(cols[1], F32)
     assert np.array_equal(_as(out[0], F32), a + b)
     assert np.array_equal(_as(out[1], F32), a * np.float32(0.5) + b)
+
+
+# ---------------------------------------------------------------- narrow and unsigned integer fields
+U32, U8, U16, I16 = oracle.U32, oracle.U8, oracle.U16, oracle.I16
+
+
+def _col(vals, fmt):
+    size = struct.calcsize("<" + fmt)
+    return np.frombuffer(b"".join(struct.pack("<" + fmt, v) for v in vals), np.uint8).reshape(len(vals), size).copy()
+
+
+def _run_one(dtypes, eb, cols, read, write, layout_of=None, op=OP_GEN):
+    n = cols[0].shape[0]
+    L = layout_of(n, eb) if layout_of else aos(n, eb)
+    buf = oracle.pack(L, cols)
+    oracle.section(L, dtypes, op, read, write, 0, None, buf)
+    return [oracle.unpack(L, buf, f) for f in range(len(eb))]
+
+
+def test_narrow_integers_convert_exactly_to_floating_point():
+    """U8, U16, I16 terms are exact in float and double: a one-term GEN sum
+    into an F32 and an F64 field gives the values back."""
+    u8 = [0, 1, 127, 128, 255]
+    u16 = [0, 1, 32768, 65534, 65535]
+    i16 = [-32768, -1, 0, 1, 32767]
+    for dt, fmt, vals, e in ((U8, "B", u8, 1), (U16, "H", u16, 2), (I16, "h", i16, 2)):
+        cols = [_col(vals, fmt), _col([0.0] * 5, "f"), _col([0.0] * 5, "d")]
+        out = _run_one([dt, F32, F64], [e, 4, 8], cols, [0], [1, 2])
+        f32 = [struct.unpack("<f", out[1][r].tobytes())[0] for r in range(5)]
+        f64 = [struct.unpack("<d", out[2][r].tobytes())[0] for r in range(5)]
+        # write k = 1 folds acc*0.5 + v from acc = 0: the value itself
+        assert f32 == [float(v) for v in vals] and f64 == [float(v) for v in vals], dt
+
+
+def test_u32_rounds_to_nearest_even_in_float():
+    """U32 is unsigned: 2^32 - 1 is 4294967295 (not -1); in float it rounds
+    to nearest even (2^24 + 1 -> 2^24, 2^24 + 3 -> 2^24 + 4), in double it is
+    exact."""
+    vals = [4294967295, 16777217, 16777219, 2147483648, 7]
+    cols = [_col(vals, "I"), _col([0.0] * 5, "f"), _col([0.0] * 5, "d")]
+    out = _run_one([U32, F32, F64], [4, 4, 8], cols, [0], [1, 2])
+    f32 = [struct.unpack("<f", out[1][r].tobytes())[0] for r in range(5)]
+    f64 = [struct.unpack("<d", out[2][r].tobytes())[0] for r in range(5)]
+    assert f32 == [4294967296.0, 16777216.0, 16777220.0, 2147483648.0, 7.0]
+    assert f64 == [float(v) for v in vals]
+
+
+def test_integer_fold_into_narrow_write_fields_keeps_the_low_bytes():
+    """Worked by hand: the integer fold runs modulo 2^32 over the terms' 32-bit
+    values (I16 sign-extended, unsigned types zero-extended) and a narrow
+    write field keeps the low bytes."""
+    # terms: I32 200, I16 -1 (0xFFFFFFFF), U16 65535 (0x0000FFFF), U8 100
+    dtypes = [I32, I16, U16, U8, U8, U16, I16, U32]
+    eb = [4, 2, 2, 1, 1, 2, 2, 4]
+    cols = [_col([200], "i"), _col([-1], "h"), _col([65535], "H"), _col([100], "B"),
+            _col([0], "B"), _col([0], "H"), _col([0], "h"), _col([0], "I")]
+    # k = 0 sum: 200 + 0xFFFFFFFF + 0xFFFF + 100 = 0x1_0001_012A -> 0x0001012A
+    s32 = (200 + 0xFFFFFFFF + 0xFFFF + 100) % (1 << 32)
+    assert s32 == 0x0001012A
+    for w, fmt, want in ((4, "B", s32 & 0xFF), (5, "H", s32 & 0xFFFF), (7, "I", s32)):
+        out = _run_one(dtypes, eb, cols, [0, 1, 2, 3], [w])
+        assert struct.unpack("<" + fmt, out[w][0].tobytes())[0] == want, w
+    # an I16 write of 0x8000 reads back as -32768
+    c2 = [_col([0x7FFF], "i"), _col([1], "h"), _col([0], "H"), _col([0], "B"),
+          _col([0], "B"), _col([0], "H"), _col([0], "h"), _col([0], "I")]
+    out = _run_one(dtypes, eb, c2, [0, 1], [6])
+    assert struct.unpack("<h", out[6][0].tobytes())[0] == -32768
+    # k = 1 (FNV fold) into a U32 and a U8 field: acc = (acc ^ u) * 16777619 mod 2^32
+    acc = 0
+    for u in (200, 0xFFFFFFFF, 0xFFFF, 100):
+        acc = ((acc ^ u) * FNV_PRIME) % (1 << 32)
+    out = _run_one(dtypes, eb, cols, [0, 1, 2, 3], [4, 7])
+    assert struct.unpack("<I", out[7][0].tobytes())[0] == acc
+    # the first write (k = 0) of the pair is the sum
+    assert out[4][0][0] == s32 & 0xFF
+
+
+def test_narrow_fields_are_layout_independent():
+    """A struct of 1-, 2-, 4- and 8-byte typed fields (unaligned members in
+    interleaved groups): a direct section and a gather give the same field
+    bytes under every layout."""
+    n = 257
+    dtypes = [U8, I16, F32, U16, F64, U32, I32, U8, F32, I16]
+    eb = [1, 2, 4, 2, 8, 4, 4, 1, 4, 2]
+    cols = [synth.field_values(17, f, n, synth.RAW, e) for f, e in enumerate(eb)]
+    idx = synth.uniform_index(17, 99, n * 4, n)
+    secs = [synth.SectionSpec(OP_GEN, [0, 1, 2, 3, 4], [8, 9]), synth.SectionSpec(OP_GEN, [0, 3, 5, 6], [7], 4),
+            synth.SectionSpec(OP_GEN, [1, 7, 9], [2, 5])]
+    st = synth.StructSpec(n, dtypes, eb)
+    outs = []
+    for L in (aos(n, eb), soa(n, eb), Layout(n, eb, [0, 0, 0, 1, 1, 1, 2, 2, 2, 2], [1, 64, 4]),
+              from_partition(n, eb, [[0, 1, 7, 9], [3, 5]], 1)):
+        outs.append(_run_program(L, st, secs, cols, idx))
+    for o in outs[1:]:
+        for f in range(len(eb)):
+            assert np.array_equal(o[f], outs[0][f]), f
