@@ -58,7 +58,16 @@ typedef int32_t adha_status;
 #define ADHA_ERR_UNSUPPORTED (-5)/* valid request this library cannot do */
 #define ADHA_ERR_IO (-6)         /* file missing, unreadable or corrupt */
 
-typedef enum { ADHA_F32 = 0, ADHA_F64 = 1, ADHA_I32 = 2, ADHA_RAW = 3 } adha_dtype;
+/* Element types.  Integer types are two's complement (I32, I16) or unsigned
+ * (U32, U16, U8).  As a term an integer field converts to floating point
+ * exactly (U8, U16, I16 always; I32 and U32 in double) or to nearest even
+ * (I32 and U32 in float); in the integer fold it is its value modulo 2^32
+ * (I16 sign-extended, unsigned types zero-extended).  An integer write field
+ * keeps the low bytes of the fold (its value modulo 2^(8 e)). */
+typedef enum {
+  ADHA_F32 = 0, ADHA_F64 = 1, ADHA_I32 = 2, ADHA_RAW = 3,
+  ADHA_U32 = 4, ADHA_U8 = 5, ADHA_U16 = 6, ADHA_I16 = 7
+} adha_dtype;
 
 /* Section bodies (the paper gives none; these are the workloads' bodies).
  * Terms are read first: direct sections (degree 0) read the read fields of
@@ -68,12 +77,16 @@ typedef enum { ADHA_F32 = 0, ADHA_F64 = 1, ADHA_I32 = 2, ADHA_RAW = 3 } adha_dty
  *   GEN, fp w:  acc = 0, per term v = convert(t) to w's type (int -> fp and
  *               f64 -> f32 round to nearest even), k = 0: acc = acc + v,
  *               k = 1: acc = acc*0.5 + v, every operation rounded in w's type;
- *   GEN, i32 w: acc = 0, per term u = its 32-bit pattern (f64: low ^ high),
- *               k = 0: acc = acc + u, k = 1: acc = (acc ^ u) * 16777619 (mod 2^32);
+ *   GEN, integer w: acc = 0, per term u = its 32-bit pattern (f64: low ^
+ *               high; an integer term its value mod 2^32), k = 0: acc = acc + u,
+ *               k = 1: acc = (acc ^ u) * 16777619 (mod 2^32), stored as the low
+ *               bytes that fit w;
  *   MULADD3:    w = a*b + c (two roundings), read set {a < b < c}, direct only;
  *   SUB2:       w = a - b, read set {a < b}, direct only;
  *   SUM:        w = ((t0 + t1) + ...) left to right, direct only.
- * MULADD3, SUB2 and SUM need one fp write field. */
+ * MULADD3, SUB2 and SUM need one fp write field.  Fields of 1 and 2 bytes, and
+ * fields that a layout places at addresses that are not multiples of 4, are
+ * read and written byte by byte (a slower kernel form). */
 typedef enum {
   ADHA_OP_GEN = 0,
   ADHA_OP_MULADD3 = 1,
@@ -138,9 +151,9 @@ adha_status adha_ctx_set_option(adha_ctx *ctx, adha_option opt, int64_t value);
 /* A struct of n_records records (n_records >= 0; 0 makes every operation a
  * no-op).  Fields are added in order and get ids 0, 1, ... */
 adha_status adha_struct_create(int64_t n_records, adha_struct **out);
-/* dtype F32 and I32 need elem_bytes 4, F64 needs 8, RAW any of 1, 2, 4, 8
- * (RAW fields can be remapped but not used by sections).  At most 64 fields
- * and 2048 record bytes. */
+/* dtype F32, I32 and U32 need elem_bytes 4, F64 needs 8, U16 and I16 need
+ * 2, U8 needs 1, RAW any of 1, 2, 4, 8 (RAW fields can be remapped but not
+ * used by sections).  At most 64 fields and 2048 record bytes. */
 adha_status adha_struct_add_field(adha_struct *s, adha_dtype dt, uint32_t elem_bytes,
                                   int32_t *out_id);
 adha_status adha_struct_destroy(adha_struct *s);
@@ -299,14 +312,15 @@ adha_status adha_section_create_stencil(const adha_struct *s, uint32_t n_read, c
                                         uint32_t n_write, const int32_t *write, uint32_t nx, uint32_t ny,
                                         uint32_t nz, uint32_t d, const int32_t *offsets, adha_section **out);
 /* A reduction section (section 3: the second K-Means section reduces all
- * the features over the points).  It reads n_read fields (F32, F64 or I32)
- * of every record and, when key_field >= 0, the I32 key field, and adds
+ * the features over the points).  It reads n_read fields (F32, F64, I32 or
+ * U32, at 4-byte aligned addresses in the layout it runs on) of every record
+ * and, when key_field >= 0, the I32 key field, and adds
  * the values of the records whose key is k into row k of a table of
  * n_keys rows of n_read + 1 eight-byte cells, written to the device array
  * `out` (caller-owned, 256-byte aligned, out_cap >= n_keys*(n_read+1)*8):
  *   cell [k][j], j < n_read: the sum over those records of read field j
  *     (ascending id): an IEEE double for F32/F64 fields; a two's-complement
- *     int64 for I32 fields (exact);
+ *     int64 for I32 and U32 fields (exact);
  *   cell [k][n_read]: the number of those records (uint64).
  * Without a key every record has key 0 and n_keys must be 1.  Records whose
  * key is outside [0, n_keys) are left out and reported by adha_ctx_check.

@@ -22,7 +22,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "adha.h")
 
 OK, WARN_FALLBACK = 0, 1
 ERR_INVALID, ERR_OOM, ERR_DEVICE, ERR_STATE, ERR_UNSUPPORTED, ERR_IO = -1, -2, -3, -4, -5, -6
-F32, F64, I32, RAW = 0, 1, 2, 3
+F32, F64, I32, RAW, U32, U8, U16, I16 = 0, 1, 2, 3, 4, 5, 6, 7
 OP_GEN, OP_MULADD3, OP_SUB2, OP_SUM, OP_REDUCE = 0, 1, 2, 3, 4
 MAX_REDUCE_CELLS = 4096
 COST_MEASURED, COST_ANALYTIC, COST_LEARNED = 0, 1, 2
@@ -256,7 +256,7 @@ class Struct:
         self.n = n
         self.dtypes = list(dtypes)
         self.elem_bytes = list(elem_bytes) if elem_bytes is not None else \
-            [8 if d == F64 else 4 for d in dtypes]
+            [{F64: 8, U16: 2, I16: 2, U8: 1}.get(d, 4) for d in dtypes]
         for d, e in zip(self.dtypes, self.elem_bytes):
             fid = ctypes.c_int32()
             check(lib().adha_struct_add_field(h, d, e, ctypes.byref(fid)))

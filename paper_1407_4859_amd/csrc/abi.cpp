@@ -334,7 +334,15 @@ adha_status adha_struct_add_field(adha_struct *s, adha_dtype dt, uint32_t elem_b
   switch (dt) {
     case ADHA_F32:
     case ADHA_I32:
-      if (elem_bytes != 4) return fail(ADHA_ERR_INVALID, "F32 / I32 fields have 4-byte elements");
+    case ADHA_U32:
+      if (elem_bytes != 4) return fail(ADHA_ERR_INVALID, "F32 / I32 / U32 fields have 4-byte elements");
+      break;
+    case ADHA_U16:
+    case ADHA_I16:
+      if (elem_bytes != 2) return fail(ADHA_ERR_INVALID, "U16 / I16 fields have 2-byte elements");
+      break;
+    case ADHA_U8:
+      if (elem_bytes != 1) return fail(ADHA_ERR_INVALID, "U8 fields have 1-byte elements");
       break;
     case ADHA_F64:
       if (elem_bytes != 8) return fail(ADHA_ERR_INVALID, "F64 fields have 8-byte elements");
@@ -670,7 +678,8 @@ adha_status adha_section_create(const adha_struct *s, adha_op op, uint32_t n_rea
       if (need && n_read != need) return fail(ADHA_ERR_INVALID, "op needs exactly %u read fields", need);
       if (n_write != 1) return fail(ADHA_ERR_INVALID, "op writes exactly one field");
       if (degree) return fail(ADHA_ERR_UNSUPPORTED, "op is direct only");
-      if (sh.dtype[d.wr[0]] == ADHA_I32) return fail(ADHA_ERR_UNSUPPORTED, "op needs a floating-point write field");
+      if (sh.dtype[d.wr[0]] != ADHA_F32 && sh.dtype[d.wr[0]] != ADHA_F64)
+        return fail(ADHA_ERR_UNSUPPORTED, "op needs a floating-point write field");
       break;
     }
     case ADHA_OP_REDUCE:
@@ -728,6 +737,9 @@ adha_status adha_section_create_reduce(const adha_struct *s, uint32_t n_read, co
     if (f < 0 || f >= F) return fail(ADHA_ERR_INVALID, "field id %d out of range", f);
     if (i && d.rd[i - 1] == f) return fail(ADHA_ERR_INVALID, "field id %d listed twice", f);
     if (sh.dtype[f] == ADHA_RAW) return fail(ADHA_ERR_UNSUPPORTED, "field %d is RAW; sections need typed fields", f);
+    if (sh.ebytes[f] < 4)
+      return fail(ADHA_ERR_UNSUPPORTED, "field %d has %u-byte elements; reductions read 4- and 8-byte fields", f,
+                  sh.ebytes[f]);
   }
   if (key_field >= 0) {
     if (key_field >= F) return fail(ADHA_ERR_INVALID, "key field %d out of range", key_field);

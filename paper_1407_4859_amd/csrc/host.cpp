@@ -160,6 +160,17 @@ inline uint64_t read_term(const uint8_t *buf, const LayoutDesc &l, int64_t r, in
   return v;
 }
 
+// The value of an integer term (its element bytes zero-extended in b).
+inline int64_t int_value(int32_t dt, uint64_t b) {
+  switch (dt) {
+    case ADHA_I32: return (int32_t)(uint32_t)b;
+    case ADHA_I16: return (int16_t)(uint16_t)b;
+    case ADHA_U32: return (uint32_t)b;
+    case ADHA_U16: return (uint16_t)b;
+    default: return (uint8_t)b;
+  }
+}
+
 inline float as_f32(int32_t dt, uint64_t b) {
   if (dt == ADHA_F32) {
     float x;
@@ -167,22 +178,28 @@ inline float as_f32(int32_t dt, uint64_t b) {
     std::memcpy(&x, &u, 4);
     return x;
   }
-  if (dt == ADHA_I32) return (float)(int32_t)(uint32_t)b;
-  double d;
-  std::memcpy(&d, &b, 8);
-  return (float)d;
+  if (dt == ADHA_F64) {
+    double d;
+    std::memcpy(&d, &b, 8);
+    return (float)d;
+  }
+  return (float)int_value(dt, b);  // nearest even; exact below 2^24
 }
 
 inline double as_f64(int32_t dt, uint64_t b) {
   if (dt == ADHA_F32) return (double)as_f32(ADHA_F32, b);
-  if (dt == ADHA_I32) return (double)(int32_t)(uint32_t)b;
-  double d;
-  std::memcpy(&d, &b, 8);
-  return d;
+  if (dt == ADHA_F64) {
+    double d;
+    std::memcpy(&d, &b, 8);
+    return d;
+  }
+  return (double)int_value(dt, b);
 }
 
 inline uint32_t word32(int32_t dt, uint64_t b) {
-  return dt == ADHA_F64 ? (uint32_t)b ^ (uint32_t)(b >> 32) : (uint32_t)b;
+  if (dt == ADHA_F64) return (uint32_t)b ^ (uint32_t)(b >> 32);
+  if (dt == ADHA_F32) return (uint32_t)b;
+  return (uint32_t)(uint64_t)int_value(dt, b);
 }
 
 struct HAcc {
@@ -218,7 +235,7 @@ inline void write_acc(uint8_t *buf, const LayoutDesc &l, int64_t r, int f, const
   const int32_t dt = l.shape.dtype[f];
   if (dt == ADHA_F32) std::memcpy(p, &a.f, 4);
   else if (dt == ADHA_F64) std::memcpy(p, &a.d, 8);
-  else std::memcpy(p, &a.u, 4);
+  else std::memcpy(p, &a.u, l.shape.ebytes[f]);  // the low bytes (x86-64 is little-endian)
 }
 
 }  // namespace
@@ -254,8 +271,9 @@ adha_status host_section_run(uint32_t threads, const SectionDesc &sec, const Lay
         for (size_t q = 0; q < nr; ++q) {
           const int f = sec.rd[q];
           const uint64_t v = read_term(buf, l, r, f);
-          if (l.shape.dtype[f] == ADHA_I32) us[k][row + q] += (uint64_t)(int64_t)(int32_t)(uint32_t)v;
-          else comp_add(fs[k][row + q], cs[k][row + q], as_f64(l.shape.dtype[f], v));
+          const int32_t dt = l.shape.dtype[f];
+          if (dt != ADHA_F32 && dt != ADHA_F64) us[k][row + q] += (uint64_t)int_value(dt, v);
+          else comp_add(fs[k][row + q], cs[k][row + q], as_f64(dt, v));
         }
         us[k][row + nr] += 1;
       }
@@ -263,7 +281,7 @@ adha_status host_section_run(uint32_t threads, const SectionDesc &sec, const Lay
     uint64_t *out = (uint64_t *)table;
     for (uint32_t c = 0; c < cells; ++c) {
       const uint32_t q = c % cols;
-      const bool fp = q < nr && l.shape.dtype[sec.rd[q]] != ADHA_I32;
+      const bool fp = q < nr && (l.shape.dtype[sec.rd[q]] == ADHA_F32 || l.shape.dtype[sec.rd[q]] == ADHA_F64);
       if (fp) {
         double hi = 0.0, lo = 0.0;
         for (uint32_t k = 0; k < t; ++k) pair_add(hi, lo, fs[k][c], cs[k][c], &hi, &lo);

@@ -28,9 +28,9 @@ struct SField {
   uint32_t TS;    // T * S_g
   uint32_t pT;    // p_f * T
   uint32_t logT;
-  uint32_t e;     // 4 or 8
+  uint32_t e;     // 1, 2, 4 or 8
   uint32_t dt;
-  uint32_t pad;
+  uint32_t al;    // 1: every address of the field is a multiple of 4
 };
 
 struct SectionArgs {
@@ -77,16 +77,36 @@ __device__ __forceinline__ uint64_t faddr(const SField &F, uint64_t r) {
   return F.base + (r >> F.logT) * F.TS + F.pT + (r & ((1ull << F.logT) - 1)) * F.e;
 }
 
+// A field of any width at any address: whole dwords when every address of
+// the field is a multiple of 4, else byte by byte (a 1- or 2-byte field, or
+// a wider one placed after narrow fields in an interleaved group).
+__device__ __forceinline__ uint64_t load_any(const uint8_t *buf, const SField &F, uint64_t r) {
+  const uint8_t *p = buf + faddr(F, r);
+  if (F.al) {
+    const uint32_t *q = reinterpret_cast<const uint32_t *>(p);
+    return F.e == 8 ? ((uint64_t)q[0] | ((uint64_t)q[1] << 32)) : q[0];
+  }
+  uint64_t v = 0;
+  for (uint32_t b = 0; b < F.e; ++b) v |= (uint64_t)p[b] << (8 * b);
+  return v;
+}
+
 // The raw words of up to N terms.  Loads only fill registers; the terms are
 // assembled afterwards (word() below), so no arithmetic sits between one
 // load and the next and all of them are in flight together.  W8: some term
 // is 8 bytes wide, so a second word is loaded per term -- for a 4-byte term
 // that second load reads the same word again and stays inside the field.
-template <int N, bool W8>
+template <int N, bool W8, bool SUB = false>
 struct Words {
   uint32_t lo[N];
-  uint32_t hi[W8 ? N : 1];
+  uint32_t hi[W8 || SUB ? N : 1];
   __device__ __forceinline__ void load(int q, const uint8_t *buf, const SField &F, uint64_t r) {
+    if constexpr (SUB) {  // any width, any alignment
+      const uint64_t v = load_any(buf, F, r);
+      lo[q] = (uint32_t)v;
+      hi[q] = (uint32_t)(v >> 32);
+      return;
+    }
     const uint32_t *p = reinterpret_cast<const uint32_t *>(buf + faddr(F, r));
     lo[q] = p[0];
     if constexpr (W8) hi[q] = p[F.e >> 3];
@@ -97,6 +117,7 @@ struct Words {
     if constexpr (W8) hi[q] = p[F.e >> 3];
   }
   __device__ __forceinline__ uint64_t term(int q, const SField &F) const {
+    if constexpr (SUB) return (uint64_t)lo[q] | ((uint64_t)hi[q] << 32);
     if constexpr (W8) return (uint64_t)lo[q] | ((uint64_t)(F.e == 8 ? hi[q] : 0u) << 32);
     return lo[q];
   }
@@ -118,20 +139,35 @@ __device__ __forceinline__ uint32_t load_word(const uint8_t *buf, const SField &
   return *reinterpret_cast<const uint32_t *>(buf + faddr(F, r));
 }
 
+// The value of an integer term (its element bytes zero-extended in b).
+__device__ __forceinline__ int64_t int_value(uint32_t dt, uint64_t b) {
+  switch (dt) {
+    case ADHA_I32: return (int32_t)(uint32_t)b;
+    case ADHA_I16: return (int16_t)(uint16_t)b;
+    case ADHA_U32: return (uint32_t)b;
+    case ADHA_U16: return (uint16_t)b;
+    default: return (uint8_t)b;
+  }
+}
+
 __device__ __forceinline__ float to_f32(uint32_t dt, uint64_t b) {
   if (dt == ADHA_F32) return __uint_as_float((uint32_t)b);
   if (dt == ADHA_I32) return __int2float_rn((int32_t)(uint32_t)b);
-  return __double2float_rn(__longlong_as_double((long long)b));
+  if (dt == ADHA_F64) return __double2float_rn(__longlong_as_double((long long)b));
+  if (dt == ADHA_U32) return __uint2float_rn((uint32_t)b);
+  return __int2float_rn((int32_t)int_value(dt, b));  // U16, I16, U8: exact
 }
 
 __device__ __forceinline__ double to_f64(uint32_t dt, uint64_t b) {
   if (dt == ADHA_F32) return (double)__uint_as_float((uint32_t)b);
-  if (dt == ADHA_I32) return (double)(int32_t)(uint32_t)b;
-  return __longlong_as_double((long long)b);
+  if (dt == ADHA_F64) return __longlong_as_double((long long)b);
+  return (double)int_value(dt, b);  // exact for every integer type
 }
 
 __device__ __forceinline__ uint32_t bits32(uint32_t dt, uint64_t b) {
-  return dt == ADHA_F64 ? (uint32_t)b ^ (uint32_t)(b >> 32) : (uint32_t)b;
+  if (dt == ADHA_F64) return (uint32_t)b ^ (uint32_t)(b >> 32);
+  if (dt == ADHA_F32) return (uint32_t)b;
+  return (uint32_t)(uint64_t)int_value(dt, b);
 }
 
 struct Acc {
@@ -154,23 +190,45 @@ __device__ __forceinline__ void fold(Acc &a, uint32_t k, uint32_t wdt, uint32_t 
   }
 }
 
+// Little-endian bytes of v, one store each (a field that is narrower than 4
+// bytes or not 4-byte aligned).
+__device__ __forceinline__ void store_bytes(uint8_t *at, uint64_t v, uint32_t e) {
+  for (uint32_t q = 0; q < e; ++q) at[q] = (uint8_t)(v >> (8 * q));
+}
+
+// Each type stores from its own branch: the three-way choice of the element
+// bits ahead of one shared store was compiled (for the generic section
+// kernel) with the integer branch's value left undefined, so no value is
+// merged across the branches here.  An integer field keeps the low bytes of
+// the fold.
 __device__ __forceinline__ void store_acc(uint8_t *buf, const SField &W, uint64_t r, const Acc &a) {
-  uint32_t *p = reinterpret_cast<uint32_t *>(buf + faddr(W, r));
-  if (W.dt == ADHA_F32) {
-    p[0] = __float_as_uint(a.f);
+  uint8_t *at = buf + faddr(W, r);
+  if (W.al) {
+    uint32_t *p = reinterpret_cast<uint32_t *>(at);
+    if (W.dt == ADHA_F32) {
+      p[0] = __float_as_uint(a.f);
+    } else if (W.dt == ADHA_F64) {
+      const uint64_t b = (uint64_t)__double_as_longlong(a.d);
+      p[0] = (uint32_t)b;
+      p[1] = (uint32_t)(b >> 32);
+    } else {
+      p[0] = a.u;
+    }
+  } else if (W.dt == ADHA_F32) {
+    store_bytes(at, __float_as_uint(a.f), 4);
   } else if (W.dt == ADHA_F64) {
-    const uint64_t b = (uint64_t)__double_as_longlong(a.d);
-    p[0] = (uint32_t)b;
-    p[1] = (uint32_t)(b >> 32);
+    store_bytes(at, (uint64_t)__double_as_longlong(a.d), 8);
   } else {
-    p[0] = a.u;
+    store_bytes(at, a.u, W.e);
   }
 }
 
 // DG = 0: direct section; otherwise a gather of at most DG neighbours.
 // MAXR: bound on the number of read fields (loads are unrolled to it).
 // W8: some read field is 8 bytes wide.
-template <int OP, int DG, int MAXR, bool W8>
+// SUB: some field is narrower than 4 bytes or not 4-byte aligned, so every
+// field is read through load_any.
+template <int OP, int DG, int MAXR, bool W8, bool SUB = false>
 __global__ __launch_bounds__(256) void section_kernel(const SectionArgs a) {
   const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
   if (i >= (uint64_t)a.n) return;
@@ -179,7 +237,7 @@ __global__ __launch_bounds__(256) void section_kernel(const SectionArgs a) {
   acc[0] = acc[1] = Acc{0.0f, 0.0, 0u};
 
   if constexpr (DG == 0) {
-    Words<MAXR, W8> w;
+    Words<MAXR, W8, SUB> w;
 #pragma unroll
     for (int q = 0; q < MAXR; ++q)
       if (q < (int)nr) w.load(q, a.buf, a.rd[q], i);
@@ -233,7 +291,10 @@ __global__ __launch_bounds__(256) void section_kernel(const SectionArgs a) {
         bad |= live && !ok[b] && !a.stencil;   // a stencil neighbour off the grid is no error
 #pragma unroll
         for (int q = 0; q < MAXR; ++q)
-          if (q < (int)nr) t[b][q] = ok[b] ? load_term(a.buf, a.rd[q], (uint64_t)cur[b]) : 0;
+          if (q < (int)nr) {
+            if constexpr (SUB) t[b][q] = ok[b] ? load_any(a.buf, a.rd[q], (uint64_t)cur[b]) : 0;
+            else t[b][q] = ok[b] ? load_term(a.buf, a.rd[q], (uint64_t)cur[b]) : 0;
+          }
       }
 #pragma unroll
       for (int b = 0; b < NB; ++b)
@@ -576,7 +637,37 @@ static SField sfield(const LayoutDesc &l, int f) {
   s.logT = g.logT;
   s.e = l.shape.ebytes[f];
   s.dt = (uint32_t)l.shape.dtype[f];
+  // base is a multiple of 256; the other terms of an address are multiples
+  // of T*S, p*T and e
+  s.al = (s.e % 4 == 0 && s.TS % 4 == 0 && s.pT % 4 == 0) ? 1u : 0u;
   return s;
+}
+
+// Kernels for sections with a field narrower than 4 bytes or a field that is
+// not 4-byte aligned in the layout: the generic kernel reading every field
+// through load_any.
+template <int OP, int DG>
+static void launch_sub_maxr(uint32_t nr, dim3 grid, const SectionArgs &a, hipStream_t st) {
+  if (nr <= 8) hipLaunchKernelGGL((section_kernel<OP, DG, 8, true, true>), grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((section_kernel<OP, DG, 32, true, true>), grid, dim3(256), 0, st, a);
+}
+
+static void launch_sub(const SectionDesc &sec, uint32_t nr, dim3 grid, const SectionArgs &a, hipStream_t st) {
+  switch (sec.op) {
+    case ADHA_OP_GEN:
+      if (sec.degree == 0) launch_sub_maxr<ADHA_OP_GEN, 0>(nr, grid, a, st);
+      else if (sec.degree <= 8) launch_sub_maxr<ADHA_OP_GEN, 8>(nr, grid, a, st);
+      else if (sec.degree <= 16) launch_sub_maxr<ADHA_OP_GEN, 16>(nr, grid, a, st);
+      else launch_sub_maxr<ADHA_OP_GEN, 32>(nr, grid, a, st);
+      break;
+    case ADHA_OP_SUM: launch_sub_maxr<ADHA_OP_SUM, 0>(nr, grid, a, st); break;
+    case ADHA_OP_MULADD3:
+      hipLaunchKernelGGL((section_kernel<ADHA_OP_MULADD3, 0, 4, true, true>), grid, dim3(256), 0, st, a);
+      break;
+    default:
+      hipLaunchKernelGGL((section_kernel<ADHA_OP_SUB2, 0, 4, true, true>), grid, dim3(256), 0, st, a);
+      break;
+  }
 }
 
 template <bool LIN, int DEG, bool ROW>
@@ -735,7 +826,8 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
   return v;
 }
 
-__device__ __forceinline__ uint64_t as_i64(uint64_t t) { return (uint64_t)(int64_t)(int32_t)(uint32_t)t; }
+// An integer column's term as int64 bits (I32 sign-extended, U32 zero-extended).
+__device__ __forceinline__ uint64_t int_col(uint32_t dt, uint64_t t) { return (uint64_t)int_value(dt, t); }
 
 // End of a register-form workgroup: per cell of the slice, the wave sums
 // (lane 0 of each wave into LDS), then the 4 waves in order, into the
@@ -834,7 +926,7 @@ __global__ __launch_bounds__(256) void reduce_reg_kernel(const ReduceArgs a) {
           hi[kk][c] = f64_bits(s);
         }
       } else {
-        const uint64_t u = col < nr ? as_i64(v[c]) : v[c];
+        const uint64_t u = col < nr ? int_col(a.rd[col].dt, v[c]) : v[c];
 #pragma unroll
         for (int kk = 0; kk < KR; ++kk) hi[kk][c] = (ok && k == kk) ? hi[kk][c] + u : hi[kk][c];
       }
@@ -925,7 +1017,7 @@ __global__ __launch_bounds__(64) void reduce_lds_kernel(const ReduceArgs a) {
 #pragma unroll
     for (int q = 0; q < MAXR; ++q) {
       const uint64_t t = q < (int)nr ? w.term(q, a.rd[q]) : 0;
-      v[q] = (a.fp_mask >> q & 1u) ? f64_bits(to_f64(a.rd[q].dt, t)) : as_i64(t);
+      v[q] = (a.fp_mask >> q & 1u) ? f64_bits(to_f64(a.rd[q].dt, t)) : int_col(a.rd[q].dt, t);
     }
     // rank of each lane among the lanes with its key, in lane order, and the
     // number of rounds (the largest count of one key)
@@ -1091,9 +1183,15 @@ adha_status reduce_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l,
   a.plain = ctx->reduce_plain ? 1u : 0u;
   for (size_t q = 0; q < sec.rd.size(); ++q) {
     a.rd[q] = sfield(l, sec.rd[q]);
-    if (l.shape.dtype[sec.rd[q]] != ADHA_I32) a.fp_mask |= 1u << q;
+    const int32_t dt = l.shape.dtype[sec.rd[q]];
+    if (dt == ADHA_F32 || dt == ADHA_F64) a.fp_mask |= 1u << q;
+    if (!a.rd[q].al)
+      return fail(ADHA_ERR_UNSUPPORTED, "reduction field %d is not 4-byte aligned in this layout", sec.rd[q]);
   }
-  if (sec.key >= 0) a.key = sfield(l, sec.key);
+  if (sec.key >= 0) {
+    a.key = sfield(l, sec.key);
+    if (!a.key.al) return fail(ADHA_ERR_UNSUPPORTED, "the reduction's key is not 4-byte aligned in this layout");
+  }
   const ReducePlan p = reduce_plan(ctx, sec, n);
   if (p.partial_bytes > partial_cap)
     return fail(ADHA_ERR_INVALID, "reduction partials need %llu bytes, the scratch holds %llu",
@@ -1191,6 +1289,15 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
   }
   const dim3 grid((uint32_t)((n + 255) / 256));
   const uint32_t nr = a.n_read;
+  // a field narrower than 4 bytes or not 4-byte aligned: the byte-wise form
+  bool sub = false;
+  for (uint32_t q = 0; q < nr; ++q) sub |= !a.rd[q].al;
+  for (uint32_t k = 0; k < a.n_write; ++k) sub |= !a.wr[k].al;
+  if (sub) {
+    launch_sub(sec, nr, grid, a, stream);
+    ADHA_HIP(hipGetLastError());
+    return ADHA_OK;
+  }
   // direct GEN / SUM over F32 fields only: the straight-line kernel
   bool all_f32 = true, all_t1 = l.nbytes <= (1ull << 32);
   for (uint32_t q = 0; q < nr; ++q) {

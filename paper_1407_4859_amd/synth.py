@@ -327,6 +327,21 @@ def medical_struct(side: int = 256) -> StructSpec:
     return StructSpec(side ** 3, [F32] * 9, [4] * 9)
 
 
+def medical_narrow_struct(side: int = 256) -> StructSpec:
+    """The Medical-shaped struct with narrow image fields: V1..V3 U16 (16-bit
+    intensities), U1..U3 F32, S U8 (an 8-bit label), T I16 (a signed 16-bit
+    value), interpT F32 -- 18 bytes per voxel, so fields of an interleaved
+    group sit at offsets that are not multiples of 4."""
+    n = side ** 3
+    return StructSpec(n, [U16, U16, U16, F32, F32, F32, U8, I16, F32], [2, 2, 2, 4, 4, 4, 1, 2, 4])
+
+
+def mixed_narrow_struct(n: int) -> StructSpec:
+    """A struct of every typed element kind: U8, I16, F32, U16, F64, U32, I32,
+    U8, F32, I16 (30 bytes per record)."""
+    return StructSpec(n, [U8, I16, F32, U16, F64, U32, I32, U8, F32, I16], [1, 2, 4, 2, 8, 4, 4, 1, 4, 2])
+
+
 def medical_sections():
     """Four loops: (read, write, stencil offsets or None for a direct loop).
     Two 7-point stencils (over U into V1, over V into U1) and two direct

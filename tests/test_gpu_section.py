@@ -23,7 +23,7 @@ def ctx():
 def ulp_distance(g: np.ndarray, w: np.ndarray, dt) -> float:
     """Largest distance in units in the last place between two fp columns
     (element bytes uint8 [n, e]); integer columns must match exactly."""
-    if dt == synth.I32:
+    if dt not in (synth.F32, synth.F64):
         return 0.0 if np.array_equal(g, w) else float("inf")
     it = np.int32 if dt == synth.F32 else np.int64
     x = g.copy().view(it).reshape(-1).astype(np.float64)
@@ -124,6 +124,28 @@ def test_ops_and_types(ctx):
     eb = spec.elem_bytes
     for O in (oaos(n, eb), osoa(n, eb), OLayout(n, eb, [0, 0, 1, 1, 0, 2, 1], [1, 4, 1])):
         _run_sections(ctx, spec, O, secs, cols, idx, "ops")
+
+
+@pytest.mark.parametrize("deg", [0, 5])
+def test_every_write_type_in_both_write_slots(ctx, deg):
+    """Each write type (F32, I32, F64, U32) in each write slot, from the
+    direct, per-field gather and span gather kernels: the store of every type
+    is checked on its own, integer folds included (bit for bit)."""
+    n = 2049
+    F32, I32, F64, U32 = synth.F32, synth.I32, synth.F64, synth.U32
+    dts = [F32, I32, F64, F32, I32, F64, U32, F32, I32, F64, U32]
+    eb = [8 if d == F64 else 4 for d in dts]
+    spec = synth.StructSpec(n, dts, eb)
+    cols = synth.record_matrix(13, n, dts, eb)
+    idx = synth.uniform_index(13, 9, n * max(deg, 1), n)
+    secs = [synth.SectionSpec(synth.OP_GEN, [0, 1, 2], [a, b], deg) for a in range(3, 7) for b in range(7, 11)]
+    for span in (1, 0):
+        ctx.set_option(A.OPT_SPAN_GATHER, span)
+        try:
+            for O in (oaos(n, eb), osoa(n, eb)):
+                _run_sections(ctx, spec, O, secs, cols, idx if deg else None, f"write types span={span}")
+        finally:
+            ctx.set_option(A.OPT_SPAN_GATHER, 1)
 
 
 def test_wide_read_sets(ctx):

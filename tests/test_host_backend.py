@@ -198,3 +198,26 @@ class _FakeDev:
 
     def element_size(self):
         return 1
+
+
+def test_narrow_typed_fields_on_the_host():
+    """Sections over U8, U16, I16, U32 fields (and wider fields at unaligned
+    offsets in interleaved groups) on the host: bit for bit the oracle's,
+    on several layouts."""
+    n = 3001
+    spec = synth.mixed_narrow_struct(n)
+    cols = synth.record_matrix(21, n, spec.dtypes, spec.elem_bytes)
+    idx = synth.uniform_index(21, 5, n * 6, n)
+    st = A.Struct.from_spec(spec)
+    secs = [synth.SectionSpec(synth.OP_GEN, [0, 1, 2, 3, 4], [8, 9]),
+            synth.SectionSpec(synth.OP_GEN, [0, 3, 5, 6], [7], 6),
+            synth.SectionSpec(synth.OP_GEN, [1, 7, 9], [2, 5]),
+            synth.SectionSpec(synth.OP_MULADD3, [0, 1, 5], [4]),
+            synth.SectionSpec(synth.OP_SUM, [3, 7, 9], [8])]
+    for O in _layouts(n, spec.elem_bytes):
+        want = oracle.pack(O, cols)
+        got = want.copy()
+        for s in secs:
+            oracle.section(O, spec.dtypes, s.op, s.read, s.write, s.degree, idx if s.degree else None, want)
+            A.host_section_run(A.Section.from_spec(st, s), _mirror(st, O), got, idx if s.degree else None, threads=3)
+        assert np.array_equal(got, want), O
