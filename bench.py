@@ -69,8 +69,11 @@ def remap_traffic_bytes():
     return round((t["fetch_kib"] * kib / t["copy_fetch_kib"] + t["write_kib"] * kib / t["copy_write_kib"]) * 1024)
 
 
+_T0 = time.perf_counter()
+
+
 def log(*a):
-    print("[bench]", *a, file=sys.stderr, flush=True)
+    print("[bench %6.1fs]" % (time.perf_counter() - _T0), *a, file=sys.stderr, flush=True)
 
 
 def parse():

@@ -456,7 +456,9 @@ typedef struct {
   adha_catalogue catalogue;
   uint32_t cap_bytes; /* ODS structure capacity in bytes (default 128: one line) */
   adha_init init;     /* FREE: data starts in the first chosen layout at no cost */
-  uint32_t reps;      /* measured costs: median of this many timed runs */
+  uint32_t reps;      /* measured costs: median of this many timed runs
+                       * after a warm-up; with reps = 1 a section launch
+                       * whose warm-up takes 2 ms or more is timed once */
   adha_devices devices; /* GPU only, or GPU and host */
   uint32_t pair_remaps; /* MEASURED, linear GPU programs: 1 (default) times the
                          * in-place remap of every ordered pair of candidates;

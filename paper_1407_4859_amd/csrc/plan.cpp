@@ -258,14 +258,29 @@ double analytic_remap_us(const LayoutDesc &a, const LayoutDesc &b, bool whole) {
   return kLaunchUs + bytes / kBytesPerUs;
 }
 
-// Median time in microseconds of `reps` runs of fn on `stream`, after one warm-up.
+// Median time in microseconds of `reps` runs of fn on `stream`, after one
+// warm-up.  With long_us > 0 and reps == 1 the warm-up is timed as well, and
+// a warm-up of at least long_us is the figure (the timed run would repeat a
+// launch whose one-time costs are small next to it).
 template <class Fn>
-static adha_status time_us(hipStream_t stream, uint32_t reps, Fn fn, double *out) {
+static adha_status time_us(hipStream_t stream, uint32_t reps, Fn fn, double *out, double long_us = 0.0) {
   hipEvent_t a, b;
   ADHA_HIP(hipEventCreate(&a));
   ADHA_HIP(hipEventCreate(&b));
   std::vector<double> ts;
+  const bool time_warm = long_us > 0.0 && reps == 1;
+  if (time_warm) (void)hipEventRecord(a, stream);
   adha_status st = fn();
+  if (time_warm && st >= 0) {
+    (void)hipEventRecord(b, stream);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    if (ms * 1000.0 >= long_us) {
+      ts.push_back(ms * 1000.0);
+      reps = 0;
+    }
+  }
   for (uint32_t r = 0; r < reps && st >= 0; ++r) {
     (void)hipEventRecord(a, stream);
     st = fn();
@@ -282,6 +297,10 @@ static adha_status time_us(hipStream_t stream, uint32_t reps, Fn fn, double *out
   *out = ts.empty() ? 0.0 : ts[ts.size() / 2];
   return ADHA_OK;
 }
+
+// Section timings of one launch (reps = 1) take a warm-up of at least this
+// long as the figure.
+static const double kLongLaunchUs = 2000.0;
 
 struct DevBuf {
   void *p = nullptr;
@@ -367,7 +386,7 @@ static adha_status measured_costs(Ctx *ctx, const Shape &sh, const std::vector<S
       // a gather section's index array is [N][d]; a wider one is read as [N][d] too
       ADHA_TRY(time_us(stream, reps,
                        [&] { return section_launch(ctx, secs[s], cands[c]->d, a.p, idx, stream, tab.p); },
-                       &(*T)[s * C + c]));
+                       &(*T)[s * C + c], kLongLaunchUs));
       seen.emplace(key, (*T)[s * C + c]);
     }
   if (only) {
