@@ -361,8 +361,10 @@ adha_status adha_section_run_static(adha_ctx *ctx, const adha_section *sec, cons
                                     void *buf, uint64_t buf_cap, const int32_t *idx, uint64_t idx_count,
                                     void *stream);
 /* Algorithmic bytes one run moves: N*(read + write bytes) for direct
- * sections, N*(4*d + d*read + write bytes) for gathers, N*(read + key
- * bytes) for reductions. */
+ * sections and stencils (a stencil's neighbours are records of the same
+ * arrays, so at the minimum each element is read once), N*(4*d + d*read +
+ * write bytes) for gathers over an index array, N*(read + key bytes) for
+ * reductions. */
 adha_status adha_section_bytes(const adha_section *sec, uint64_t *out);
 /* Effective HBM bytes one run moves under layout l, counted in 128-byte
  * access granules (the line a random access fetches, measured with
@@ -599,10 +601,11 @@ adha_status adha_run_hetero(adha_ctx *ctx, const adha_plan *pl, const adha_layou
 /* ------------------------------------------------------------ probes */
 /* Bandwidth ceilings of the device, with plain kernels of the library:
  * kind 0 reads `bytes` of a, kind 1 writes `bytes` of b, kind 2 copies a to
- * b, all as 16-byte accesses over a persistent grid (8 workgroups per CU).
- * *us is the best over four forms (1 or 4 chunks in flight per thread,
- * ordinary or streaming accesses) of the median of reps timed launches
- * after one warm-up.  Buffers are
+ * b, all as 16-byte accesses over a persistent grid.  *us is the best, over
+ * a sweep of 48 forms (1, 2, 4 or 8 chunks in flight per thread; ordinary
+ * or streaming accesses; 4, 8 or 16 workgroups per CU; the grid striding
+ * over the buffer or each workgroup streaming a contiguous share), of the
+ * median of reps timed launches after one warm-up.  Buffers are
  * device, 256-byte aligned, `bytes` each (a multiple of 16; b is the read
  * probe's sink and stays unwritten in practice); a and b may not overlap
  * for a copy.  GB/s = bytes (read, write) or 2*bytes (copy) / us / 1e3. */

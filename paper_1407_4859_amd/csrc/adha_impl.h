@@ -227,9 +227,10 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
 static const uint64_t kReducePartialPairs = 1ull << 20;
 struct ReducePlan {
   uint32_t keys_in_regs = 0;  // 1..8: register form with that many key rows; 0: LDS form
+  uint32_t slot_cols = 0;     // > 0: slot form (F32 reads, 3..8 keys) with this slice width
   uint32_t slices = 1;        // column slices (gridDim.y) of the register form
   uint32_t groups = 1;        // workgroups per slice
-  size_t lds = 0;             // dynamic LDS of the LDS form
+  size_t lds = 0;             // dynamic LDS of the LDS and slot forms
   uint64_t partial_bytes = 0;
 };
 ReducePlan reduce_plan(const Ctx *ctx, const SectionDesc &sec, int64_t n);

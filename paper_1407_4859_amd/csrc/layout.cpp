@@ -310,8 +310,9 @@ uint64_t SectionDesc::algorithmic_bytes() const {
   for (int f : wr) wb += shape.ebytes[f];
   uint64_t n = (uint64_t)shape.n;
   if (key >= 0) rb += shape.ebytes[key];
-  if (degree == 0) return n * (rb + wb);
-  if (stencil) return n * ((uint64_t)degree * rb + wb);
+  // a stencil's neighbours are records of the same arrays: at the minimum
+  // every element is read once, as in a direct pass
+  if (degree == 0 || stencil) return n * (rb + wb);
   return n * (4ull * degree + (uint64_t)degree * rb + wb);
 }
 

@@ -3,9 +3,11 @@
 //
 // stream_*: plain 16-byte streams over a buffer -- read only, write only,
 // and copy (read + write, the access pattern of a remap) -- with a
-// persistent grid striding over 16-byte chunks, so every wave issues
-// coalesced 1 KiB accesses; the host takes the best of four forms (1 or 4
-// chunks in flight per thread, ordinary or streaming accesses).
+// persistent grid, every wave issuing coalesced 1 KiB accesses; the host
+// takes the best of a sweep of forms (1, 2, 4 or 8 chunks in flight per
+// thread, ordinary or streaming accesses, 4, 8 or 16 workgroups per CU, the
+// grid striding over the buffer or each workgroup streaming a contiguous
+// share of it).
 // gather: random accesses of 4, 8 or 16 bytes at record r * stride for
 // uniformly random records r (the access of a gather section's neighbour
 // field), one per lane, the index array and the per-lane results streamed.
@@ -35,15 +37,35 @@ __device__ __forceinline__ void st16(u32x4p *p, u32x4p v) {
   else *p = v;
 }
 
-template <int U, bool NT>
+// The chunks a thread visits: from `first`, steps of `step` below `end`.
+// Grid-striding (CONT = false): workgroup w starts at w * 256 * U and the
+// grid moves over the buffer together.  Contiguous (CONT = true): workgroup
+// w streams chunks [w * share, (w + 1) * share), share a multiple of 256 * U.
+template <int U, bool CONT>
+__device__ __forceinline__ void chunk_range(uint64_t n16, uint64_t *first, uint64_t *end, uint64_t *step) {
+  if constexpr (CONT) {
+    const uint64_t per = 256ull * U;
+    const uint64_t share = (n16 + (uint64_t)gridDim.x * per - 1) / ((uint64_t)gridDim.x * per) * per;
+    *first = (uint64_t)blockIdx.x * share + threadIdx.x;
+    *end = std::min<uint64_t>(n16, (uint64_t)(blockIdx.x + 1) * share);
+    *step = per;
+  } else {
+    *first = (uint64_t)blockIdx.x * 256 * U + threadIdx.x;
+    *end = n16;
+    *step = (uint64_t)gridDim.x * 256 * U;
+  }
+}
+
+template <int U, bool NT, bool CONT>
 __global__ __launch_bounds__(256) void probe_read_kernel(const u32x4p *__restrict__ a, uint64_t n16,
                                                          uint32_t *__restrict__ sink) {
   u32x4p acc = {0, 0, 0, 0};
-  const uint64_t step = (uint64_t)gridDim.x * 256 * U;
-  for (uint64_t i = (uint64_t)blockIdx.x * 256 * U + threadIdx.x; i < n16; i += step) {
+  uint64_t i, end, step;
+  chunk_range<U, CONT>(n16, &i, &end, &step);
+  for (; i < end; i += step) {
     u32x4p v[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = i + 256 * u < n16 ? ld16<NT>(a + i + 256 * u) : u32x4p{0, 0, 0, 0};
+    for (int u = 0; u < U; ++u) v[u] = i + 256 * u < end ? ld16<NT>(a + i + 256 * u) : u32x4p{0, 0, 0, 0};
 #pragma unroll
     for (int u = 0; u < U; ++u) acc ^= v[u];
   }
@@ -53,29 +75,31 @@ __global__ __launch_bounds__(256) void probe_read_kernel(const u32x4p *__restric
   if (x == 0x9E3779B9u) sink[(uint64_t)blockIdx.x * 256 + threadIdx.x] = x;
 }
 
-template <int U, bool NT>
+template <int U, bool NT, bool CONT>
 __global__ __launch_bounds__(256) void probe_write_kernel(u32x4p *__restrict__ b, uint64_t n16, uint32_t v) {
   const u32x4p w = {v, v ^ 1u, v ^ 2u, v ^ 3u};
-  const uint64_t step = (uint64_t)gridDim.x * 256 * U;
-  for (uint64_t i = (uint64_t)blockIdx.x * 256 * U + threadIdx.x; i < n16; i += step) {
+  uint64_t i, end, step;
+  chunk_range<U, CONT>(n16, &i, &end, &step);
+  for (; i < end; i += step) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (i + 256 * u < n16) st16<NT>(b + i + 256 * u, w);
+      if (i + 256 * u < end) st16<NT>(b + i + 256 * u, w);
   }
 }
 
-template <int U, bool NT>
+template <int U, bool NT, bool CONT>
 __global__ __launch_bounds__(256) void probe_copy_kernel(const u32x4p *__restrict__ a, u32x4p *__restrict__ b,
                                                          uint64_t n16) {
-  const uint64_t step = (uint64_t)gridDim.x * 256 * U;
-  for (uint64_t i = (uint64_t)blockIdx.x * 256 * U + threadIdx.x; i < n16; i += step) {
+  uint64_t i, end, step;
+  chunk_range<U, CONT>(n16, &i, &end, &step);
+  for (; i < end; i += step) {
     u32x4p v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (i + 256 * u < n16) v[u] = ld16<NT>(a + i + 256 * u);
+      if (i + 256 * u < end) v[u] = ld16<NT>(a + i + 256 * u);
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (i + 256 * u < n16) st16<NT>(b + i + 256 * u, v[u]);
+      if (i + 256 * u < end) st16<NT>(b + i + 256 * u, v[u]);
   }
 }
 
@@ -154,34 +178,47 @@ adha_status adha_probe_stream(adha_ctx *ctx, uint32_t kind, void *a, void *b, ui
     return fail(ADHA_ERR_INVALID, "source and destination overlap");
   DeviceGuard g(ctx->c.device);
   hipStream_t st = (hipStream_t)stream;
-  // the best of four forms: 1 or 4 chunks in flight per thread, ordinary or
-  // streaming accesses; a persistent grid of 8 workgroups per CU
+  // the best of the sweep: U chunks in flight per thread (1, 2, 4, 8),
+  // ordinary or streaming accesses, 4, 8 or 16 workgroups per CU, grid-
+  // striding or contiguous shares
   double best = 0.0;
-  for (int form = 0; form < 4; ++form) {
-    const int U = form & 1 ? 4 : 1;
-    const bool nt = form >= 2;
-    const uint32_t grid = (uint32_t)std::max<uint64_t>(
-        1, std::min<uint64_t>((n16 + 256 * U - 1) / (256 * U), (uint64_t)ctx->c.cu_count * 8));
-    if (kind == 0 && (uint64_t)grid * 256 * 4 > bytes) return fail(ADHA_ERR_INVALID, "buffer too small for the probe");
-    double t = 0.0;
-#define ADHA_PROBE(UU, NTT)                                                                                        \
-  ADHA_TRY(median_us(st, reps, [&] {                                                                               \
-    if (kind == 0)                                                                                                 \
-      hipLaunchKernelGGL((probe_read_kernel<UU, NTT>), dim3(grid), dim3(256), 0, st, (const u32x4p *)a, n16,      \
-                         (uint32_t *)b);                                                                           \
-    else if (kind == 1)                                                                                            \
-      hipLaunchKernelGGL((probe_write_kernel<UU, NTT>), dim3(grid), dim3(256), 0, st, (u32x4p *)b, n16, 0x5A5A5A5Au); \
-    else                                                                                                           \
-      hipLaunchKernelGGL((probe_copy_kernel<UU, NTT>), dim3(grid), dim3(256), 0, st, (const u32x4p *)a,           \
-                         (u32x4p *)b, n16);                                                                        \
+  bool have = false;
+  for (uint32_t wpc : {4u, 8u, 16u})
+    for (int U : {1, 2, 4, 8})
+      for (int nt = 0; nt < 2; ++nt)
+        for (int cont = 0; cont < 2; ++cont) {
+          const uint32_t grid = (uint32_t)std::max<uint64_t>(
+              1, std::min<uint64_t>((n16 + 256 * U - 1) / (256 * U), (uint64_t)ctx->c.cu_count * wpc));
+          // the read probe's sink holds one word per thread of the grid
+          if (kind == 0 && (uint64_t)grid * 256 * 4 > bytes) continue;
+          double t = 0.0;
+#define ADHA_PROBE(UU, NTT, CC)                                                                                  \
+  ADHA_TRY(median_us(st, reps, [&] {                                                                             \
+    if (kind == 0)                                                                                               \
+      hipLaunchKernelGGL((probe_read_kernel<UU, NTT, CC>), dim3(grid), dim3(256), 0, st, (const u32x4p *)a, n16, \
+                         (uint32_t *)b);                                                                         \
+    else if (kind == 1)                                                                                          \
+      hipLaunchKernelGGL((probe_write_kernel<UU, NTT, CC>), dim3(grid), dim3(256), 0, st, (u32x4p *)b, n16,      \
+                         0x5A5A5A5Au);                                                                           \
+    else                                                                                                         \
+      hipLaunchKernelGGL((probe_copy_kernel<UU, NTT, CC>), dim3(grid), dim3(256), 0, st, (const u32x4p *)a,      \
+                         (u32x4p *)b, n16);                                                                      \
   }, &t))
-    if (U == 1 && !nt) ADHA_PROBE(1, false);
-    else if (U == 4 && !nt) ADHA_PROBE(4, false);
-    else if (U == 1) ADHA_PROBE(1, true);
-    else ADHA_PROBE(4, true);
+#define ADHA_PROBE_U(UU)                                \
+  if (nt && cont) ADHA_PROBE(UU, true, true);           \
+  else if (nt) ADHA_PROBE(UU, true, false);             \
+  else if (cont) ADHA_PROBE(UU, false, true);           \
+  else ADHA_PROBE(UU, false, false);
+          if (U == 1) { ADHA_PROBE_U(1) }
+          else if (U == 2) { ADHA_PROBE_U(2) }
+          else if (U == 4) { ADHA_PROBE_U(4) }
+          else { ADHA_PROBE_U(8) }
+#undef ADHA_PROBE_U
 #undef ADHA_PROBE
-    if (form == 0 || t < best) best = t;
-  }
+          if (!have || t < best) best = t;
+          have = true;
+        }
+  if (!have) return fail(ADHA_ERR_INVALID, "buffer too small for the probe");
   *us = best;
   return ADHA_OK;
 }

@@ -990,6 +990,118 @@ __global__ __launch_bounds__(256) void reduce_reg_f32_kernel(const ReduceArgs a)
   if (bad) atomicOr(a.err, 1u);
 }
 
+// 3 to 8 keys, every read field F32: the slot form.  Each thread keeps its
+// pairs for a slice of CR columns in LDS, slot[(key * CR + c) * 128 + t], so
+// a value costs one TwoSum at its record's key (the register form spends one
+// per key, selecting which to keep).  128 threads; a thread walks its
+// records U at a time (all loads first, then the adds in record order).
+constexpr uint32_t kSlotThreads = 128;
+
+// The slot form's end: the pairs of the C = K * CR cells (cell x = key * CR
+// + column slot) reduced over the workgroup's threads in a fixed tree, then
+// written as the workgroup's partial.  Recursive halving first: at mask m
+// (1, 2, .., P/2; P the power of two >= C) thread t keeps half of its cell
+// range -- the upper half when t & m -- and adds thread t ^ m's pair for
+// each cell of it, the lower thread's pair first; after it thread t holds
+// one cell summed over the P threads that share its high bits.  Those
+// groups are then added pairwise in order of t, and thread t < P writes
+// cell x(t).  A barrier separates the levels.  Pairs are added with
+// pair_add, count cells as integers.
+template <int CR>
+__device__ __forceinline__ void reduce_slot_finish(const ReduceArgs &a, double2 *slot, uint32_t K, uint32_t c0,
+                                                   uint32_t nc) {
+  const uint32_t t = threadIdx.x, nr = a.n_read, cols = nr + 1;
+  const uint32_t C = K * CR;
+  uint32_t P = 1;
+  while (P < C) P <<= 1;
+  auto is_count = [&](uint32_t x) { return c0 + x % CR == nr; };
+  auto add = [&](uint32_t x, double2 lo_t, double2 hi_t) {
+    double2 r;
+    if (is_count(x)) {
+      r.x = bits_f64(f64_bits(lo_t.x) + f64_bits(hi_t.x));
+      r.y = 0.0;
+    } else {
+      pair_add(lo_t.x, lo_t.y, hi_t.x, hi_t.y, r.x, r.y);
+    }
+    return r;
+  };
+  uint32_t first = 0, span = P;
+  for (uint32_t m = 1; m < P; m <<= 1) {
+    span >>= 1;
+    const bool upper = (t & m) != 0;
+    if (upper) first += span;
+    __syncthreads();
+    for (uint32_t x = first; x < first + span; ++x) {
+      if (x >= C) break;
+      const double2 mine = slot[x * kSlotThreads + t], other = slot[x * kSlotThreads + (t ^ m)];
+      slot[x * kSlotThreads + t] = upper ? add(x, other, mine) : add(x, mine, other);
+    }
+  }
+  // thread t now holds cell `first` (if below C), summed over its P-group
+  for (uint32_t m = P; m < kSlotThreads; m <<= 1) {
+    __syncthreads();
+    if ((t & (2 * m - 1)) < P && first < C) {
+      // t is the lowest thread of its 2m-block holding this cell
+      slot[first * kSlotThreads + t] = add(first, slot[first * kSlotThreads + t], slot[first * kSlotThreads + t + m]);
+    }
+  }
+  __syncthreads();
+  if (t < P && first < C) {
+    const uint32_t kk = first / CR, c = first % CR, col = c0 + c;
+    if (c < nc && kk < a.n_keys) {
+      const double2 v = slot[first * kSlotThreads + t];
+      const uint64_t at = ((uint64_t)(kk * cols + col) * gridDim.x + blockIdx.x) * 2;
+      a.partials[at] = f64_bits(v.x);
+      a.partials[at + 1] = is_count(first) ? 0 : f64_bits(v.y);
+    }
+  }
+}
+
+template <int CR, bool LIN, bool PLAIN>
+__global__ __launch_bounds__(kSlotThreads) void reduce_slot_f32_kernel(const ReduceArgs a) {
+  extern __shared__ double2 slot[];  // [K * CR][kSlotThreads]
+  constexpr int U = 8;
+  const uint32_t nr = a.n_read, cols = nr + 1, K = a.n_keys, t = threadIdx.x;
+  const uint32_t c0 = blockIdx.y * CR;
+  const uint32_t nc = min((uint32_t)CR, cols - c0);
+  for (uint32_t x = 0; x < K * CR; ++x) slot[x * kSlotThreads + t] = make_double2(0.0, 0.0);
+  bool bad = false;
+  const uint64_t stride = (uint64_t)gridDim.x * kSlotThreads;
+  for (uint64_t i0 = (uint64_t)blockIdx.x * kSlotThreads + t; i0 < (uint64_t)a.n; i0 += U * stride) {
+    // U records: i0, i0 + stride, ...: keys and words loaded first
+    int32_t k[U];
+    uint32_t w[U][CR];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t i = i0 + u * stride;
+      const bool live = i < (uint64_t)a.n;
+      const uint64_t r = live ? i : 0;  // past N: record 0, dropped below
+      k[u] = a.has_key ? (int32_t)reduce_word<LIN>(a, a.key, r) : 0;
+      if (!live) k[u] = -1;
+#pragma unroll
+      for (int c = 0; c < CR; ++c) w[u][c] = reduce_word<LIN>(a, a.rd[c0 + c < nr ? c0 + c : ADHA_MAX_READ - 1], r);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool live = i0 + u * stride < (uint64_t)a.n;
+      const bool ok = k[u] >= 0 && (uint32_t)k[u] < K;
+      bad |= live && !ok;
+      if (!ok) continue;
+      double2 *row = slot + (uint32_t)k[u] * CR * kSlotThreads + t;
+#pragma unroll
+      for (int c = 0; c < CR; ++c) {
+        if ((uint32_t)c >= nc) continue;
+        double2 q = row[c * kSlotThreads];
+        if (c0 + c < nr) comp_add<PLAIN>(q.x, q.y, (double)__uint_as_float(w[u][c]));
+        else q.x = bits_f64(f64_bits(q.x) + 1);  // the count column: an int64 in the first word
+        row[c * kSlotThreads] = q;
+      }
+    }
+  }
+  reduce_slot_finish<CR>(a, slot, K, c0, nc);
+  if (bad) atomicOr(a.err, 1u);
+}
+
 // More keys: one wave per workgroup, with its own table of pairs in LDS.
 template <int MAXR, bool W8, bool PLAIN>
 __global__ __launch_bounds__(64) void reduce_lds_kernel(const ReduceArgs a) {
@@ -1143,10 +1255,38 @@ static void reduce_f32_dispatch(uint32_t KR, dim3 grid, hipStream_t stream, cons
 
 // Register slice widths per key count (pairs per thread: keys x columns).
 static const uint32_t kRedCols[9] = {0, 17, 9, 6, 5, 4, 3, 3, 3};
+// Slot form slice widths per key count (3..8): at most 24 KB of LDS per
+// workgroup, so a CU holds 6 or more of them (occupancy gains more than the
+// wider slices' fewer key reads: 5 keys, 32 F32 columns, 2^23 records run
+// 344 us at 2 columns per slice, 374 us at 3, 405 us at 4).
+static const uint32_t kSlotCols[9] = {0, 0, 0, 3, 2, 2, 2, 2, 2};
+
+template <bool LIN, bool PLAIN>
+static void reduce_slot_dispatch(uint32_t CR, dim3 grid, size_t lds, hipStream_t stream, const ReduceArgs &a) {
+  if (CR == 2) hipLaunchKernelGGL((reduce_slot_f32_kernel<2, LIN, PLAIN>), grid, dim3(kSlotThreads), lds, stream, a);
+  else hipLaunchKernelGGL((reduce_slot_f32_kernel<3, LIN, PLAIN>), grid, dim3(kSlotThreads), lds, stream, a);
+}
 
 ReducePlan reduce_plan(const Ctx *ctx, const SectionDesc &sec, int64_t n) {
   ReducePlan p;
   const uint32_t cells = sec.reduce_cells(), cols = (uint32_t)sec.rd.size() + 1;
+  bool f32 = true;
+  for (int f : sec.rd) f32 &= sec.shape.dtype[f] == ADHA_F32;
+  if (f32 && sec.n_keys >= 3 && sec.n_keys <= 8) {
+    // slot form: chains of at most 64 records per thread where the partial
+    // tables allow, and at least the workgroups the CUs hold at once
+    p.slot_cols = kSlotCols[sec.n_keys];
+    p.slices = (cols + p.slot_cols - 1) / p.slot_cols;
+    p.lds = (size_t)sec.n_keys * p.slot_cols * kSlotThreads * 16;
+    const uint64_t want = std::max<uint64_t>(1, ((uint64_t)n + kSlotThreads - 1) / kSlotThreads);
+    const uint64_t per_cu = std::max<uint64_t>(1, 163840 / p.lds);
+    const uint64_t budget = std::max<uint64_t>(1, (uint64_t)std::max(1, ctx->cu_count) * per_cu / p.slices);
+    const uint64_t short_chains = ((uint64_t)n + kSlotThreads * 64 - 1) / (kSlotThreads * 64);
+    const uint64_t cap = std::max<uint64_t>(1, kReducePartialPairs / cells);
+    p.groups = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(want, std::max(budget, short_chains)), cap);
+    p.partial_bytes = (uint64_t)p.groups * cells * 16;
+    return p;
+  }
   p.keys_in_regs = sec.n_keys <= 8 ? sec.n_keys : 0;
   p.slices = p.keys_in_regs ? (cols + kRedCols[p.keys_in_regs] - 1) / kRedCols[p.keys_in_regs] : 1;
   const uint64_t per_wg = p.keys_in_regs ? 256 : 64;
@@ -1205,7 +1345,14 @@ adha_status reduce_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l,
     f32 &= l.shape.dtype[f] == ADHA_F32;
   }
   const bool plain = a.plain != 0;
-  if (f32 && KR >= 1) {
+  if (p.slot_cols) {
+    bool lin = l.nbytes <= (1ull << 32) && (sec.key < 0 || a.key.logT == 0);
+    for (uint32_t q = 0; q < nr; ++q) lin &= a.rd[q].logT == 0;
+    if (lin) plain ? reduce_slot_dispatch<true, true>(p.slot_cols, grid, p.lds, stream, a)
+                   : reduce_slot_dispatch<true, false>(p.slot_cols, grid, p.lds, stream, a);
+    else plain ? reduce_slot_dispatch<false, true>(p.slot_cols, grid, p.lds, stream, a)
+               : reduce_slot_dispatch<false, false>(p.slot_cols, grid, p.lds, stream, a);
+  } else if (f32 && KR >= 1) {
     bool lin = l.nbytes <= (1ull << 32) && (sec.key < 0 || a.key.logT == 0);
     for (uint32_t q = 0; q < nr; ++q) lin &= a.rd[q].logT == 0;
     if (lin) plain ? reduce_f32_dispatch<true, true>(KR, grid, stream, a) : reduce_f32_dispatch<true, false>(KR, grid, stream, a);

@@ -125,6 +125,11 @@ def test_invalid_host_arguments_are_rejected():
         A.Section(A.Struct(4, [A.I32, A.I32]), A.OP_SUM, [0], [1])  # SUM needs an fp write
     s = A.Section(st, A.OP_GEN, [0, 2], [1], 16)
     assert s.bytes == 10 * (4 * 16 + 16 * 12 + 4)
+    # a stencil's algorithmic bytes count every element once (neighbours
+    # are records of the same arrays), like a direct pass
+    grid_st = A.Struct(2 * 5 * 1, [A.F32, A.F32, A.F64])
+    sten = A.Section.stencil(grid_st, [0, 2], [1], (2, 5, 1), [(0, 0, 0), (1, 0, 0), (0, -1, 0)])
+    assert sten.bytes == 10 * (4 + 8 + 4)
     with pytest.raises(A.AdhaError):
         A.Layout.aos(st).addr(10, 0)
 
