@@ -59,7 +59,7 @@ def test_stencil_validation_and_costs():
         with pytest.raises(A.AdhaError):
             A.Section.stencil(st, rd, wr, grid, offs)
     s = A.Section.stencil(st, [0, 1], [2], (4, 4, 4), synth.STENCIL7)
-    assert s.bytes == 64 * (7 * 8 + 4)                 # no index bytes
+    assert s.bytes == 64 * (8 + 4)                     # every element once, no index bytes
     prog = A.Program(st, [s])
     opts = A.plan_opts(cost=A.COST_ANALYTIC, cap_bytes=64)
     h = ctypes.c_void_p()
