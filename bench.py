@@ -164,17 +164,19 @@ class Timer:
         return ts[len(ts) // 2], ts
 
     def time_cold(self, fn, reps=5, warm=1):
-        """As time(), with 512 MiB written to a scratch buffer before each
-        timed launch (outside the events), so no launch finds its data in
-        the 256 MB last-level cache or the L2s from the one before."""
+        """As time(), with a 512 MiB scratch buffer read before each timed
+        launch (outside the events), so no launch finds its data in the
+        256 MB last-level cache or the L2s from the one before.  The buffer
+        is read, not written: evicting clean lines costs the timed launch no
+        write-backs."""
         t = self.torch
         if getattr(self, "_flush", None) is None:
-            self._flush = t.empty(1 << 29, dtype=t.uint8, device="cuda")
+            self._flush = t.ones(1 << 26, dtype=t.int64, device="cuda")
         for _ in range(warm):
             fn()
         ts = []
         for r in range(reps):
-            self._flush.fill_(r & 0xFF)
+            self._sink = self._flush.sum()
             a, b = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
             a.record()
             fn()

@@ -26,7 +26,10 @@ def ctx():
 
 def _program(st, grid, extra=True):
     secs = []
-    for rd, wr, offs in synth.medical_sections() + ([([0, 1, 2], [6, 7], OFFS27)] if extra else []):
+    # extra: a 27-point stencil, and a 7-point one over 4 fields with two
+    # writes (the multi-record 7-point kernel's widest form)
+    more = [([0, 1, 2], [6, 7], OFFS27), ([3, 4, 5, 8], [0, 1], synth.STENCIL7)]
+    for rd, wr, offs in synth.medical_sections() + (more if extra else []):
         if offs is None:
             secs.append((A.Section(st, A.OP_GEN, rd, wr, 0), rd, wr, None))
         else:
