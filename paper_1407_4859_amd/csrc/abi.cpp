@@ -295,7 +295,7 @@ adha_status adha_ctx_cu_count(const adha_ctx *ctx, int32_t *out) {
 
 adha_status adha_ctx_set_option(adha_ctx *ctx, adha_option opt, int64_t value) {
   if (!ctx) return fail(ADHA_ERR_INVALID, "ctx is NULL");
-  switch (opt) {
+  switch (enum_value(opt)) {
     case ADHA_OPT_SPAN_GATHER:
       if (value != 0 && value != 1) return fail(ADHA_ERR_INVALID, "span-gather option is 0 or 1");
       ctx->c.no_span = value == 0;
@@ -313,7 +313,7 @@ adha_status adha_ctx_set_option(adha_ctx *ctx, adha_option opt, int64_t value) {
       ctx->c.reduce_plain = value == 0;
       return ADHA_OK;
     default:
-      return fail(ADHA_ERR_INVALID, "unknown option %d", (int)opt);
+      return fail(ADHA_ERR_INVALID, "unknown option %d", enum_value(opt));
   }
 }
 
@@ -331,7 +331,7 @@ adha_status adha_struct_create(int64_t n_records, adha_struct **out) {
 
 adha_status adha_struct_add_field(adha_struct *s, adha_dtype dt, uint32_t elem_bytes, int32_t *out_id) {
   if (!s) return fail(ADHA_ERR_INVALID, "struct is NULL");
-  switch (dt) {
+  switch (enum_value(dt)) {
     case ADHA_F32:
     case ADHA_I32:
     case ADHA_U32:
@@ -352,7 +352,7 @@ adha_status adha_struct_add_field(adha_struct *s, adha_dtype dt, uint32_t elem_b
         return fail(ADHA_ERR_INVALID, "RAW element size %u not in {1, 2, 4, 8}", elem_bytes);
       break;
     default:
-      return fail(ADHA_ERR_INVALID, "unknown dtype %d", (int)dt);
+      return fail(ADHA_ERR_INVALID, "unknown dtype %d", enum_value(dt));
   }
   if (s->shape.nfields() >= ADHA_MAX_FIELDS) return fail(ADHA_ERR_INVALID, "at most %d fields", ADHA_MAX_FIELDS);
   if (s->shape.record_bytes() + elem_bytes > 2048) return fail(ADHA_ERR_INVALID, "records are limited to 2048 bytes");
@@ -649,7 +649,7 @@ adha_status adha_section_create(const adha_struct *s, adha_op op, uint32_t n_rea
   if (degree > ADHA_MAX_DEGREE) return fail(ADHA_ERR_INVALID, "degree %u > %d", degree, ADHA_MAX_DEGREE);
   SectionDesc d;
   d.shape = sh;
-  d.op = (int32_t)op;
+  d.op = enum_value(op);
   d.degree = degree;
   d.rd.assign(read, read + n_read);
   d.wr.assign(write, write + n_write);
@@ -668,7 +668,7 @@ adha_status adha_section_create(const adha_struct *s, adha_op op, uint32_t n_rea
       if (std::find(d.rd.begin(), d.rd.end(), f) != d.rd.end())
         return fail(ADHA_ERR_INVALID, "gather section writes field %d that it reads (records would race)", f);
   }
-  switch (op) {
+  switch (enum_value(op)) {
     case ADHA_OP_GEN:
       break;
     case ADHA_OP_MULADD3:
@@ -685,7 +685,7 @@ adha_status adha_section_create(const adha_struct *s, adha_op op, uint32_t n_rea
     case ADHA_OP_REDUCE:
       return fail(ADHA_ERR_INVALID, "reductions are created by adha_section_create_reduce");
     default:
-      return fail(ADHA_ERR_INVALID, "unknown op %d", (int)op);
+      return fail(ADHA_ERR_INVALID, "unknown op %d", enum_value(op));
   }
   auto *sec = new (std::nothrow) adha_section;
   if (!sec) return fail(ADHA_ERR_OOM, "section allocation failed");

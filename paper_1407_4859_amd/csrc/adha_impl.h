@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstring>
 #include <map>
 #include <memory>
 #include <string>
@@ -14,6 +15,18 @@
 #include "adha.h"
 
 namespace adha {
+
+// The integer a caller passed for an enum parameter or option field, read
+// from its bytes: a value outside the enumerators (an invalid argument from
+// C or Python) is then an ordinary int to reject, not a load of an enum
+// outside its range.
+template <class E>
+inline int32_t enum_value(const E &e) {
+  static_assert(sizeof(E) == sizeof(int32_t), "C-ABI enums are 32-bit");
+  int32_t v;
+  std::memcpy(&v, &e, sizeof v);
+  return v;
+}
 
 // ------------------------------------------------------------------ errors
 adha_status fail(adha_status st, const char *fmt, ...);

@@ -898,13 +898,18 @@ adha_status adha_plan_opts_default(adha_plan_opts *o) {
 adha_status adha_plan_create(adha_ctx *ctx, const adha_program *p, const adha_plan_opts *o,
                              const int32_t *idx, uint64_t idx_count, void *stream, adha_plan **out) {
   if (!p || !o || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
+  // the option fields' enums are checked as integers before any other use
+  const int32_t cost = enum_value(o->cost), devices = enum_value(o->devices), init = enum_value(o->init);
+  const int32_t catalogue_kind = enum_value(o->catalogue);
+  if (cost < ADHA_COST_MEASURED || cost > ADHA_COST_LEARNED) return fail(ADHA_ERR_INVALID, "unknown cost source");
+  if (catalogue_kind != ADHA_CAT_AOS_SOA && catalogue_kind != ADHA_CAT_FULL)
+    return fail(ADHA_ERR_INVALID, "unknown catalogue %d", catalogue_kind);
+  if (devices != ADHA_DEVICES_GPU && devices != ADHA_DEVICES_GPU_HOST)
+    return fail(ADHA_ERR_INVALID, "unknown devices option %d", devices);
+  if (init < ADHA_INIT_FREE || init > ADHA_INIT_HOST_AOS) return fail(ADHA_ERR_INVALID, "unknown init option");
   if (o->cost != ADHA_COST_ANALYTIC && !ctx) return fail(ADHA_ERR_INVALID, "measured and learned costs need a context");
   if (o->cap_bytes == 0) return fail(ADHA_ERR_INVALID, "cap_bytes must be positive");
-  if (o->cost < ADHA_COST_MEASURED || o->cost > ADHA_COST_LEARNED) return fail(ADHA_ERR_INVALID, "unknown cost source");
   if (idx && ((uintptr_t)idx & 255u)) return fail(ADHA_ERR_INVALID, "idx is not 256-byte aligned");
-  if (o->devices != ADHA_DEVICES_GPU && o->devices != ADHA_DEVICES_GPU_HOST)
-    return fail(ADHA_ERR_INVALID, "unknown devices option %d", (int)o->devices);
-  if (o->init < ADHA_INIT_FREE || o->init > ADHA_INIT_HOST_AOS) return fail(ADHA_ERR_INVALID, "unknown init option");
   if (o->init == ADHA_INIT_HOST_AOS && o->devices != ADHA_DEVICES_GPU_HOST)
     return fail(ADHA_ERR_INVALID, "data starting on the host needs a plan over both devices");
   if (!p->tokens.empty() && o->devices != ADHA_DEVICES_GPU)
@@ -1043,7 +1048,8 @@ adha_status adha_plan_create(adha_ctx *ctx, const adha_program *p, const adha_pl
 
 adha_status adha_plan_with_init(const adha_plan *src, adha_init init, adha_plan **out) {
   if (!src || !out) return fail(ADHA_ERR_INVALID, "NULL argument");
-  if (init != ADHA_INIT_FREE && init != ADHA_INIT_AOS) return fail(ADHA_ERR_INVALID, "init must be FREE or AOS");
+  if (enum_value(init) != ADHA_INIT_FREE && enum_value(init) != ADHA_INIT_AOS)
+    return fail(ADHA_ERR_INVALID, "init must be FREE or AOS");
   if (src->hetero || !src->tokens.empty() || src->placed.empty())
     return fail(ADHA_ERR_UNSUPPORTED, "only linear GPU plans are solved again for another start");
   const size_t k = src->secs.size(), C = src->cands.size();
