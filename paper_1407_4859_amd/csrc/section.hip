@@ -323,6 +323,103 @@ __global__ __launch_bounds__(256) void section_kernel(const SectionArgs a) {
 // and are never folded.  LIN: every read field sits in a group with T = 1
 // and the layout fits in 4 GiB, so a field's offset is base + p + r*S in 32
 // bits.
+// Direct GEN / SUM sections over F32, F64, I32 and U32 fields at 4-byte
+// aligned addresses, not all F32.  The generic kernel's fold branches on
+// the write type and the term type of every term, tens of scalar
+// instructions per term.  Here the fold is specialised on the write types
+// (WT0, WT1: 0 an F32 write, 1 F64, 2 an integer fold; WT1 = 3: one write)
+// and every term is converted by computing each candidate conversion and
+// keeping the one its type names, so no branch depends on a field's type.
+// The conversions are those of the generic kernel (nearest even).
+// RPT records per thread, one per 256-record chunk of the workgroup's RPT
+// chunks, all their loads issued before any fold: a section with few fields
+// streams few bytes per record, and one record per thread leaves too few
+// bytes in flight.
+template <int MAXR, bool W8, int WT0, int WT1, int RPT>
+__global__ __launch_bounds__(256) void direct_mixed_kernel(const SectionArgs a) {
+  const uint32_t nr = a.n_read;
+  Words<MAXR, W8> w[RPT];
+  uint64_t rec[RPT];
+  bool live[RPT];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    rec[r] = ((uint64_t)blockIdx.x * RPT + r) * 256u + threadIdx.x;
+    live[r] = rec[r] < (uint64_t)a.n;
+    const uint64_t rr = live[r] ? rec[r] : 0;  // past N: record 0, nothing stored
+#pragma unroll
+    for (int q = 0; q < MAXR; ++q)
+      if (q < (int)nr) w[r].load(q, a.buf, a.rd[q], rr);
+  }
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    if (!live[r]) continue;
+    float f0 = 0.0f, f1 = 0.0f;
+    double d0 = 0.0, d1 = 0.0;
+    uint32_t u0 = 0u, u1 = 0u;
+#pragma unroll
+    for (int q = 0; q < MAXR; ++q) {
+      if (q >= (int)nr) continue;
+      const uint32_t dt = a.rd[q].dt;
+      const uint32_t lo = w[r].lo[q];
+      const uint32_t hi = W8 ? w[r].hi[q] : 0u;
+      const double dbits = __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+      if constexpr (WT0 == 0 || WT1 == 0) {
+        const float c_f = __uint_as_float(lo), c_i = __int2float_rn((int32_t)lo), c_u = __uint2float_rn(lo);
+        const float c_d = W8 ? __double2float_rn(dbits) : 0.0f;
+        const float v = dt == ADHA_F32 ? c_f : dt == ADHA_I32 ? c_i : dt == ADHA_U32 ? c_u : c_d;
+        if constexpr (WT0 == 0) f0 = __fadd_rn(f0, v);
+        if constexpr (WT1 == 0) f1 = __fadd_rn(__fmul_rn(f1, 0.5f), v);
+      }
+      if constexpr (WT0 == 1 || WT1 == 1) {
+        const double c_f = (double)__uint_as_float(lo), c_i = (double)(int32_t)lo, c_u = (double)lo;
+        const double v = dt == ADHA_F32 ? c_f : dt == ADHA_I32 ? c_i : dt == ADHA_U32 ? c_u : dbits;
+        if constexpr (WT0 == 1) d0 = __dadd_rn(d0, v);
+        if constexpr (WT1 == 1) d1 = __dadd_rn(__dmul_rn(d1, 0.5), v);
+      }
+      if constexpr (WT0 == 2 || WT1 == 2) {
+        const uint32_t v = dt == ADHA_F64 ? lo ^ hi : lo;  // an F32, I32 or U32 term is its own 32 bits
+        if constexpr (WT0 == 2) u0 = u0 + v;
+        if constexpr (WT1 == 2) u1 = (u1 ^ v) * 16777619u;
+      }
+    }
+    const uint64_t i = rec[r];
+    auto put = [&](const SField &W, int wt, float f, double d, uint32_t u) {
+      uint32_t *p = reinterpret_cast<uint32_t *>(a.buf + faddr(W, i));
+      if (wt == 0) {
+        p[0] = __float_as_uint(f);
+      } else if (wt == 1) {
+        const uint64_t b = (uint64_t)__double_as_longlong(d);
+        p[0] = (uint32_t)b;
+        p[1] = (uint32_t)(b >> 32);
+      } else {
+        p[0] = u;
+      }
+    };
+    put(a.wr[0], WT0, f0, d0, u0);
+    if constexpr (WT1 != 3) put(a.wr[1], WT1, f1, d1, u1);
+  }
+}
+
+template <int MAXR, bool W8, int WT0>
+static void launch_direct_mixed_w1(int wt1, const SectionArgs &a, hipStream_t st) {
+  // 4 records per thread for up to 4 reads, else 1
+  constexpr int RPT = MAXR <= 4 ? 4 : 1;
+  const dim3 grid((uint32_t)(((uint64_t)a.n + 256ull * RPT - 1) / (256ull * RPT)));
+  switch (wt1) {
+    case 0: hipLaunchKernelGGL((direct_mixed_kernel<MAXR, W8, WT0, 0, RPT>), grid, dim3(256), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((direct_mixed_kernel<MAXR, W8, WT0, 1, RPT>), grid, dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((direct_mixed_kernel<MAXR, W8, WT0, 2, RPT>), grid, dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((direct_mixed_kernel<MAXR, W8, WT0, 3, RPT>), grid, dim3(256), 0, st, a); break;
+  }
+}
+
+template <int MAXR, bool W8>
+static void launch_direct_mixed_w0(int wt0, int wt1, const SectionArgs &a, hipStream_t st) {
+  if (wt0 == 0) launch_direct_mixed_w1<MAXR, W8, 0>(wt1, a, st);
+  else if (wt0 == 1) launch_direct_mixed_w1<MAXR, W8, 1>(wt1, a, st);
+  else launch_direct_mixed_w1<MAXR, W8, 2>(wt1, a, st);
+}
+
 template <int MAXR, bool LIN>
 __global__ __launch_bounds__(256) void direct_f32_kernel(const SectionArgs a) {
   const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
@@ -1452,6 +1549,27 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
     all_t1 &= a.rd[q].logT == 0;
   }
   for (uint32_t k = 0; k < a.n_write; ++k) all_f32 &= a.wr[k].dt == ADHA_F32;
+  // direct GEN / SUM over F32, F64, I32 and U32 fields (not all F32): the
+  // fold specialised on the write types, terms converted by selects
+  bool wide_types = true, w8 = false;
+  for (uint32_t q = 0; q < nr; ++q) {
+    const uint32_t dt = a.rd[q].dt;
+    wide_types &= dt == ADHA_F32 || dt == ADHA_F64 || dt == ADHA_I32 || dt == ADHA_U32;
+    w8 |= a.rd[q].e == 8;
+  }
+  auto wclass = [](uint32_t dt) { return dt == ADHA_F32 ? 0 : dt == ADHA_F64 ? 1 : 2; };
+  for (uint32_t k = 0; k < a.n_write; ++k) {
+    const uint32_t dt = a.wr[k].dt;
+    wide_types &= dt == ADHA_F32 || dt == ADHA_F64 || dt == ADHA_I32 || dt == ADHA_U32;
+  }
+  if ((sec.op == ADHA_OP_GEN || sec.op == ADHA_OP_SUM) && sec.degree == 0 && !sec.stencil && !all_f32 &&
+      wide_types && nr <= 16 && !ctx->no_span) {
+    const int wt0 = wclass(a.wr[0].dt), wt1 = a.n_write > 1 ? wclass(a.wr[1].dt) : 3;
+    if (nr <= 4) w8 ? launch_direct_mixed_w0<4, true>(wt0, wt1, a, stream) : launch_direct_mixed_w0<4, false>(wt0, wt1, a, stream);
+    else w8 ? launch_direct_mixed_w0<16, true>(wt0, wt1, a, stream) : launch_direct_mixed_w0<16, false>(wt0, wt1, a, stream);
+    ADHA_HIP(hipGetLastError());
+    return ADHA_OK;
+  }
   if ((sec.op == ADHA_OP_GEN || sec.op == ADHA_OP_SUM) && sec.degree == 0 && !sec.stencil && all_f32) {
     if (all_t1) launch_direct_f32<true>(nr, grid, a, stream);
     else launch_direct_f32<false>(nr, grid, a, stream);
