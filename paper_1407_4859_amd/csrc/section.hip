@@ -420,32 +420,43 @@ static void launch_direct_mixed_w0(int wt0, int wt1, const SectionArgs &a, hipSt
   else launch_direct_mixed_w1<MAXR, W8, 2>(wt1, a, st);
 }
 
-template <int MAXR, bool LIN>
+// RPT records per thread, one per 256-record chunk of the workgroup's RPT
+// chunks, every load issued before any fold (a few fields per record leave
+// too few bytes in flight at one record per thread).
+template <int MAXR, bool LIN, int RPT>
 __global__ __launch_bounds__(256) void direct_f32_kernel(const SectionArgs a) {
-  const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
-  if (i >= (uint64_t)a.n) return;
   const uint32_t nr = a.n_read, nw = a.n_write;
-  uint32_t w[MAXR];
+  uint32_t w[RPT][MAXR];
+  uint64_t rec[RPT];
 #pragma unroll
-  for (int q = 0; q < MAXR; ++q) {
-    const SField &F = a.rd[q];
-    if constexpr (LIN) {
-      const uint32_t off = (uint32_t)F.base + F.pT + (uint32_t)i * F.TS;
-      w[q] = *reinterpret_cast<const uint32_t *>(a.buf + off);
-    } else {
-      w[q] = *reinterpret_cast<const uint32_t *>(a.buf + faddr(F, i));
+  for (int r = 0; r < RPT; ++r) {
+    rec[r] = ((uint64_t)blockIdx.x * RPT + r) * 256u + threadIdx.x;
+    const uint64_t i = rec[r] < (uint64_t)a.n ? rec[r] : 0;  // past N: record 0, nothing stored
+#pragma unroll
+    for (int q = 0; q < MAXR; ++q) {
+      const SField &F = a.rd[q];
+      if constexpr (LIN) {
+        const uint32_t off = (uint32_t)F.base + F.pT + (uint32_t)i * F.TS;
+        w[r][q] = *reinterpret_cast<const uint32_t *>(a.buf + off);
+      } else {
+        w[r][q] = *reinterpret_cast<const uint32_t *>(a.buf + faddr(F, i));
+      }
     }
   }
-  float acc0 = 0.0f, acc1 = 0.0f;
 #pragma unroll
-  for (int q = 0; q < MAXR; ++q)
-    if (q < (int)nr) {
-      const float v = __uint_as_float(w[q]);
-      acc0 = __fadd_rn(acc0, v);
-      if (nw > 1) acc1 = __fadd_rn(__fmul_rn(acc1, 0.5f), v);
-    }
-  *reinterpret_cast<uint32_t *>(a.buf + faddr(a.wr[0], i)) = __float_as_uint(acc0);
-  if (nw > 1) *reinterpret_cast<uint32_t *>(a.buf + faddr(a.wr[1], i)) = __float_as_uint(acc1);
+  for (int r = 0; r < RPT; ++r) {
+    if (rec[r] >= (uint64_t)a.n) continue;
+    float acc0 = 0.0f, acc1 = 0.0f;
+#pragma unroll
+    for (int q = 0; q < MAXR; ++q)
+      if (q < (int)nr) {
+        const float v = __uint_as_float(w[r][q]);
+        acc0 = __fadd_rn(acc0, v);
+        if (nw > 1) acc1 = __fadd_rn(__fmul_rn(acc1, 0.5f), v);
+      }
+    *reinterpret_cast<uint32_t *>(a.buf + faddr(a.wr[0], rec[r])) = __float_as_uint(acc0);
+    if (nw > 1) *reinterpret_cast<uint32_t *>(a.buf + faddr(a.wr[1], rec[r])) = __float_as_uint(acc1);
+  }
 }
 
 // Workgroups go to the chip's 8 XCDs round-robin (workgroup b to XCD b mod
@@ -824,10 +835,12 @@ static void launch_maxr_w(uint32_t nr, dim3 grid, const SectionArgs &a, hipStrea
 
 template <bool LIN>
 static void launch_direct_f32(uint32_t nr, dim3 grid, const SectionArgs &a, hipStream_t st) {
-  if (nr <= 4) hipLaunchKernelGGL((direct_f32_kernel<4, LIN>), grid, dim3(256), 0, st, a);
-  else if (nr <= 8) hipLaunchKernelGGL((direct_f32_kernel<8, LIN>), grid, dim3(256), 0, st, a);
-  else if (nr <= 16) hipLaunchKernelGGL((direct_f32_kernel<16, LIN>), grid, dim3(256), 0, st, a);
-  else hipLaunchKernelGGL((direct_f32_kernel<32, LIN>), grid, dim3(256), 0, st, a);
+  // up to 4 reads: 4 records per thread
+  const dim3 grid4((uint32_t)(((uint64_t)a.n + 1023) / 1024));
+  if (nr <= 4) hipLaunchKernelGGL((direct_f32_kernel<4, LIN, 4>), grid4, dim3(256), 0, st, a);
+  else if (nr <= 8) hipLaunchKernelGGL((direct_f32_kernel<8, LIN, 1>), grid, dim3(256), 0, st, a);
+  else if (nr <= 16) hipLaunchKernelGGL((direct_f32_kernel<16, LIN, 1>), grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((direct_f32_kernel<32, LIN, 1>), grid, dim3(256), 0, st, a);
 }
 
 template <int OP, int DG>
