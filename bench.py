@@ -760,6 +760,8 @@ def learned_bench(A, synth, torch, args):
             "analytic_mean_ratio": round(float(np.mean(ar)), 4), "analytic_max_ratio": round(float(np.max(ar)), 4),
             "plan_seconds_measured": round(sum(r["plan_s_measured"] for r in rows), 2),
             "plan_seconds_learned": round(sum(r["plan_s_learned"] for r in rows), 3),
+            "plan_time_ratio_measured_over_learned": round(
+                sum(r["plan_s_measured"] for r in rows) / max(1e-9, sum(r["plan_s_learned"] for r in rows)), 1),
             "rows": rows}
 
 
