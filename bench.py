@@ -95,6 +95,9 @@ def parse():
     ap.add_argument("--only-batched", action="store_true", help="the batched remap leg only")
     ap.add_argument("--cap-bytes", type=int, default=128, help="greedy grouping cap of the program leg's catalogue")
     ap.add_argument("--only-medical", action="store_true", help="the Medical-shaped stencil leg only")
+    ap.add_argument("--only-medical-narrow", action="store_true",
+                    help="the Medical-shaped leg with 1- and 2-byte image fields only")
+    ap.add_argument("--skip-medical-narrow", action="store_true")
     ap.add_argument("--only-flow", action="store_true", help="the branching-program leg only")
     ap.add_argument("--only-hetero", action="store_true", help="the GPU + host planning leg only")
     ap.add_argument("--only-kmeans", action="store_true", help="the K-Means-shaped leg only (for profiling)")
@@ -375,11 +378,12 @@ def kmeans_bench(A, synth, torch, timer, log2n=23):
     return res
 
 
-def medical_bench(A, synth, torch, timer, side=256):
-    """The Medical-shaped program on a side^3 image of 9 f32 fields: two
-    7-point stencils and two direct loops, planned with measured costs and
-    compared with all-AoS and all-SoA; per-section times and GB/s."""
-    spec = synth.medical_struct(side)
+def medical_bench(A, synth, torch, timer, side=256, narrow=False):
+    """The Medical-shaped program on a side^3 image of 9 f32 fields (narrow:
+    V1-V3 U16, U1-U3 F32, S U8, T I16, interpT F32): two 7-point stencils and
+    two direct loops, planned with measured costs and compared with all-AoS
+    and all-SoA; per-section times and GB/s."""
+    spec = synth.medical_narrow_struct(side) if narrow else synth.medical_struct(side)
     n = spec.n
     st = A.Struct.from_spec(spec)
     grid = (side, side, side)
@@ -396,7 +400,8 @@ def medical_bench(A, synth, torch, timer, side=256):
     t0 = time.perf_counter()
     plan = A.Plan.create(ctx, prog, A.plan_opts(cost=A.COST_MEASURED, catalogue=A.CAT_FULL, cap_bytes=64, reps=3))
     plan_s = time.perf_counter() - t0
-    res = {"workload": f"{side}^3 image, 9 f32 fields (36 B); 7-point stencil U->V1, direct V1,S,T->interpT, "
+    fields = ("V1-V3 u16, U1-U3 f32, S u8, T i16, interpT f32 (18 B)" if narrow else "9 f32 fields (36 B)")
+    res = {"workload": f"{side}^3 image, {fields}; 7-point stencil U->V1, direct V1,S,T->interpT, "
                        f"7-point stencil V->U1, direct U,interpT->V2,V3",
            "candidates": plan.n_candidates, "plan_seconds": round(plan_s, 2)}
     for name, pl in (("adha", plan), ("all_aos", A.Plan.uniform(prog, aos_l)), ("all_soa", A.Plan.uniform(prog, soa_l))):
@@ -788,6 +793,9 @@ def main():
     if args.only_medical:
         print(json.dumps({"medical": medical_bench(A, synth, torch, timer)}), flush=True)
         return
+    if args.only_medical_narrow:
+        print(json.dumps({"medical_narrow": medical_bench(A, synth, torch, timer, narrow=True)}), flush=True)
+        return
     if args.only_batched:
         print(json.dumps({"batched": batched_bench(A, synth, torch, timer)}), flush=True)
         return
@@ -926,6 +934,12 @@ def main():
                 line["medical"] = medical_bench(A, synth, torch, timer)
             except Exception as e:
                 line["medical"] = {"error": repr(e)}
+            torch.cuda.empty_cache()
+        if not args.skip_medical_narrow:
+            try:
+                line["medical_narrow"] = medical_bench(A, synth, torch, timer, narrow=True)
+            except Exception as e:
+                line["medical_narrow"] = {"error": repr(e)}
             torch.cuda.empty_cache()
         if not args.skip_flow:
             try:

@@ -86,6 +86,8 @@ __device__ __forceinline__ uint64_t load_any(const uint8_t *buf, const SField &F
     const uint32_t *q = reinterpret_cast<const uint32_t *>(p);
     return F.e == 8 ? ((uint64_t)q[0] | ((uint64_t)q[1] << 32)) : q[0];
   }
+  // a 2-byte field at even addresses (base is a multiple of 256): one load
+  if (F.e == 2 && ((F.TS | F.pT) & 1u) == 0) return *reinterpret_cast<const uint16_t *>(p);
   uint64_t v = 0;
   for (uint32_t b = 0; b < F.e; ++b) v |= (uint64_t)p[b] << (8 * b);
   return v;
@@ -218,6 +220,8 @@ __device__ __forceinline__ void store_acc(uint8_t *buf, const SField &W, uint64_
     store_bytes(at, __float_as_uint(a.f), 4);
   } else if (W.dt == ADHA_F64) {
     store_bytes(at, (uint64_t)__double_as_longlong(a.d), 8);
+  } else if (W.e == 2 && ((W.TS | W.pT) & 1u) == 0) {
+    *reinterpret_cast<uint16_t *>(at) = (uint16_t)a.u;  // a 2-byte field at an even address
   } else {
     store_bytes(at, a.u, W.e);
   }
@@ -498,7 +502,7 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) {
 // The load phase has no branches: a neighbour past the degree or off the
 // grid loads the record's own fields and is not selected, and the grid test
 // uses no short-circuit operators, so all loads of a batch stay in flight.
-template <int MAXR, bool W8, bool LIN, bool F32, bool EXACT, int DEG = 0, bool ROW = false>
+template <int MAXR, bool W8, bool LIN, bool F32, bool EXACT, int DEG = 0, bool ROW = false, bool SUB = false>
 __global__ __launch_bounds__(256) void stencil_kernel(const SectionArgs a) {
   const uint64_t i = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
   if (i >= (uint64_t)a.n) return;
@@ -527,7 +531,7 @@ __global__ __launch_bounds__(256) void stencil_kernel(const SectionArgs a) {
       own[q] = q < (int)nr ? (uint32_t)a.rd[q].base + a.rd[q].pT + (uint32_t)i * a.rd[q].TS : 0u;
   }
   for (int j0 = 0; j0 < deg; j0 += NB) {
-    Words<MAXR, W8> w[NB];
+    Words<MAXR, W8, SUB> w[NB];
     bool ok[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -761,6 +765,13 @@ static void launch_sub_maxr(uint32_t nr, dim3 grid, const SectionArgs &a, hipStr
 }
 
 static void launch_sub(const SectionDesc &sec, uint32_t nr, dim3 grid, const SectionArgs &a, hipStream_t st) {
+  if (sec.stencil) {
+    // the stencil kernel's generic form, every field through load_any
+    if (nr <= 4) hipLaunchKernelGGL((stencil_kernel<4, true, false, false, false, 0, false, true>), grid, dim3(256), 0, st, a);
+    else if (nr <= 8) hipLaunchKernelGGL((stencil_kernel<8, true, false, false, false, 0, false, true>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((stencil_kernel<32, true, false, false, false, 0, false, true>), grid, dim3(256), 0, st, a);
+    return;
+  }
   switch (sec.op) {
     case ADHA_OP_GEN:
       if (sec.degree == 0) launch_sub_maxr<ADHA_OP_GEN, 0>(nr, grid, a, st);
@@ -1546,11 +1557,15 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
   }
   const dim3 grid((uint32_t)((n + 255) / 256));
   const uint32_t nr = a.n_read;
-  // a field narrower than 4 bytes or not 4-byte aligned: the byte-wise form
-  bool sub = false;
-  for (uint32_t q = 0; q < nr; ++q) sub |= !a.rd[q].al;
-  for (uint32_t k = 0; k < a.n_write; ++k) sub |= !a.wr[k].al;
-  if (sub) {
+  // a read field narrower than 4 bytes or not 4-byte aligned: the byte-wise
+  // form.  Narrow or unaligned write fields alone keep the dword loads: the
+  // generic, span and generic-fold stencil kernels store through store_acc,
+  // which writes such fields byte by byte; the straight-line forms below
+  // (dword stores) are then left out.
+  bool sub_rd = false, sub_wr = false;
+  for (uint32_t q = 0; q < nr; ++q) sub_rd |= !a.rd[q].al;
+  for (uint32_t k = 0; k < a.n_write; ++k) sub_wr |= !a.wr[k].al;
+  if (sub_rd) {
     launch_sub(sec, nr, grid, a, stream);
     ADHA_HIP(hipGetLastError());
     return ADHA_OK;
@@ -1562,6 +1577,7 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
     all_t1 &= a.rd[q].logT == 0;
   }
   for (uint32_t k = 0; k < a.n_write; ++k) all_f32 &= a.wr[k].dt == ADHA_F32;
+  all_f32 &= !sub_wr;
   // direct GEN / SUM over F32, F64, I32 and U32 fields (not all F32): the
   // fold specialised on the write types, terms converted by selects
   bool wide_types = true, w8 = false;
@@ -1575,6 +1591,7 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
     const uint32_t dt = a.wr[k].dt;
     wide_types &= dt == ADHA_F32 || dt == ADHA_F64 || dt == ADHA_I32 || dt == ADHA_U32;
   }
+  wide_types &= !sub_wr;
   if ((sec.op == ADHA_OP_GEN || sec.op == ADHA_OP_SUM) && sec.degree == 0 && !sec.stencil && !all_f32 &&
       wide_types && nr <= 16 && !ctx->no_span) {
     const int wt0 = wclass(a.wr[0].dt), wt1 = a.n_write > 1 ? wclass(a.wr[1].dt) : 3;
@@ -1602,6 +1619,7 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
           f32 &= a.rd[q].dt == ADHA_F32;
         }
         for (uint32_t k = 0; k < a.n_write; ++k) f32 &= a.wr[k].dt == ADHA_F32;
+        f32 &= !sub_wr;  // the F32 forms store dwords
         if (f32) {
           if (lin) launch_stencil<false, true, true>(nr, grid, a, stream);
           else launch_stencil<false, false, true>(nr, grid, a, stream);
