@@ -134,8 +134,10 @@ adha_status adha_ctx_cu_count(const adha_ctx *ctx, int32_t *out);
 typedef enum {
   /* 1 (default): a gather whose read fields share one interleaved group
    * fetches each neighbour's span with wide loads, and direct sections over
-   * mixed F32 / F64 / I32 / U32 fields take the type-specialised kernel;
-   * 0: one load per field and the generic kernels (same results). */
+   * mixed F32 / F64 / I32 / U32 fields, direct sections with a narrow or
+   * unaligned field and stencils with a narrow or unaligned read field (up
+   * to 8 reads) take the kernels specialised on the write types; 0: one
+   * load per field and the generic kernels (same results). */
   ADHA_OPT_SPAN_GATHER = 1,
   /* reductions: workgroups per compute unit in the first pass (1..32,
    * default 8) */

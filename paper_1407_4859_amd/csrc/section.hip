@@ -77,20 +77,27 @@ __device__ __forceinline__ uint64_t faddr(const SField &F, uint64_t r) {
   return F.base + (r >> F.logT) * F.TS + F.pT + (r & ((1ull << F.logT) - 1)) * F.e;
 }
 
-// A field of any width at any address: whole dwords when every address of
-// the field is a multiple of 4, else byte by byte (a 1- or 2-byte field, or
-// a wider one placed after narrow fields in an interleaved group).
+// A field of any width at any address (a 1- or 2-byte field, or a wider one
+// placed after narrow fields in an interleaved group), zero-extended: the
+// one to three dwords that hold its bytes are loaded and funnel-shifted.
+// A dword the field does not reach is replaced by the one before it, so no
+// branch depends on the field's width or offset and every load is a dword
+// holding a byte of the field.  Such a dword lies inside the field's group
+// region, whose base and size are multiples of 256, so it is inside the
+// buffer.  Bytes of other fields in those dwords are discarded.  (Loading
+// only the dwords a field can reach, by a branch on the field, measured
+// slower: the branches split the batches of loads.)
 __device__ __forceinline__ uint64_t load_any(const uint8_t *buf, const SField &F, uint64_t r) {
-  const uint8_t *p = buf + faddr(F, r);
-  if (F.al) {
-    const uint32_t *q = reinterpret_cast<const uint32_t *>(p);
-    return F.e == 8 ? ((uint64_t)q[0] | ((uint64_t)q[1] << 32)) : q[0];
-  }
-  // a 2-byte field at even addresses (base is a multiple of 256): one load
-  if (F.e == 2 && ((F.TS | F.pT) & 1u) == 0) return *reinterpret_cast<const uint16_t *>(p);
-  uint64_t v = 0;
-  for (uint32_t b = 0; b < F.e; ++b) v |= (uint64_t)p[b] << (8 * b);
-  return v;
+  const uint64_t at = faddr(F, r);
+  const uint32_t *q = reinterpret_cast<const uint32_t *>(buf + (at & ~3ull));
+  const uint32_t o = (uint32_t)at & 3u, end = o + F.e;
+  const uint32_t w0 = q[0];
+  const uint32_t w1 = q[end > 4 ? 1 : 0];
+  const uint32_t w2 = q[end > 8 ? 2 : (end > 4 ? 1 : 0)];
+  const uint32_t lo = __builtin_amdgcn_alignbit(w1, w0, 8 * o);  // bytes o..o+3 of w1:w0
+  const uint32_t hi = __builtin_amdgcn_alignbit(w2, w1, 8 * o);
+  const uint32_t mask = F.e >= 4 ? ~0u : (1u << (8 * F.e)) - 1u;
+  return (uint64_t)(lo & mask) | ((uint64_t)(F.e == 8 ? hi : 0u) << 32);
 }
 
 // The raw words of up to N terms.  Loads only fill registers; the terms are
@@ -227,6 +234,77 @@ __device__ __forceinline__ void store_acc(uint8_t *buf, const SField &W, uint64_
   }
 }
 
+// The GEN / SUM fold specialised on the write types (WT0, WT1: 0 an F32
+// write, 1 F64, 2 an integer fold; WT1 = 3: one write).  Every term is
+// converted by computing each candidate conversion and keeping the one its
+// type names, so no branch depends on a field's type; the conversions are
+// those of to_f32, to_f64 and bits32 (nearest even).  lo, hi: the term's
+// element bytes, zero-extended (hi only for an 8-byte term, W8).  NAR: terms
+// may also be U16, I16 or U8, and write fields narrow or unaligned.
+template <int WT0, int WT1, bool W8, bool NAR>
+struct MixFold {
+  float f0 = 0.0f, f1 = 0.0f;
+  double d0 = 0.0, d1 = 0.0;
+  uint32_t u0 = 0u, u1 = 0u;
+  // take = false leaves the accumulators as they are
+  __device__ __forceinline__ void add(uint32_t dt, uint32_t lo, uint32_t hi, bool take) {
+    const double dbits = __longlong_as_double((long long)(((uint64_t)(W8 ? hi : 0u) << 32) | lo));
+    const int32_t s16 = (int32_t)(int16_t)(uint16_t)lo;
+    if constexpr (WT0 == 0 || WT1 == 0) {
+      // I32, U16 and U8 (zero-extended) convert as the int32 lo
+      const float c_f = __uint_as_float(lo), c_i = __int2float_rn((int32_t)lo), c_u = __uint2float_rn(lo);
+      const float c_d = W8 ? __double2float_rn(dbits) : 0.0f;
+      float v = dt == ADHA_F32 ? c_f : dt == ADHA_U32 ? c_u : dt == ADHA_F64 ? c_d : c_i;
+      if constexpr (NAR) v = dt == ADHA_I16 ? __int2float_rn(s16) : v;
+      if constexpr (WT0 == 0) f0 = take ? __fadd_rn(f0, v) : f0;
+      if constexpr (WT1 == 0) f1 = take ? __fadd_rn(__fmul_rn(f1, 0.5f), v) : f1;
+    }
+    if constexpr (WT0 == 1 || WT1 == 1) {
+      const double c_f = (double)__uint_as_float(lo), c_i = (double)(int32_t)lo, c_u = (double)lo;
+      double v = dt == ADHA_F32 ? c_f : dt == ADHA_U32 ? c_u : dt == ADHA_F64 ? dbits : c_i;
+      if constexpr (NAR) v = dt == ADHA_I16 ? (double)s16 : v;
+      if constexpr (WT0 == 1) d0 = take ? __dadd_rn(d0, v) : d0;
+      if constexpr (WT1 == 1) d1 = take ? __dadd_rn(__dmul_rn(d1, 0.5), v) : d1;
+    }
+    if constexpr (WT0 == 2 || WT1 == 2) {
+      // an F32, I32, U32, U16 or U8 term is its own (zero-extended) bits
+      uint32_t v = dt == ADHA_F64 ? lo ^ hi : lo;
+      if constexpr (NAR) v = dt == ADHA_I16 ? (uint32_t)s16 : v;
+      if constexpr (WT0 == 2) u0 = take ? u0 + v : u0;
+      if constexpr (WT1 == 2) u1 = take ? (u1 ^ v) * 16777619u : u1;
+    }
+  }
+  template <int WT>
+  __device__ __forceinline__ static void put1(uint8_t *buf, const SField &W, uint64_t i, float f, double d,
+                                              uint32_t u) {
+    uint8_t *at = buf + faddr(W, i);
+    uint32_t *p = reinterpret_cast<uint32_t *>(at);
+    const uint64_t db = (uint64_t)__double_as_longlong(d);
+    if (!NAR || W.al) {
+      if constexpr (WT == 0) {
+        p[0] = __float_as_uint(f);
+      } else if constexpr (WT == 1) {
+        p[0] = (uint32_t)db;
+        p[1] = (uint32_t)(db >> 32);
+      } else {
+        p[0] = u;
+      }
+    } else if constexpr (WT == 0) {
+      store_bytes(at, __float_as_uint(f), 4);
+    } else if constexpr (WT == 1) {
+      store_bytes(at, db, 8);
+    } else if (W.e == 2 && ((W.TS | W.pT) & 1u) == 0) {
+      *reinterpret_cast<uint16_t *>(at) = (uint16_t)u;  // a 2-byte field at an even address
+    } else {
+      store_bytes(at, u, W.e);  // an integer field keeps the low bytes of the fold
+    }
+  }
+  __device__ __forceinline__ void put(uint8_t *buf, const SectionArgs &a, uint64_t i) const {
+    put1<WT0>(buf, a.wr[0], i, f0, d0, u0);
+    if constexpr (WT1 != 3) put1<WT1>(buf, a.wr[1], i, f1, d1, u1);
+  }
+};
+
 // DG = 0: direct section; otherwise a gather of at most DG neighbours.
 // MAXR: bound on the number of read fields (loads are unrolled to it).
 // W8: some read field is 8 bytes wide.
@@ -328,21 +406,20 @@ __global__ __launch_bounds__(256) void section_kernel(const SectionArgs a) {
 // and the layout fits in 4 GiB, so a field's offset is base + p + r*S in 32
 // bits.
 // Direct GEN / SUM sections over F32, F64, I32 and U32 fields at 4-byte
-// aligned addresses, not all F32.  The generic kernel's fold branches on
-// the write type and the term type of every term, tens of scalar
-// instructions per term.  Here the fold is specialised on the write types
-// (WT0, WT1: 0 an F32 write, 1 F64, 2 an integer fold; WT1 = 3: one write)
-// and every term is converted by computing each candidate conversion and
-// keeping the one its type names, so no branch depends on a field's type.
-// The conversions are those of the generic kernel (nearest even).
+// aligned addresses, not all F32 (NAR = false), or with some field narrow
+// or unaligned (NAR = true: every field through load_any, stores that fit
+// each write field).  The generic kernel's fold branches on the write type
+// and the term type of every term, tens of scalar instructions per term;
+// here the fold is MixFold, specialised on the write types and converting
+// terms by selects.
 // RPT records per thread, one per 256-record chunk of the workgroup's RPT
 // chunks, all their loads issued before any fold: a section with few fields
 // streams few bytes per record, and one record per thread leaves too few
 // bytes in flight.
-template <int MAXR, bool W8, int WT0, int WT1, int RPT>
+template <int MAXR, bool W8, int WT0, int WT1, int RPT, bool NAR = false>
 __global__ __launch_bounds__(256) void direct_mixed_kernel(const SectionArgs a) {
   const uint32_t nr = a.n_read;
-  Words<MAXR, W8> w[RPT];
+  Words<MAXR, W8, NAR> w[RPT];
   uint64_t rec[RPT];
   bool live[RPT];
 #pragma unroll
@@ -357,71 +434,32 @@ __global__ __launch_bounds__(256) void direct_mixed_kernel(const SectionArgs a) 
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     if (!live[r]) continue;
-    float f0 = 0.0f, f1 = 0.0f;
-    double d0 = 0.0, d1 = 0.0;
-    uint32_t u0 = 0u, u1 = 0u;
+    MixFold<WT0, WT1, W8 || NAR, NAR> m;
 #pragma unroll
-    for (int q = 0; q < MAXR; ++q) {
-      if (q >= (int)nr) continue;
-      const uint32_t dt = a.rd[q].dt;
-      const uint32_t lo = w[r].lo[q];
-      const uint32_t hi = W8 ? w[r].hi[q] : 0u;
-      const double dbits = __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-      if constexpr (WT0 == 0 || WT1 == 0) {
-        const float c_f = __uint_as_float(lo), c_i = __int2float_rn((int32_t)lo), c_u = __uint2float_rn(lo);
-        const float c_d = W8 ? __double2float_rn(dbits) : 0.0f;
-        const float v = dt == ADHA_F32 ? c_f : dt == ADHA_I32 ? c_i : dt == ADHA_U32 ? c_u : c_d;
-        if constexpr (WT0 == 0) f0 = __fadd_rn(f0, v);
-        if constexpr (WT1 == 0) f1 = __fadd_rn(__fmul_rn(f1, 0.5f), v);
-      }
-      if constexpr (WT0 == 1 || WT1 == 1) {
-        const double c_f = (double)__uint_as_float(lo), c_i = (double)(int32_t)lo, c_u = (double)lo;
-        const double v = dt == ADHA_F32 ? c_f : dt == ADHA_I32 ? c_i : dt == ADHA_U32 ? c_u : dbits;
-        if constexpr (WT0 == 1) d0 = __dadd_rn(d0, v);
-        if constexpr (WT1 == 1) d1 = __dadd_rn(__dmul_rn(d1, 0.5), v);
-      }
-      if constexpr (WT0 == 2 || WT1 == 2) {
-        const uint32_t v = dt == ADHA_F64 ? lo ^ hi : lo;  // an F32, I32 or U32 term is its own 32 bits
-        if constexpr (WT0 == 2) u0 = u0 + v;
-        if constexpr (WT1 == 2) u1 = (u1 ^ v) * 16777619u;
-      }
-    }
-    const uint64_t i = rec[r];
-    auto put = [&](const SField &W, int wt, float f, double d, uint32_t u) {
-      uint32_t *p = reinterpret_cast<uint32_t *>(a.buf + faddr(W, i));
-      if (wt == 0) {
-        p[0] = __float_as_uint(f);
-      } else if (wt == 1) {
-        const uint64_t b = (uint64_t)__double_as_longlong(d);
-        p[0] = (uint32_t)b;
-        p[1] = (uint32_t)(b >> 32);
-      } else {
-        p[0] = u;
-      }
-    };
-    put(a.wr[0], WT0, f0, d0, u0);
-    if constexpr (WT1 != 3) put(a.wr[1], WT1, f1, d1, u1);
+    for (int q = 0; q < MAXR; ++q)
+      if (q < (int)nr) m.add(a.rd[q].dt, w[r].lo[q], W8 || NAR ? w[r].hi[q] : 0u, true);
+    m.put(a.buf, a, rec[r]);
   }
 }
 
-template <int MAXR, bool W8, int WT0>
+template <int MAXR, bool W8, int WT0, bool NAR>
 static void launch_direct_mixed_w1(int wt1, const SectionArgs &a, hipStream_t st) {
   // 4 records per thread for up to 4 reads, else 1
   constexpr int RPT = MAXR <= 4 ? 4 : 1;
   const dim3 grid((uint32_t)(((uint64_t)a.n + 256ull * RPT - 1) / (256ull * RPT)));
   switch (wt1) {
-    case 0: hipLaunchKernelGGL((direct_mixed_kernel<MAXR, W8, WT0, 0, RPT>), grid, dim3(256), 0, st, a); break;
-    case 1: hipLaunchKernelGGL((direct_mixed_kernel<MAXR, W8, WT0, 1, RPT>), grid, dim3(256), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((direct_mixed_kernel<MAXR, W8, WT0, 2, RPT>), grid, dim3(256), 0, st, a); break;
-    default: hipLaunchKernelGGL((direct_mixed_kernel<MAXR, W8, WT0, 3, RPT>), grid, dim3(256), 0, st, a); break;
+    case 0: hipLaunchKernelGGL((direct_mixed_kernel<MAXR, W8, WT0, 0, RPT, NAR>), grid, dim3(256), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((direct_mixed_kernel<MAXR, W8, WT0, 1, RPT, NAR>), grid, dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((direct_mixed_kernel<MAXR, W8, WT0, 2, RPT, NAR>), grid, dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((direct_mixed_kernel<MAXR, W8, WT0, 3, RPT, NAR>), grid, dim3(256), 0, st, a); break;
   }
 }
 
-template <int MAXR, bool W8>
+template <int MAXR, bool W8, bool NAR = false>
 static void launch_direct_mixed_w0(int wt0, int wt1, const SectionArgs &a, hipStream_t st) {
-  if (wt0 == 0) launch_direct_mixed_w1<MAXR, W8, 0>(wt1, a, st);
-  else if (wt0 == 1) launch_direct_mixed_w1<MAXR, W8, 1>(wt1, a, st);
-  else launch_direct_mixed_w1<MAXR, W8, 2>(wt1, a, st);
+  if (wt0 == 0) launch_direct_mixed_w1<MAXR, W8, 0, NAR>(wt1, a, st);
+  else if (wt0 == 1) launch_direct_mixed_w1<MAXR, W8, 1, NAR>(wt1, a, st);
+  else launch_direct_mixed_w1<MAXR, W8, 2, NAR>(wt1, a, st);
 }
 
 // RPT records per thread, one per 256-record chunk of the workgroup's RPT
@@ -502,13 +540,16 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) {
 // The load phase has no branches: a neighbour past the degree or off the
 // grid loads the record's own fields and is not selected, and the grid test
 // uses no short-circuit operators, so all loads of a batch stay in flight.
-template <int MAXR, bool W8, bool LIN, bool F32, bool EXACT, int DEG = 0, bool ROW = false, bool SUB = false>
+template <int MAXR, bool W8, bool LIN, bool F32, bool EXACT, int DEG = 0, bool ROW = false, bool SUB = false,
+          int WT0 = -1, int WT1 = -1>
 __global__ __launch_bounds__(256) void stencil_kernel(const SectionArgs a) {
   const uint64_t i = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
   if (i >= (uint64_t)a.n) return;
   const uint32_t nr = EXACT ? (uint32_t)MAXR : a.n_read, nw = a.n_write;
   Acc acc[2];
   acc[0] = acc[1] = Acc{0.0f, 0.0, 0u};
+  // WT0 >= 0: the fold specialised on the write types (fields of any type)
+  MixFold<WT0 < 0 ? 0 : WT0, WT1 < 0 ? 3 : WT1, W8 || SUB, SUB> m;
   constexpr int NB = DEG > 0 ? DEG : (MAXR >= 32 ? 1 : (MAXR <= 4 ? 8 : 32 / MAXR));
   static_assert(DEG > 0 ? DEG <= ADHA_MAX_DEGREE : ADHA_MAX_DEGREE % NB == 0,
                 "batches must tile the offset tables");
@@ -572,6 +613,12 @@ __global__ __launch_bounds__(256) void stencil_kernel(const SectionArgs a) {
               acc[1].f = ok[b] ? s1 : acc[1].f;
             }
           }
+    } else if constexpr (WT0 >= 0) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int q = 0; q < MAXR; ++q)
+          if (q < (int)nr) m.add(a.rd[q].dt, w[b].lo[q], W8 || SUB ? w[b].hi[q] : 0u, ok[b]);
     } else {
 #pragma unroll
       for (int b = 0; b < NB; ++b)
@@ -589,6 +636,8 @@ __global__ __launch_bounds__(256) void stencil_kernel(const SectionArgs a) {
   if constexpr (F32) {
     *reinterpret_cast<uint32_t *>(a.buf + faddr(a.wr[0], i)) = __float_as_uint(acc[0].f);
     if (nw > 1) *reinterpret_cast<uint32_t *>(a.buf + faddr(a.wr[1], i)) = __float_as_uint(acc[1].f);
+  } else if constexpr (WT0 >= 0) {
+    m.put(a.buf, a, i);
   } else {
     store_acc(a.buf, a.wr[0], i, acc[0]);
     if (nw > 1) store_acc(a.buf, a.wr[1], i, acc[1]);
@@ -764,12 +813,30 @@ static void launch_sub_maxr(uint32_t nr, dim3 grid, const SectionArgs &a, hipStr
   else hipLaunchKernelGGL((section_kernel<OP, DG, 32, true, true>), grid, dim3(256), 0, st, a);
 }
 
+// Stencils that are not all F32, up to 8 read fields: every field through
+// load_any (any type, width and alignment) and MixFold for the write types.
+template <int MAXR, int WT0>
+static void launch_stencil_mixed_w1(int wt1, dim3 grid, const SectionArgs &a, hipStream_t st) {
+  switch (wt1) {
+    case 0: hipLaunchKernelGGL((stencil_kernel<MAXR, true, false, false, false, 0, false, true, WT0, 0>), grid, dim3(256), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((stencil_kernel<MAXR, true, false, false, false, 0, false, true, WT0, 1>), grid, dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((stencil_kernel<MAXR, true, false, false, false, 0, false, true, WT0, 2>), grid, dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((stencil_kernel<MAXR, true, false, false, false, 0, false, true, WT0, 3>), grid, dim3(256), 0, st, a); break;
+  }
+}
+
+template <int MAXR>
+static void launch_stencil_mixed(int wt0, int wt1, dim3 grid, const SectionArgs &a, hipStream_t st) {
+  if (wt0 == 0) launch_stencil_mixed_w1<MAXR, 0>(wt1, grid, a, st);
+  else if (wt0 == 1) launch_stencil_mixed_w1<MAXR, 1>(wt1, grid, a, st);
+  else launch_stencil_mixed_w1<MAXR, 2>(wt1, grid, a, st);
+}
+
 static void launch_sub(const SectionDesc &sec, uint32_t nr, dim3 grid, const SectionArgs &a, hipStream_t st) {
   if (sec.stencil) {
-    // the stencil kernel's generic form, every field through load_any
-    if (nr <= 4) hipLaunchKernelGGL((stencil_kernel<4, true, false, false, false, 0, false, true>), grid, dim3(256), 0, st, a);
-    else if (nr <= 8) hipLaunchKernelGGL((stencil_kernel<8, true, false, false, false, 0, false, true>), grid, dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((stencil_kernel<32, true, false, false, false, 0, false, true>), grid, dim3(256), 0, st, a);
+    // more than 8 read fields: the stencil kernel's generic fold, every
+    // field through load_any
+    hipLaunchKernelGGL((stencil_kernel<32, true, false, false, false, 0, false, true>), grid, dim3(256), 0, st, a);
     return;
   }
   switch (sec.op) {
@@ -1565,6 +1632,26 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
   bool sub_rd = false, sub_wr = false;
   for (uint32_t q = 0; q < nr; ++q) sub_rd |= !a.rd[q].al;
   for (uint32_t k = 0; k < a.n_write; ++k) sub_wr |= !a.wr[k].al;
+  auto wclass = [](uint32_t dt) { return dt == ADHA_F32 ? 0 : dt == ADHA_F64 ? 1 : 2; };
+  const int wt0 = wclass(a.wr[0].dt), wt1 = a.n_write > 1 ? wclass(a.wr[1].dt) : 3;
+  // a stencil with a narrow or unaligned read field, up to 8 reads: the fold
+  // specialised on the write types.  (With aligned reads the linear-offset
+  // forms below are faster, even with the generic fold.)
+  if (sec.stencil && nr <= 8 && sub_rd && !ctx->no_span) {
+    if (nr <= 4) launch_stencil_mixed<4>(wt0, wt1, grid, a, stream);
+    else launch_stencil_mixed<8>(wt0, wt1, grid, a, stream);
+    ADHA_HIP(hipGetLastError());
+    return ADHA_OK;
+  }
+  // a direct GEN / SUM section with a narrow or unaligned field: the mixed
+  // direct kernel's narrow form
+  if ((sec.op == ADHA_OP_GEN || sec.op == ADHA_OP_SUM) && sec.degree == 0 && !sec.stencil && (sub_rd || sub_wr) &&
+      nr <= 16 && !ctx->no_span) {
+    if (nr <= 4) launch_direct_mixed_w0<4, true, true>(wt0, wt1, a, stream);
+    else launch_direct_mixed_w0<16, true, true>(wt0, wt1, a, stream);
+    ADHA_HIP(hipGetLastError());
+    return ADHA_OK;
+  }
   if (sub_rd) {
     launch_sub(sec, nr, grid, a, stream);
     ADHA_HIP(hipGetLastError());
@@ -1586,7 +1673,6 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
     wide_types &= dt == ADHA_F32 || dt == ADHA_F64 || dt == ADHA_I32 || dt == ADHA_U32;
     w8 |= a.rd[q].e == 8;
   }
-  auto wclass = [](uint32_t dt) { return dt == ADHA_F32 ? 0 : dt == ADHA_F64 ? 1 : 2; };
   for (uint32_t k = 0; k < a.n_write; ++k) {
     const uint32_t dt = a.wr[k].dt;
     wide_types &= dt == ADHA_F32 || dt == ADHA_F64 || dt == ADHA_I32 || dt == ADHA_U32;
@@ -1594,7 +1680,6 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
   wide_types &= !sub_wr;
   if ((sec.op == ADHA_OP_GEN || sec.op == ADHA_OP_SUM) && sec.degree == 0 && !sec.stencil && !all_f32 &&
       wide_types && nr <= 16 && !ctx->no_span) {
-    const int wt0 = wclass(a.wr[0].dt), wt1 = a.n_write > 1 ? wclass(a.wr[1].dt) : 3;
     if (nr <= 4) w8 ? launch_direct_mixed_w0<4, true>(wt0, wt1, a, stream) : launch_direct_mixed_w0<4, false>(wt0, wt1, a, stream);
     else w8 ? launch_direct_mixed_w0<16, true>(wt0, wt1, a, stream) : launch_direct_mixed_w0<16, false>(wt0, wt1, a, stream);
     ADHA_HIP(hipGetLastError());
