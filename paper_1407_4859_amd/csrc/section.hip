@@ -87,17 +87,20 @@ __device__ __forceinline__ uint64_t faddr(const SField &F, uint64_t r) {
 // buffer.  Bytes of other fields in those dwords are discarded.  (Loading
 // only the dwords a field can reach, by a branch on the field, measured
 // slower: the branches split the batches of loads.)
-__device__ __forceinline__ uint64_t load_any(const uint8_t *buf, const SField &F, uint64_t r) {
-  const uint64_t at = faddr(F, r);
+__device__ __forceinline__ uint64_t load_span(const uint8_t *buf, uint32_t e, uint64_t at) {
   const uint32_t *q = reinterpret_cast<const uint32_t *>(buf + (at & ~3ull));
-  const uint32_t o = (uint32_t)at & 3u, end = o + F.e;
+  const uint32_t o = (uint32_t)at & 3u, end = o + e;
   const uint32_t w0 = q[0];
   const uint32_t w1 = q[end > 4 ? 1 : 0];
   const uint32_t w2 = q[end > 8 ? 2 : (end > 4 ? 1 : 0)];
   const uint32_t lo = __builtin_amdgcn_alignbit(w1, w0, 8 * o);  // bytes o..o+3 of w1:w0
   const uint32_t hi = __builtin_amdgcn_alignbit(w2, w1, 8 * o);
-  const uint32_t mask = F.e >= 4 ? ~0u : (1u << (8 * F.e)) - 1u;
-  return (uint64_t)(lo & mask) | ((uint64_t)(F.e == 8 ? hi : 0u) << 32);
+  const uint32_t mask = e >= 4 ? ~0u : (1u << (8 * e)) - 1u;
+  return (uint64_t)(lo & mask) | ((uint64_t)(e == 8 ? hi : 0u) << 32);
+}
+
+__device__ __forceinline__ uint64_t load_any(const uint8_t *buf, const SField &F, uint64_t r) {
+  return load_span(buf, F.e, faddr(F, r));
 }
 
 // The raw words of up to N terms.  Loads only fill registers; the terms are
@@ -119,6 +122,12 @@ struct Words {
     const uint32_t *p = reinterpret_cast<const uint32_t *>(buf + faddr(F, r));
     lo[q] = p[0];
     if constexpr (W8) hi[q] = p[F.e >> 3];
+  }
+  // SUB: the field's element at byte offset off (any width, any alignment)
+  __device__ __forceinline__ void load_off(int q, const uint8_t *buf, const SField &F, uint32_t off) {
+    const uint64_t v = load_span(buf, F.e, off);
+    lo[q] = (uint32_t)v;
+    hi[q] = (uint32_t)(v >> 32);
   }
   __device__ __forceinline__ void load_at(int q, const uint8_t *at, const SField &F) {
     const uint32_t *p = reinterpret_cast<const uint32_t *>(at);
@@ -590,8 +599,11 @@ __global__ __launch_bounds__(256) void stencil_kernel(const SectionArgs a) {
         const int32_t d = ok[b] ? a.lin[jj] : 0;
 #pragma unroll
         for (int q = 0; q < MAXR; ++q)
-          if (q < (int)nr)
-            w[b].load_at(q, a.buf + (own[q] + (uint32_t)__mul24(d, (int32_t)a.rd[q].TS)), a.rd[q]);
+          if (q < (int)nr) {
+            const uint32_t off = own[q] + (uint32_t)__mul24(d, (int32_t)a.rd[q].TS);
+            if constexpr (SUB) w[b].load_off(q, a.buf, a.rd[q], off);
+            else w[b].load_at(q, a.buf + off, a.rd[q]);
+          }
       } else {
         const uint64_t rr = ok[b] ? (uint64_t)(ii + a.lin[jj]) : i;
 #pragma unroll
@@ -815,21 +827,35 @@ static void launch_sub_maxr(uint32_t nr, dim3 grid, const SectionArgs &a, hipStr
 
 // Stencils that are not all F32, up to 8 read fields: every field through
 // load_any (any type, width and alignment) and MixFold for the write types.
-template <int MAXR, int WT0>
+template <int MAXR, bool LIN, int WT0>
 static void launch_stencil_mixed_w1(int wt1, dim3 grid, const SectionArgs &a, hipStream_t st) {
   switch (wt1) {
-    case 0: hipLaunchKernelGGL((stencil_kernel<MAXR, true, false, false, false, 0, false, true, WT0, 0>), grid, dim3(256), 0, st, a); break;
-    case 1: hipLaunchKernelGGL((stencil_kernel<MAXR, true, false, false, false, 0, false, true, WT0, 1>), grid, dim3(256), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((stencil_kernel<MAXR, true, false, false, false, 0, false, true, WT0, 2>), grid, dim3(256), 0, st, a); break;
-    default: hipLaunchKernelGGL((stencil_kernel<MAXR, true, false, false, false, 0, false, true, WT0, 3>), grid, dim3(256), 0, st, a); break;
+    case 0: hipLaunchKernelGGL((stencil_kernel<MAXR, true, LIN, false, false, 0, false, true, WT0, 0>), grid, dim3(256), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((stencil_kernel<MAXR, true, LIN, false, false, 0, false, true, WT0, 1>), grid, dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((stencil_kernel<MAXR, true, LIN, false, false, 0, false, true, WT0, 2>), grid, dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((stencil_kernel<MAXR, true, LIN, false, false, 0, false, true, WT0, 3>), grid, dim3(256), 0, st, a); break;
   }
 }
 
-template <int MAXR>
+template <int MAXR, bool LIN>
 static void launch_stencil_mixed(int wt0, int wt1, dim3 grid, const SectionArgs &a, hipStream_t st) {
-  if (wt0 == 0) launch_stencil_mixed_w1<MAXR, 0>(wt1, grid, a, st);
-  else if (wt0 == 1) launch_stencil_mixed_w1<MAXR, 1>(wt1, grid, a, st);
-  else launch_stencil_mixed_w1<MAXR, 2>(wt1, grid, a, st);
+  if (wt0 == 0) launch_stencil_mixed_w1<MAXR, LIN, 0>(wt1, grid, a, st);
+  else if (wt0 == 1) launch_stencil_mixed_w1<MAXR, LIN, 1>(wt1, grid, a, st);
+  else launch_stencil_mixed_w1<MAXR, LIN, 2>(wt1, grid, a, st);
+}
+
+// The stencil kernel's linear-offset forms apply: the layout fits in 4 GiB,
+// every read field sits in a group with T = 1 (its offset is base + p +
+// r*S), and each neighbour's record step, its product with a field's record
+// bytes and that record size fit the 24-bit multiply-add and 32-bit sums.
+static bool stencil_linear(const SectionArgs &a, const LayoutDesc &l) {
+  bool lin = l.nbytes <= (1ull << 32);
+  int64_t max_lin = 0;
+  for (uint32_t j = 0; j < a.degree; ++j) max_lin = std::max<int64_t>(max_lin, std::abs((int64_t)a.lin[j]));
+  lin &= max_lin < (1 << 23);
+  for (uint32_t q = 0; q < a.n_read; ++q)
+    lin &= a.rd[q].logT == 0 && a.rd[q].TS < (1u << 23) && max_lin * (int64_t)a.rd[q].TS < (int64_t(1) << 31);
+  return lin;
 }
 
 static void launch_sub(const SectionDesc &sec, uint32_t nr, dim3 grid, const SectionArgs &a, hipStream_t st) {
@@ -1638,8 +1664,9 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
   // specialised on the write types.  (With aligned reads the linear-offset
   // forms below are faster, even with the generic fold.)
   if (sec.stencil && nr <= 8 && sub_rd && !ctx->no_span) {
-    if (nr <= 4) launch_stencil_mixed<4>(wt0, wt1, grid, a, stream);
-    else launch_stencil_mixed<8>(wt0, wt1, grid, a, stream);
+    const bool lin = stencil_linear(a, l);
+    if (nr <= 4) lin ? launch_stencil_mixed<4, true>(wt0, wt1, grid, a, stream) : launch_stencil_mixed<4, false>(wt0, wt1, grid, a, stream);
+    else lin ? launch_stencil_mixed<8, true>(wt0, wt1, grid, a, stream) : launch_stencil_mixed<8, false>(wt0, wt1, grid, a, stream);
     ADHA_HIP(hipGetLastError());
     return ADHA_OK;
   }
@@ -1694,13 +1721,10 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
   switch (sec.op) {
     case ADHA_OP_GEN: {
       if (sec.stencil) {
-        bool w8 = false, lin = l.nbytes <= (1ull << 32), f32 = true;
-        int64_t max_lin = 0;
-        for (uint32_t j = 0; j < sec.degree; ++j) max_lin = std::max<int64_t>(max_lin, std::abs((int64_t)a.lin[j]));
-        lin &= max_lin < (1 << 23);
+        bool w8 = false, f32 = true;
+        const bool lin = stencil_linear(a, l);
         for (uint32_t q = 0; q < nr; ++q) {
           w8 |= a.rd[q].e == 8;
-          lin &= a.rd[q].logT == 0 && a.rd[q].TS < (1u << 23) && max_lin * (int64_t)a.rd[q].TS < (int64_t(1) << 31);
           f32 &= a.rd[q].dt == ADHA_F32;
         }
         for (uint32_t k = 0; k < a.n_write; ++k) f32 &= a.wr[k].dt == ADHA_F32;
