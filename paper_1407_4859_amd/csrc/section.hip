@@ -87,13 +87,17 @@ __device__ __forceinline__ uint64_t faddr(const SField &F, uint64_t r) {
 // buffer.  Bytes of other fields in those dwords are discarded.  (Loading
 // only the dwords a field can reach, by a branch on the field, measured
 // slower: the branches split the batches of loads.)
+// W8 = false: no field of the section is 8 bytes wide, so the third dword
+// is never needed and not loaded.
+template <bool W8 = true>
 __device__ __forceinline__ uint64_t load_span(const uint8_t *buf, uint32_t e, uint64_t at) {
   const uint32_t *q = reinterpret_cast<const uint32_t *>(buf + (at & ~3ull));
   const uint32_t o = (uint32_t)at & 3u, end = o + e;
   const uint32_t w0 = q[0];
   const uint32_t w1 = q[end > 4 ? 1 : 0];
-  const uint32_t w2 = q[end > 8 ? 2 : (end > 4 ? 1 : 0)];
   const uint32_t lo = __builtin_amdgcn_alignbit(w1, w0, 8 * o);  // bytes o..o+3 of w1:w0
+  if constexpr (!W8) return e >= 4 ? lo : lo & ((1u << (8 * e)) - 1u);
+  const uint32_t w2 = q[end > 8 ? 2 : (end > 4 ? 1 : 0)];
   const uint32_t hi = __builtin_amdgcn_alignbit(w2, w1, 8 * o);
   const uint32_t mask = e >= 4 ? ~0u : (1u << (8 * e)) - 1u;
   return (uint64_t)(lo & mask) | ((uint64_t)(e == 8 ? hi : 0u) << 32);
@@ -125,7 +129,7 @@ struct Words {
   }
   // SUB: the field's element at byte offset off (any width, any alignment)
   __device__ __forceinline__ void load_off(int q, const uint8_t *buf, const SField &F, uint32_t off) {
-    const uint64_t v = load_span(buf, F.e, off);
+    const uint64_t v = load_span<W8>(buf, F.e, off);
     lo[q] = (uint32_t)v;
     hi[q] = (uint32_t)(v >> 32);
   }
@@ -558,7 +562,7 @@ __global__ __launch_bounds__(256) void stencil_kernel(const SectionArgs a) {
   Acc acc[2];
   acc[0] = acc[1] = Acc{0.0f, 0.0, 0u};
   // WT0 >= 0: the fold specialised on the write types (fields of any type)
-  MixFold<WT0 < 0 ? 0 : WT0, WT1 < 0 ? 3 : WT1, W8 || SUB, SUB> m;
+  MixFold<WT0 < 0 ? 0 : WT0, WT1 < 0 ? 3 : WT1, W8, SUB> m;
   constexpr int NB = DEG > 0 ? DEG : (MAXR >= 32 ? 1 : (MAXR <= 4 ? 8 : 32 / MAXR));
   static_assert(DEG > 0 ? DEG <= ADHA_MAX_DEGREE : ADHA_MAX_DEGREE % NB == 0,
                 "batches must tile the offset tables");
@@ -827,21 +831,23 @@ static void launch_sub_maxr(uint32_t nr, dim3 grid, const SectionArgs &a, hipStr
 
 // Stencils that are not all F32, up to 8 read fields: every field through
 // load_any (any type, width and alignment) and MixFold for the write types.
-template <int MAXR, bool LIN, int WT0>
+// W8: some read field is 8 bytes wide (the forms without linear offsets
+// always take W8).
+template <int MAXR, bool LIN, bool W8, int WT0>
 static void launch_stencil_mixed_w1(int wt1, dim3 grid, const SectionArgs &a, hipStream_t st) {
   switch (wt1) {
-    case 0: hipLaunchKernelGGL((stencil_kernel<MAXR, true, LIN, false, false, 0, false, true, WT0, 0>), grid, dim3(256), 0, st, a); break;
-    case 1: hipLaunchKernelGGL((stencil_kernel<MAXR, true, LIN, false, false, 0, false, true, WT0, 1>), grid, dim3(256), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((stencil_kernel<MAXR, true, LIN, false, false, 0, false, true, WT0, 2>), grid, dim3(256), 0, st, a); break;
-    default: hipLaunchKernelGGL((stencil_kernel<MAXR, true, LIN, false, false, 0, false, true, WT0, 3>), grid, dim3(256), 0, st, a); break;
+    case 0: hipLaunchKernelGGL((stencil_kernel<MAXR, W8, LIN, false, false, 0, false, true, WT0, 0>), grid, dim3(256), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((stencil_kernel<MAXR, W8, LIN, false, false, 0, false, true, WT0, 1>), grid, dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((stencil_kernel<MAXR, W8, LIN, false, false, 0, false, true, WT0, 2>), grid, dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((stencil_kernel<MAXR, W8, LIN, false, false, 0, false, true, WT0, 3>), grid, dim3(256), 0, st, a); break;
   }
 }
 
-template <int MAXR, bool LIN>
+template <int MAXR, bool LIN, bool W8>
 static void launch_stencil_mixed(int wt0, int wt1, dim3 grid, const SectionArgs &a, hipStream_t st) {
-  if (wt0 == 0) launch_stencil_mixed_w1<MAXR, LIN, 0>(wt1, grid, a, st);
-  else if (wt0 == 1) launch_stencil_mixed_w1<MAXR, LIN, 1>(wt1, grid, a, st);
-  else launch_stencil_mixed_w1<MAXR, LIN, 2>(wt1, grid, a, st);
+  if (wt0 == 0) launch_stencil_mixed_w1<MAXR, LIN, W8, 0>(wt1, grid, a, st);
+  else if (wt0 == 1) launch_stencil_mixed_w1<MAXR, LIN, W8, 1>(wt1, grid, a, st);
+  else launch_stencil_mixed_w1<MAXR, LIN, W8, 2>(wt1, grid, a, st);
 }
 
 // The stencil kernel's linear-offset forms apply: the layout fits in 4 GiB,
@@ -1665,8 +1671,17 @@ adha_status section_launch(Ctx *ctx, const SectionDesc &sec, const LayoutDesc &l
   // forms below are faster, even with the generic fold.)
   if (sec.stencil && nr <= 8 && sub_rd && !ctx->no_span) {
     const bool lin = stencil_linear(a, l);
-    if (nr <= 4) lin ? launch_stencil_mixed<4, true>(wt0, wt1, grid, a, stream) : launch_stencil_mixed<4, false>(wt0, wt1, grid, a, stream);
-    else lin ? launch_stencil_mixed<8, true>(wt0, wt1, grid, a, stream) : launch_stencil_mixed<8, false>(wt0, wt1, grid, a, stream);
+    bool w8 = false;
+    for (uint32_t q = 0; q < nr; ++q) w8 |= a.rd[q].e == 8;
+    if (nr <= 4) {
+      if (!lin) launch_stencil_mixed<4, false, true>(wt0, wt1, grid, a, stream);
+      else if (w8) launch_stencil_mixed<4, true, true>(wt0, wt1, grid, a, stream);
+      else launch_stencil_mixed<4, true, false>(wt0, wt1, grid, a, stream);
+    } else {
+      if (!lin) launch_stencil_mixed<8, false, true>(wt0, wt1, grid, a, stream);
+      else if (w8) launch_stencil_mixed<8, true, true>(wt0, wt1, grid, a, stream);
+      else launch_stencil_mixed<8, true, false>(wt0, wt1, grid, a, stream);
+    }
     ADHA_HIP(hipGetLastError());
     return ADHA_OK;
   }
