@@ -173,3 +173,37 @@ def test_reduction_type_rules(ctx):
     with pytest.raises(A.AdhaError) as e:
         A.section_run(ctx, sec, mirror(st, Ou), dev_bytes(oracle.pack(Ou, cols)))
     assert e.value.status == A.ERR_UNSUPPORTED
+
+
+# Stencils over every field type: F64 beside 1- and 2-byte reads (the forms
+# that load a third dword), narrow reads only (two dwords), 8 reads, and
+# F64, I32, F32 and I16 writes; SoA and AoS take linear offsets, the tiled
+# and T = 8 layouts do not.  Span option 0 runs the generic fold instead.
+MIXED_STENCILS = [([0, 1, 3, 4], [2, 9]), ([3, 7, 9], [8]), ([0, 1, 2, 3, 4, 5, 6, 7], [8, 9]),
+                  ([1, 3], [4, 6])]
+OFFS_WIDE = OFFS7 + [(1, 1, 0), (-1, 0, 1), (0, -1, -1)]
+
+
+@pytest.mark.parametrize("grid", [(9, 7, 5), (64, 3, 5)])
+@pytest.mark.parametrize("span", [1, 0])
+def test_mixed_narrow_stencils_match_oracle(ctx, grid, span):
+    n = grid[0] * grid[1] * grid[2]
+    spec = synth.mixed_narrow_struct(n)
+    st = A.Struct.from_spec(spec)
+    cols = synth.record_matrix(37, n, spec.dtypes, spec.elem_bytes)
+    ctx.set_option(A.OPT_SPAN_GATHER, span)
+    try:
+        for O in _layouts(n, spec.elem_bytes):
+            want = oracle.pack(O, cols)
+            dev = dev_bytes(want)
+            L = mirror(st, O)
+            for k, (rd, wr) in enumerate(MIXED_STENCILS):
+                offs = OFFS7 if k % 2 == 0 else OFFS_WIDE
+                idx = oracle.stencil_index(*grid, offs)
+                oracle.section(O, spec.dtypes, synth.OP_GEN, rd, wr, len(offs), idx, want)
+                say("narrow stencil", grid, span, O, rd, wr)
+                A.section_run(ctx, A.Section.stencil(st, rd, wr, grid, offs), L, dev)
+            ctx.check()
+            assert first_diff(host(dev, O.nbytes), want) is None, (grid, span, O, first_diff(host(dev, O.nbytes), want))
+    finally:
+        ctx.set_option(A.OPT_SPAN_GATHER, 1)
